@@ -1,0 +1,677 @@
+// IFEAST engine (Algorithm 2) on one GPU.
+//
+// Outer iteration (FP64): Rayleigh-Ritz on span(Q), residuals, membership.
+// Inner solve (complex T = float for the mixed precision path, double for the
+// FP64 path): for all nc shifted systems at once, restarted block GMRES from
+// the Ritz initial guess, i.e. on the right-hand side R (z_s - Lambda)^{-1},
+// accumulating the quadrature sum directly into the FP64 Q:
+//     Q = X rho_hat(Lambda) + sum_s wf_s V_s y_s      (wf = 2w, real part, on half contours)
+// Batched layout: basis block j of all shifts is one n x (nc*m0) complex
+// row-major array, so the shifted SpMM of a step is a single launch and each
+// shift's block is the column slice [s*m0, (s+1)*m0).
+#include "engine.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <random>
+
+namespace ifeast {
+
+DevBuf::DevBuf(size_t b) : bytes(b) {
+  if (b > 0) IF_HIP(hipMalloc(&p, b));
+}
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
+  if (this != &o) {
+    if (p) (void)hipFree(p);
+    p = o.p;
+    bytes = o.bytes;
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  return *this;
+}
+
+// ------------------------------------------------------------ quadrature
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton's method on P_n, with
+// the three-term recurrence for P_n and P_n' (ascending nodes).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wt) {
+  x.assign(n, 0.0);
+  wt.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double t = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = t;
+        p0 = 1.0;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (t * p1 - p0) / (t * t - 1.0);
+    const double w = 2.0 / ((1.0 - t * t) * dp * dp);
+    x[i] = -t;
+    x[n - 1 - i] = t;
+    wt[i] = wt[n - 1 - i] = w;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+Nodes make_nodes(const ifeast_contour& C) {
+  Nodes nd;
+  const double pi = 3.14159265358979323846;
+  const cd I(0.0, 1.0);
+  if (C.kind == IFEAST_CONTOUR_HALF) {
+    const double c = 0.5 * (C.emin + C.emax), r = 0.5 * (C.emax - C.emin);
+    nd.half = true;
+    if (C.rule == IFEAST_RULE_GAUSS_LEGENDRE) {
+      // theta = (pi/2)(1 - x): x in [-1, 1] onto the upper half circle
+      std::vector<double> x, g;
+      gauss_legendre(C.nc, x, g);
+      for (int k = 0; k < C.nc; ++k) {
+        const double th = 0.5 * pi * (1.0 - x[k]);
+        const cd e = std::exp(I * th);
+        nd.z.push_back(c + r * e);
+        nd.w.push_back(g[k] * r * e / 4.0);
+      }
+    } else {
+      // upper half of the 2nc-point trapezoidal rule
+      for (int k = 1; k <= C.nc; ++k) {
+        const double th = pi * (k - 0.5) / C.nc;
+        const cd e = std::exp(I * th);
+        nd.z.push_back(c + r * e);
+        nd.w.push_back(r * e / (2.0 * C.nc));
+      }
+    }
+  } else if (C.kind == IFEAST_CONTOUR_CIRCLE) {
+    nd.half = false;
+    const cd c(C.c_re, C.c_im);
+    for (int k = 1; k <= C.nc; ++k) {
+      const double th = 2.0 * pi * (k - 0.5) / C.nc;
+      const cd e = std::exp(I * th);
+      nd.z.push_back(c + C.r * e);
+      nd.w.push_back(C.r * e / (double)C.nc);
+    }
+  } else {
+    nd.half = C.half != 0;
+    for (int k = 0; k < C.nc; ++k) {
+      nd.z.push_back(cd(C.z[2 * k], C.z[2 * k + 1]));
+      nd.w.push_back(cd(C.w[2 * k], C.w[2 * k + 1]));
+    }
+  }
+  return nd;
+}
+
+void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n) {
+  IF_REQUIRE(p.m0 > 0 && p.m0 % 16 == 0 && p.m0 <= 128, "m0 must be a multiple of 16 in [16, 128]");
+  IF_REQUIRE(p.m0 <= n, "m0 must not exceed n");
+  IF_REQUIRE(p.max_outer >= 1 && p.max_inner >= 1 && p.max_cycles >= 1, "iteration limits must be >= 1");
+  IF_REQUIRE(p.alpha >= 0.0 && p.alpha < 1.0, "alpha must be in [0, 1)");
+  IF_REQUIRE(p.tol > 0.0, "tol must be positive");
+  IF_REQUIRE(p.precision == IFEAST_PREC_FP64 || p.precision == IFEAST_PREC_MIXED, "unknown precision");
+  IF_REQUIRE(p.inner_rule == IFEAST_INNER_GLOBAL || p.inner_rule == IFEAST_INNER_COLUMN, "unknown inner rule");
+  if (p.problem != IFEAST_PROBLEM_SYMMETRIC)
+    throw Error{IFEAST_ERR_UNSUPPORTED, "only real symmetric problems (IFEAST_PROBLEM_SYMMETRIC) are implemented"};
+  if (p.inner_guess != IFEAST_GUESS_RITZ)
+    throw Error{IFEAST_ERR_UNSUPPORTED, "only the Ritz initial guess (IFEAST_GUESS_RITZ) is implemented"};
+  IF_REQUIRE(C.nc >= 1 && C.nc <= 64, "nc must be in [1, 64]");
+  if (C.kind == IFEAST_CONTOUR_HALF) {
+    IF_REQUIRE(C.emax > C.emin, "emax must exceed emin");
+    IF_REQUIRE(C.rule == IFEAST_RULE_GAUSS_LEGENDRE || C.rule == IFEAST_RULE_TRAPEZOID, "unknown rule");
+  } else if (C.kind == IFEAST_CONTOUR_EXPLICIT) {
+    IF_REQUIRE(C.z != nullptr && C.w != nullptr, "explicit contour needs z and w");
+    IF_REQUIRE(C.half == 1, "symmetric problems need the upper half of a conjugate-symmetric rule");
+    IF_REQUIRE(C.emax > C.emin, "explicit contour needs the interval for membership");
+  } else {
+    throw Error{IFEAST_ERR_UNSUPPORTED, "symmetric problems use a HALF or EXPLICIT contour"};
+  }
+}
+
+// ------------------------------------------------------------ workspace
+namespace {
+
+struct Layout {
+  // byte sizes of every buffer of the workspace
+  size_t X, Q, AQ, BQ, R, vec, mm, rrwork, colpart;
+  size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, Hr, Tinv, Racc, chol, Yq, Uc, zs;
+};
+
+Layout layout(const Shape& s) {
+  const size_t ts = s.precision == IFEAST_PREC_MIXED ? 4 : 8;
+  const size_t n = (size_t)s.n, m0 = s.m0, ns = s.ns, k = s.k, m2 = 2 * m0;
+  const size_t ldc = ns * m0, ldh = (k + 1) * m0;
+  Layout L{};
+  L.X = L.Q = L.R = n * m0 * 8;
+  L.AQ = n * m0 * 8;
+  L.BQ = s.hasB ? n * m0 * 8 : 0;
+  L.vec = 4 * 128 * 8;
+  L.mm = m0 * m0 * 8;
+  L.rrwork = (4 * m0 * m0 + 4 * m0) * 8;
+  L.colpart = (size_t)col_sumsq_blocks(s.n) * m0 * 8;
+  L.V = (k + 1) * n * ldc * 2 * ts;
+  L.T1 = n * ldc * 2 * ts;
+  L.H = ns * ldh * k * m0 * 16;
+  L.Vh = ns * k * m2 * m0 * 16;
+  L.tauh = ns * k * m0 * 8;
+  L.g = L.u = ns * ldh * m0 * 16;
+  L.y = ns * k * m0 * m0 * 16;
+  L.flags = 8 * 64 * 4;
+  L.tol = ns * m0 * 8 * 2;
+  const size_t gp_inner = ts == 4 ? gram_partial_bytes<float>(s.n, (int)m2, (int)m2, (int)(ns * k))
+                                  : gram_partial_bytes<double>(s.n, (int)m2, (int)m2, (int)(ns * k));
+  const size_t gp_rr = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
+  L.gpart = std::max(gp_inner, gp_rr);
+  L.gred = std::max(ns * k * m2 * m2, 2 * m0 * m0) * 8;
+  L.Hr = ns * k * m2 * m2 * ts;
+  L.Tinv = ns * m2 * m2 * ts;
+  L.Racc = ns * m0 * m0 * 16;
+  L.chol = ns * 3 * m0 * m0 * 16;
+  L.Yq = ns * k * m2 * m0 * ts;
+  L.Uc = ns * (k + 1) * m2 * m2 * ts;
+  L.zs = 4 * 64 * 8;
+  return L;
+}
+
+size_t total(const Layout& L) {
+  return 3 * L.X + L.AQ + L.BQ + L.R + 8 * L.vec + 3 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
+         L.tauh + 2 * L.g + L.y + L.flags + L.tol + L.gpart + L.gred + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq + L.Uc +
+         3 * L.zs;
+}
+
+}  // namespace
+
+uint64_t workspace_bytes(const Shape& s) { return (uint64_t)total(layout(s)); }
+
+struct Engine::Impl {
+  Shape sh;
+  hipStream_t st;
+  Layout L;
+  // outer, FP64
+  DevBuf X, Q, Xn, AQ, BQ, R, lam, resid, eta, rho, C, GA, GB, rrwork, colpart, clsout;
+  // inner
+  DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
+  int* d_active = nullptr;  // ns
+  int* d_run = nullptr;     // ns
+  int* d_cont = nullptr;    // ns
+  int* d_iters = nullptr;   // ns
+  int* d_cdone = nullptr;   // ns
+  int* d_cls = nullptr;     // m0 flags
+  int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
+
+  Impl(hipStream_t s, const Shape& shape) : sh(shape), st(s), L(layout(shape)) {
+    X = DevBuf(L.X);
+    Q = DevBuf(L.Q);
+    Xn = DevBuf(L.X);
+    AQ = DevBuf(L.AQ);
+    if (L.BQ) BQ = DevBuf(L.BQ);
+    R = DevBuf(L.R);
+    lam = DevBuf(L.vec);
+    resid = DevBuf(L.vec);
+    eta = DevBuf(L.vec);
+    rho = DevBuf(L.vec);
+    clsout = DevBuf(L.vec);
+    C = DevBuf(L.mm);
+    GA = DevBuf(L.mm);
+    GB = DevBuf(L.mm);
+    rrwork = DevBuf(L.rrwork);
+    colpart = DevBuf(L.colpart);
+    V = DevBuf(L.V);
+    T1 = DevBuf(L.T1);
+    T2 = DevBuf(L.T1);
+    H = DevBuf(L.H);
+    Vh = DevBuf(L.Vh);
+    tauh = DevBuf(L.tauh);
+    g = DevBuf(L.g);
+    u = DevBuf(L.u);
+    y = DevBuf(L.y);
+    flags = DevBuf(L.flags);
+    tol = DevBuf(L.tol);
+    gpart = DevBuf(L.gpart);
+    gred = DevBuf(L.gred);
+    Hr = DevBuf(L.Hr);
+    Tinv = DevBuf(L.Tinv);
+    Racc = DevBuf(L.Racc);
+    chol = DevBuf(L.chol);
+    Yq = DevBuf(L.Yq);
+    Uc = DevBuf(L.Uc);
+    zsT = DevBuf(L.zs);
+    zsD = DevBuf(L.zs);
+    wsD = DevBuf(L.zs);
+    int* f = flags.as<int>();
+    d_active = f;
+    d_run = f + 64;
+    d_cont = f + 128;
+    d_iters = f + 192;
+    d_cdone = f + 256;
+    d_cls = f + 320;
+    ldc = (int64_t)sh.ns * sh.m0;
+    blk = sh.n * ldc * 2;
+    // stale basis blocks of shifts that stopped early are multiplied by zero
+    // coefficients later; zero them once so they are always finite
+    launch_fill_zero(st, V.p, V.bytes);
+    launch_fill_zero(st, H.p, H.bytes);
+  }
+
+  // -------------------------------------------------------- Rayleigh-Ritz
+  // X <- Qin C, lam, R = A X - B X Lambda, resid = ||R e_j||, eta (Algorithm 2, step 3-4)
+  void rr(const ifeast_matrix* A, const ifeast_matrix* B, const double* Qin, double* Xout, double* lamv, double* Rout,
+          double* residv, double* etav) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0;
+    double* aq = AQ.as<double>();
+    launch_spmm_real(st, A, m0, Qin, aq);
+    const double* bq = Qin;
+    if (B != nullptr) {
+      launch_spmm_real(st, B, m0, Qin, BQ.as<double>());
+      bq = BQ.as<double>();
+    }
+    GramArgs ga{n, m0, m0, 1, 1, Qin, m0, 0, 0, aq, m0, 0, 0, nullptr, GA.as<double>()};
+    launch_gram<double>(st, ga, gpart.p, gpart.bytes);
+    GramArgs gb{n, m0, m0, 1, 1, Qin, m0, 0, 0, bq, m0, 0, 0, nullptr, GB.as<double>()};
+    launch_gram<double>(st, gb, gpart.p, gpart.bytes);
+    launch_rr_small(st, m0, GA.as<double>(), GB.as<double>(), lamv, C.as<double>(), etav, rrwork.as<double>());
+    // X = Q C, AX = AQ C (into R), BX = BQ C (into Xn scratch unless B = I)
+    ApplyArgs ap{n, m0, m0, 1, 1, 1, Qin, m0, 0, 0, 0, C.p, 0, Xout, m0, 0, 1.0, 0.0, nullptr, nullptr};
+    launch_apply<double, double>(st, ap);
+    ApplyArgs aa = ap;
+    aa.A = aq;
+    aa.O = Rout;
+    launch_apply<double, double>(st, aa);
+    const double* bx = Xout;
+    if (B != nullptr) {
+      ApplyArgs ab = ap;
+      ab.A = bq;
+      ab.O = AQ.p;  // AQ is free now
+      launch_apply<double, double>(st, ab);
+      bx = AQ.as<double>();
+    }
+    launch_residual(st, n, m0, Rout, bx, lamv, Rout);
+    launch_col_sumsq(st, n, m0, Rout, residv, colpart.as<double>());
+  }
+
+  // ---------------------------------------------------------- CholQR2
+  // dst_s = orthonormal basis of src_s (n x m0 complex, per shift), Racc_s = R factor.
+  template <class T>
+  void cholqr2(const T* src, T* tmp, T* dst, const int* act) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0, m2 = 2 * m0, ns = sh.ns;
+    const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
+    const T* in = src;
+    for (int pass = 0; pass < 2; ++pass) {
+      T* out = pass == 0 ? tmp : dst;
+      GramArgs gg{n, m2, m2, ns, 1, in, 2 * ldc, m2, 0, in, 2 * ldc, m2, 0, act, gred.as<double>()};
+      launch_gram<T>(st, gg, gpart.p, gpart.bytes);
+      launch_cholqr_factor<T>(st, ns, m0, gred.as<double>(), pass == 0 ? 4.0 * m0 * eps : 0.0, act, Tinv.as<T>(),
+                              Racc.as<cd>(), pass, chol.as<cd>());
+      ApplyArgs ap{n, m2, m2, ns, 1, 1, in, 2 * ldc, m2, 0, 0, Tinv.p, (int64_t)m2 * m2, out, 2 * ldc, m2,
+                   1.0, 0.0, act, nullptr};
+      launch_apply<T, T>(st, ap);
+      in = out;
+    }
+  }
+
+  LsqArgs lsq_args() {
+    LsqArgs a;
+    a.ns = sh.ns;
+    a.m0 = sh.m0;
+    a.k = sh.k;
+    a.ldh = (sh.k + 1) * sh.m0;
+    a.H = H.as<cd>();
+    a.Vh = Vh.as<cd>();
+    a.tauh = tauh.as<double>();
+    a.g = g.as<cd>();
+    a.y = y.as<cd>();
+    a.u = u.as<cd>();
+    a.res = tol.as<double>() + (size_t)sh.ns * sh.m0;
+    a.tol = tol.as<double>();
+    a.active = d_active;
+    a.iters = d_iters;
+    a.cycle_done = d_cdone;
+    return a;
+  }
+
+  std::vector<int> d2h_ints(const int* d, int cnt) {
+    std::vector<int> h(cnt);
+    IF_HIP(hipMemcpyAsync(h.data(), d, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+    IF_HIP(hipStreamSynchronize(st));
+    return h;
+  }
+  void h2d(void* d, const void* h, size_t bytes) {
+    IF_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
+  }
+
+  // --------------------------------------------------------- inner solve
+  // Q = X rho_hat(Lambda) + sum_s wf_s V_s y_s over all GMRES(k) cycles.
+  // tolh: ns x m0 host stopping thresholds.  Returns per-shift block iterations.
+  template <class T>
+  std::vector<int> inner(const ifeast_matrix* A, const ifeast_matrix* B, const Nodes& nd, const ifeast_params& p,
+                         const double* Xd, const double* lamd, const double* Rd, const double* rhod,
+                         const std::vector<double>& tolh, double* Qd) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0, m2 = 2 * m0, ns = sh.ns, k = sh.k, ldh = (k + 1) * m0;
+    T* Vb = V.as<T>();
+    T* t1 = T1.as<T>();
+    T* t2 = T2.as<T>();
+    // shifts (device, type T and FP64) and quadrature factors
+    std::vector<T> zt(2 * ns);
+    std::vector<double> zdv(2 * ns), wf(2 * ns);
+    for (int s = 0; s < ns; ++s) {
+      zt[2 * s] = (T)nd.z[s].real();
+      zt[2 * s + 1] = (T)nd.z[s].imag();
+      zdv[2 * s] = nd.z[s].real();
+      zdv[2 * s + 1] = nd.z[s].imag();
+      const cd f = nd.half ? 2.0 * nd.w[s] : nd.w[s];
+      wf[2 * s] = f.real();
+      wf[2 * s + 1] = f.imag();
+    }
+    h2d(zsT.p, zt.data(), zt.size() * sizeof(T));
+    h2d(zsD.p, zdv.data(), zdv.size() * sizeof(double));
+    h2d(wsD.p, wf.data(), wf.size() * sizeof(double));
+    h2d(tol.p, tolh.data(), tolh.size() * sizeof(double));
+    // Q = X rho_hat(Lambda); start blocks R (z_s - Lambda)^{-1}
+    launch_scale_cols(st, n, m0, Xd, rhod, Qd);
+    launch_rhs_build<T>(st, n, m0, ns, Rd, lamd, zsD.as<double>(), t1);
+    std::vector<int> run(ns, 1), total_iters(ns, 0);
+    LsqArgs la = lsq_args();
+    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
+      h2d(d_run, run.data(), ns * sizeof(int));
+      h2d(d_active, run.data(), ns * sizeof(int));
+      // V_1 S = qr(start block)
+      cholqr2<T>(t1, t2, Vb, d_run);
+      launch_lsq_init(st, la, Racc.as<cd>());
+      int jdone = 0;
+      for (int j = 0; j < k; ++j) {
+        T* Vj = Vb + (int64_t)j * blk;
+        // W = z_s V_j - A V_j (all shifts in one launch)
+        launch_spmm_shifted<T>(st, A, B, ns, m0, zsT.as<T>(), d_active, Vj, t1);
+        // CGS2 against V_0..V_j
+        for (int pass = 0; pass < 2; ++pass) {
+          GramArgs gg{n, m2, m2, ns, j + 1, Vb, 2 * ldc, m2, blk, t1, 2 * ldc, m2, 0, d_active, gred.as<double>()};
+          launch_gram<T>(st, gg, gpart.p, gpart.bytes);
+          launch_cgs_combine<T>(st, ns, j + 1, m0, j, ldh, gred.as<double>(), d_active, H.as<cd>(), Hr.as<T>(), pass);
+          ApplyArgs ap{n,   m2,  m2,  ns,     j + 1,         j + 1, Vb, 2 * ldc, m2,      0,        blk,
+                       Hr.p, (int64_t)(j + 1) * m2 * m2, t1, 2 * ldc, m2, -1.0, 1.0, d_active, nullptr};
+          launch_apply<T, T>(st, ap);
+        }
+        // V_{j+1} H_{j+1,j} = qr(W)
+        cholqr2<T>(t1, t2, Vb + (int64_t)(j + 1) * blk, d_active);
+        launch_store_subdiag(st, ns, m0, j, ldh, d_active, Racc.as<cd>(), H.as<cd>());
+        launch_lsq_step(st, la, j);
+        jdone = j + 1;
+        const std::vector<int> act = d2h_ints(d_active, ns);
+        if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) break;
+      }
+      launch_lsq_finish(st, la);
+      launch_make_coefs<T>(st, la, wsD.as<double>(), jdone, Yq.as<T>(), Uc.as<T>(), 0);
+      // Q += Re sum_s V_s[0..jdone) Yq_s
+      ApplyArgs aq{n,  m2, m0, 1, ns * jdone, jdone, Vb, 2 * ldc, 0, m2, blk, Yq.p, 0, Qd, m0, 0,
+                   1.0, 1.0, nullptr, d_run};
+      launch_apply<T, double>(st, aq);
+      const std::vector<int> it = d2h_ints(d_iters, ns);
+      const std::vector<int> cd_ = d2h_ints(d_cdone, ns);
+      std::vector<int> cont(ns, 0);
+      bool any = false;
+      for (int s = 0; s < ns; ++s) {
+        if (!run[s]) continue;
+        total_iters[s] += it[s];
+        cont[s] = (cd_[s] == 0 && cyc + 1 < p.max_cycles) ? 1 : 0;
+        any = any || cont[s];
+      }
+      if (!any) break;
+      // restart residual: T1_s = sum_b V_s[b] u_s[b], b = 0..jdone
+      h2d(d_cont, cont.data(), ns * sizeof(int));
+      ApplyArgs ar{n, m2, m2, ns, jdone + 1, jdone + 1, Vb, 2 * ldc, m2, 0, blk, Uc.p,
+                   (int64_t)(jdone + 1) * m2 * m2, t1, 2 * ldc, m2, 1.0, 0.0, d_cont, nullptr};
+      launch_apply<T, T>(st, ar);
+      run = cont;
+    }
+    return total_iters;
+  }
+};
+
+Engine::Engine(hipStream_t st, const Shape& shape) : shape_(shape), st_(st), impl_(new Impl(st, shape)) {}
+Engine::~Engine() = default;
+
+namespace {
+
+std::vector<double> inner_tolerances(const Nodes& nd, const ifeast_params& p, const std::vector<double>& lam,
+                                     const std::vector<double>& resid, double rf, int m0) {
+  const int ns = (int)nd.z.size();
+  std::vector<double> t((size_t)ns * m0 * 2, 0.0);
+  for (int s = 0; s < ns; ++s)
+    for (int j = 0; j < m0; ++j) {
+      double v;
+      if (p.inner_rule == IFEAST_INNER_GLOBAL) {
+        v = p.alpha * rf;
+      } else {
+        // alpha times the start residual of column j: ||r_j|| / |z_s - lambda_j|
+        v = p.alpha * resid[j] / std::abs(nd.z[s] - lam[j]);
+      }
+      t[(size_t)s * m0 + j] = v;
+    }
+  return t;
+}
+
+ClassifyArgs classify_args(const ifeast_contour& C, const Nodes& nd, int m0, double tau, const double* zd,
+                           const double* wd) {
+  ClassifyArgs a;
+  a.m0 = m0;
+  a.nc = (int)nd.z.size();
+  a.half = nd.half ? 1 : 0;
+  a.kind = C.kind;
+  a.emin = C.emin;
+  a.emax = C.emax;
+  a.c_re = C.c_re;
+  a.c_im = C.c_im;
+  a.r = C.r;
+  a.tau = tau;
+  a.z = zd;
+  a.w = wd;
+  return a;
+}
+
+__global__ void k_rho(int m0, int nc, int half, const double* __restrict__ z, const double* __restrict__ w,
+                      const double* __restrict__ lam, double* __restrict__ rho) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m0) return;
+  double rr = 0.0, ri = 0.0;
+  const double l = lam[j];
+  for (int k = 0; k < nc; ++k) {
+    const double zr = z[2 * k] - l, zi = z[2 * k + 1];
+    const double d = zr * zr + zi * zi;
+    rr += (w[2 * k] * zr + w[2 * k + 1] * zi) / d;
+    ri += (w[2 * k + 1] * zr - w[2 * k] * zi) / d;
+  }
+  rho[j] = half ? 2.0 * rr : rr;
+}
+
+}  // namespace
+
+void Engine::rayleigh_ritz(const ifeast_matrix* A, const ifeast_matrix* B, const double* Q, double* lam, double* X,
+                           double* R, double* resid, double* eta) {
+  impl_->rr(A, B, Q, X, lam, R, resid, eta);
+}
+
+void Engine::filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour& C, const ifeast_params& p,
+                    const double* X, const double* lam, const double* R, double rf, double* Q,
+                    std::vector<int>* iters) {
+  Impl& I = *impl_;
+  const int m0 = shape_.m0;
+  const Nodes nd = make_nodes(C);
+  std::vector<double> zd(2 * nd.z.size()), wd(2 * nd.z.size());
+  for (size_t s = 0; s < nd.z.size(); ++s) {
+    zd[2 * s] = nd.z[s].real();
+    zd[2 * s + 1] = nd.z[s].imag();
+    wd[2 * s] = nd.w[s].real();
+    wd[2 * s + 1] = nd.w[s].imag();
+  }
+  DevBuf zb(zd.size() * 8), wb(wd.size() * 8);
+  I.h2d(zb.p, zd.data(), zd.size() * 8);
+  I.h2d(wb.p, wd.data(), wd.size() * 8);
+  hipLaunchKernelGGL(k_rho, dim3(1), dim3(128), 0, st_, m0, (int)nd.z.size(), nd.half ? 1 : 0, zb.as<double>(),
+                     wb.as<double>(), lam, I.rho.as<double>());
+  IF_HIP(hipGetLastError());
+  std::vector<double> lamh(m0), residh(m0);
+  IF_HIP(hipMemcpyAsync(lamh.data(), lam, m0 * 8, hipMemcpyDeviceToHost, st_));
+  launch_col_sumsq(st_, shape_.n, m0, R, I.resid.as<double>(), I.colpart.as<double>());
+  IF_HIP(hipMemcpyAsync(residh.data(), I.resid.p, m0 * 8, hipMemcpyDeviceToHost, st_));
+  IF_HIP(hipStreamSynchronize(st_));
+  const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, rf, m0);
+  std::vector<int> it = shape_.precision == IFEAST_PREC_MIXED
+                            ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+                            : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+  IF_HIP(hipStreamSynchronize(st_));
+  if (iters) *iters = it;
+}
+
+int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour& C, const ifeast_params& p,
+                  const double* X0_host, ifeast_result* res) {
+  Impl& I = *impl_;
+  const int64_t n = shape_.n;
+  const int m0 = shape_.m0, ns = shape_.ns;
+  const Nodes nd = make_nodes(C);
+  std::vector<double> zd(2 * ns), wd(2 * ns);
+  for (int s = 0; s < ns; ++s) {
+    zd[2 * s] = nd.z[s].real();
+    zd[2 * s + 1] = nd.z[s].imag();
+    wd[2 * s] = nd.w[s].real();
+    wd[2 * s + 1] = nd.w[s].imag();
+  }
+  DevBuf zb(zd.size() * 8), wb(wd.size() * 8), outh(16);
+  I.h2d(zb.p, zd.data(), zd.size() * 8);
+  I.h2d(wb.p, wd.data(), wd.size() * 8);
+  // initial block
+  std::vector<double> x0;
+  if (X0_host == nullptr) {
+    std::mt19937_64 gen(p.seed);
+    std::normal_distribution<double> nrm(0.0, 1.0);
+    x0.resize((size_t)n * m0);
+    for (auto& v : x0) v = nrm(gen);
+    X0_host = x0.data();
+  }
+  I.h2d(I.Q.p, X0_host, (size_t)n * m0 * 8);
+
+  hipEvent_t e0, e1;
+  IF_HIP(hipEventCreate(&e0));
+  IF_HIP(hipEventCreate(&e1));
+  IF_HIP(hipEventRecord(e0, st_));
+
+  double* X = I.X.as<double>();
+  double* Q = I.Q.as<double>();
+  double* lam = I.lam.as<double>();
+  double* resid = I.resid.as<double>();
+  double* eta = I.eta.as<double>();
+  double* R = I.R.as<double>();
+  SolveStats stats;
+  std::vector<double> lamh(m0), residh(m0), cls(2);
+  std::vector<int> flagh(m0);
+
+  auto classify = [&](double tau) {
+    const ClassifyArgs ca = classify_args(C, nd, m0, tau, zb.as<double>(), wb.as<double>());
+    launch_classify(st_, ca, lam, resid, eta, I.d_cls, I.clsout.as<double>());
+    hipLaunchKernelGGL(k_rho, dim3(1), dim3(128), 0, st_, m0, ns, nd.half ? 1 : 0, zb.as<double>(), wb.as<double>(),
+                       lam, I.rho.as<double>());
+    IF_HIP(hipGetLastError());
+    IF_HIP(hipMemcpyAsync(cls.data(), I.clsout.p, 16, hipMemcpyDeviceToHost, st_));
+    IF_HIP(hipMemcpyAsync(lamh.data(), lam, m0 * 8, hipMemcpyDeviceToHost, st_));
+    IF_HIP(hipMemcpyAsync(residh.data(), resid, m0 * 8, hipMemcpyDeviceToHost, st_));
+    IF_HIP(hipMemcpyAsync(flagh.data(), I.d_cls, m0 * 4, hipMemcpyDeviceToHost, st_));
+    IF_HIP(hipStreamSynchronize(st_));
+    for (int j = 0; j < m0; ++j)
+      if (!std::isfinite(lamh[j]) || !std::isfinite(residh[j]))
+        throw Error{IFEAST_ERR_NUMERICAL, "non-finite Ritz value or residual"};
+    stats.rf = cls[0];
+    stats.m = (int)cls[1];
+  };
+
+  // initial Rayleigh-Ritz on X0 gives Lambda, R and the exact initial ||R_F||
+  I.rr(A, B, Q, X, lam, R, resid, eta);
+  classify(0.0);
+  int status = IFEAST_WARN_NOT_CONVERGED;
+  for (int it = 0; it < p.max_outer; ++it) {
+    const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, stats.rf, m0);
+    std::vector<int> iters = shape_.precision == IFEAST_PREC_MIXED
+                                 ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+                                 : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+    I.rr(A, B, Q, X, lam, R, resid, eta);
+    classify(p.spurious_tau);
+    stats.outer = it + 1;
+    stats.rf_hist.push_back(stats.rf);
+    int mx = 0;
+    for (int s = 0; s < ns; ++s) {
+      stats.inner_hist.push_back(iters[s]);
+      stats.total_matvec += (int64_t)iters[s] * m0;
+      mx = std::max(mx, iters[s]);
+    }
+    stats.seq_matvec += mx;
+    if (stats.m > 0 && stats.rf <= p.tol) {
+      stats.converged = 1;
+      status = IFEAST_OK;
+      break;
+    }
+  }
+  IF_HIP(hipEventRecord(e1, st_));
+  IF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  IF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  stats.seconds = ms * 1e-3;
+  if (stats.converged && stats.m == 0) status = IFEAST_WARN_NO_EIG_IN_CONTOUR;
+  if (stats.m >= m0) status = IFEAST_WARN_M0_TOO_SMALL;
+
+  // outputs: counted pairs first (ascending), then the rest (ascending)
+  std::vector<int> order;
+  for (int j = 0; j < m0; ++j)
+    if (flagh[j] & IFEAST_FLAG_INSIDE) order.push_back(j);
+  for (int j = 0; j < m0; ++j)
+    if (!(flagh[j] & IFEAST_FLAG_INSIDE)) order.push_back(j);
+  res->m = stats.m;
+  res->outer_iters = stats.outer;
+  res->converged = stats.converged;
+  res->total_matvec = stats.total_matvec;
+  res->seq_matvec = stats.seq_matvec;
+  res->max_resid = stats.rf;
+  res->solve_seconds = stats.seconds;
+  for (int j = 0; j < m0; ++j) {
+    if (res->eval_re) res->eval_re[j] = lamh[order[j]];
+    if (res->eval_im) res->eval_im[j] = 0.0;
+    if (res->resid) res->resid[j] = residh[order[j]];
+    if (res->flags) res->flags[j] = flagh[order[j]];
+  }
+  if (res->rf_hist)
+    for (size_t i = 0; i < stats.rf_hist.size(); ++i) res->rf_hist[i] = stats.rf_hist[i];
+  if (res->inner_hist)
+    for (size_t i = 0; i < stats.inner_hist.size(); ++i) res->inner_hist[i] = stats.inner_hist[i];
+  if (res->evec) {
+    std::vector<double> xh((size_t)n * m0);
+    IF_HIP(hipMemcpyAsync(xh.data(), X, xh.size() * 8, hipMemcpyDeviceToHost, st_));
+    IF_HIP(hipStreamSynchronize(st_));
+    for (int64_t i = 0; i < n; ++i)
+      for (int j = 0; j < m0; ++j) res->evec[i * m0 + j] = xh[i * m0 + order[j]];
+  }
+  return status;
+}
+
+}  // namespace ifeast

@@ -1,0 +1,308 @@
+// Tall-skinny dense products on MFMA (gfx950 v_mfma_f32_16x16x4_f32 and
+// v_mfma_f64_16x16x4_f64).
+//
+// Block Arnoldi (Sec. 3.1) orthogonalises each new block against the basis
+// with Gram products H = V^H W and updates W -= V H; the Cholesky-QR of a
+// block, the quadrature sum Q = sum_k w_k V_k y_k, the restart residual and
+// the Rayleigh-Ritz products X = Q C are the same shapes.  Complex blocks are
+// handled through their real views: an n x m complex row-major block with
+// interleaved (re, im) is an n x 2m real block, so V^H W is read off the real
+// product V_r^T W_r (2m x 2m) and V H is V_r times the 2m x 2m real form of H.
+// Every product is therefore a real GEMM with one long dimension n.
+//
+// MFMA fragment layout used below (16x16x4, 64 lanes, lane l):
+//   A operand: A[i = l % 16][k = l / 16]
+//   B operand: B[k = l / 16][j = l % 16]
+//   D (4 values v): D[i = 4 * (l / 16) + v][j = l % 16]
+#include "internal.h"
+
+namespace ifeast {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = v4f;
+  __device__ static inline acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static inline acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  using acc = v4d;
+  __device__ static inline acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static inline acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int bid, int per) { return (bid % kXcds) * per + bid / kXcds; }
+
+// ------------------------------------------------------------------ Gram
+// grid: x = row split, y = output tile (tp * ntq + tq), z = item.
+// Each workgroup accumulates a (TB*16) x (TB*16) tile of A^T B over its rows
+// and writes it to `partial`; k_gram_reduce sums the splits in FP64.
+template <class T> struct GramCfg { static constexpr int KC = 32; };
+template <> struct GramCfg<double> { static constexpr int KC = 16; };
+
+template <class T, int TB>
+__global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t rows_per_split, int ntq,
+                                              T* __restrict__ partial) {
+  constexpr int KC = GramCfg<T>::KC;
+  constexpr int TP = TB * 16;
+  constexpr int LDS_LD = TP + 4;
+  constexpr int NBW = (TB * TB + 3) / 4;  // MFMA blocks per wavefront
+  __shared__ T sA[KC * LDS_LD];
+  __shared__ T sB[KC * LDS_LD];
+
+  const int item = blockIdx.z;
+  const int s = item / g.ni, i = item % g.ni;
+  if (g.active != nullptr && g.active[s] == 0) return;
+  const int split = blockIdx.x;
+  const int tp = blockIdx.y / ntq, tq = blockIdx.y % ntq;
+  const int p0 = tp * TP, q0 = tq * TP;
+  const int vp = min(TP, g.PW - p0), vq = min(TP, g.QW - q0);  // valid extents (multiples of 16)
+  const int64_t r0 = (int64_t)split * rows_per_split;
+  const int64_t r1 = min(g.n, r0 + rows_per_split);
+
+  const T* __restrict__ A = static_cast<const T*>(g.A) + s * g.a_s + i * g.a_i + p0;
+  const T* __restrict__ B = static_cast<const T*>(g.B) + s * g.b_s + i * g.b_i + q0;
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  typename Mfma<T>::acc acc[NBW];
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) acc[t] = Mfma<T>::zero();
+
+  for (int64_t rc = r0; rc < r1; rc += KC) {
+    for (int idx = tid; idx < KC * TP; idx += 256) {
+      const int r = idx / TP, c = idx % TP;
+      const int64_t row = rc + r;
+      const bool ok = row < r1;
+      sA[r * LDS_LD + c] = (ok && c < vp) ? A[row * g.lda + c] : T(0);
+      sB[r * LDS_LD + c] = (ok && c < vq) ? B[row * g.ldb + c] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+#pragma unroll
+      for (int t = 0; t < NBW; ++t) {
+        const int b = wave + 4 * t;
+        if (b < TB * TB) {
+          const int pb = b / TB, qb = b % TB;
+          if (pb * 16 < vp && qb * 16 < vq) {
+            const T a = sA[(kk + lk) * LDS_LD + pb * 16 + li];
+            const T bb = sB[(kk + lk) * LDS_LD + qb * 16 + li];
+            acc[t] = Mfma<T>::mma(a, bb, acc[t]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  T* out = partial + ((int64_t)item * nsplit + split) * g.PW * g.QW;
+#pragma unroll
+  for (int t = 0; t < NBW; ++t) {
+    const int b = wave + 4 * t;
+    if (b < TB * TB) {
+      const int pb = b / TB, qb = b % TB;
+      if (pb * 16 < vp && qb * 16 < vq) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int p = p0 + pb * 16 + 4 * lk + v;
+          const int q = q0 + qb * 16 + li;
+          out[(int64_t)p * g.QW + q] = acc[t][v];
+        }
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, const int* __restrict__ active,
+                              const T* __restrict__ partial, double* __restrict__ G) {
+  const int64_t per_item = (int64_t)PW * QW;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= per_item * items) return;
+  const int item = (int)(idx / per_item);
+  const int64_t e = idx % per_item;
+  if (active != nullptr && active[item / ni] == 0) return;
+  const T* p = partial + (int64_t)item * nsplit * per_item + e;
+  double sum = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) sum += (double)p[(int64_t)sp * per_item];
+  G[idx] = sum;
+}
+
+inline int gram_tb(int W) {
+  // tile blocks per dimension: at most 8 (128 reals), as few tiles as possible
+  const int nb = W / 16;
+  const int nt = (nb + 7) / 8;
+  return (nb + nt - 1) / nt;
+}
+
+inline int gram_nsplit(int64_t n, int items, int tiles) {
+  int64_t want = (2048 + (int64_t)items * tiles - 1) / ((int64_t)items * tiles);
+  int64_t maxs = std::max<int64_t>(1, n / 512);
+  return (int)std::max<int64_t>(1, std::min(want, maxs));
+}
+
+// ------------------------------------------------------------------ apply
+// grid: x = 64-row tile (XCD renumbered), y = output column tile, z = item.
+// Wavefront w owns rows [16w, 16w+16) of the tile and TBQ column blocks.
+template <class T> struct ApplyCfg { static constexpr int KC = 32; };
+template <> struct ApplyCfg<double> { static constexpr int KC = 16; };
+
+template <class T, class TO, int TBQ>
+__global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
+  constexpr int KC = ApplyCfg<T>::KC;
+  constexpr int TQ = TBQ * 16;
+  constexpr int LDA_S = KC + 4;
+  constexpr int LDB_S = TQ + 4;
+  __shared__ T sA[64 * LDA_S];
+  __shared__ T sB[KC * LDB_S];
+
+  const int item = blockIdx.z;
+  if (a.active_item != nullptr && a.active_item[item] == 0) return;
+  const int64_t nrt = (a.n + 63) / 64;
+  const int64_t rt = xcd_block(blockIdx.x, per);
+  if (rt >= nrt) return;
+  const int64_t r0 = rt * 64;
+  const int q0 = blockIdx.y * TQ;
+  const int vq = min(TQ, a.OW - q0);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  typename Mfma<T>::acc acc[TBQ];
+#pragma unroll
+  for (int t = 0; t < TBQ; ++t) acc[t] = Mfma<T>::zero();
+
+  const T* __restrict__ Abase = static_cast<const T*>(a.A) + item * a.a_item;
+  const T* __restrict__ Bbase = static_cast<const T*>(a.Bm) + item * a.bm_item;
+  for (int b = 0; b < a.nb; ++b) {
+    const int sb = b / a.nbi, ib = b % a.nbi;
+    if (a.active_sb != nullptr && a.active_sb[sb] == 0) continue;
+    const T* __restrict__ Ab = Abase + sb * a.a_s + ib * a.a_i;
+    const T* __restrict__ Bb = Bbase + (int64_t)b * a.KW * a.OW;
+    for (int k0 = 0; k0 < a.KW; k0 += KC) {
+      for (int idx = tid; idx < 64 * KC; idx += 256) {
+        const int r = idx / KC, c = idx % KC;
+        const int64_t row = r0 + r;
+        sA[r * LDA_S + c] = (row < a.n && k0 + c < a.KW) ? Ab[row * a.lda + k0 + c] : T(0);
+      }
+      for (int idx = tid; idx < KC * TQ; idx += 256) {
+        const int r = idx / TQ, c = idx % TQ;
+        sB[r * LDB_S + c] = (k0 + r < a.KW && c < vq) ? Bb[(int64_t)(k0 + r) * a.OW + q0 + c] : T(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const T av = sA[(wave * 16 + li) * LDA_S + kk + lk];
+#pragma unroll
+        for (int t = 0; t < TBQ; ++t) {
+          if (t * 16 < vq) {
+            const T bv = sB[(kk + lk) * LDB_S + t * 16 + li];
+            acc[t] = Mfma<T>::mma(av, bv, acc[t]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  TO* __restrict__ O = static_cast<TO*>(a.O) + item * a.o_item;
+#pragma unroll
+  for (int t = 0; t < TBQ; ++t) {
+    if (t * 16 < vq) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + wave * 16 + 4 * lk + v;
+        const int col = q0 + t * 16 + li;
+        if (row < a.n) {
+          TO* o = O + row * a.ldo + col;
+          const TO val = (TO)(a.alpha * (double)acc[t][v]);
+          *o = (a.beta == 0.0) ? val : (TO)(a.beta * (double)(*o)) + val;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <class T>
+size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
+  const int tb = std::max(gram_tb(PW), gram_tb(QW));
+  const int tiles = ((PW / 16 + tb - 1) / tb) * ((QW / 16 + tb - 1) / tb);
+  const int ns = gram_nsplit(n, items, tiles);
+  return (size_t)items * ns * PW * QW * sizeof(T);
+}
+
+template <class T>
+void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes) {
+  IF_REQUIRE(g.PW % 16 == 0 && g.QW % 16 == 0, "gram: widths must be multiples of 16");
+  // one square tile size for both dimensions
+  const int tb = std::max(gram_tb(g.PW), gram_tb(g.QW));
+  const int ntp = (g.PW / 16 + tb - 1) / tb, ntq = (g.QW / 16 + tb - 1) / tb;
+  const int items = g.ns * g.ni;
+  const int nsplit = gram_nsplit(g.n, items, ntp * ntq);
+  IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
+  constexpr int KC = GramCfg<T>::KC;
+  int64_t rps = (g.n + nsplit - 1) / nsplit;
+  rps = (rps + KC - 1) / KC * KC;
+  const dim3 grid(nsplit, ntp * ntq, items), block(256);
+  T* part = static_cast<T*>(partial);
+  switch (tb) {
+    case 1: hipLaunchKernelGGL((k_gram<T, 1>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 2: hipLaunchKernelGGL((k_gram<T, 2>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 3: hipLaunchKernelGGL((k_gram<T, 3>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 4: hipLaunchKernelGGL((k_gram<T, 4>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 5: hipLaunchKernelGGL((k_gram<T, 5>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 6: hipLaunchKernelGGL((k_gram<T, 6>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 7: hipLaunchKernelGGL((k_gram<T, 7>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 8: hipLaunchKernelGGL((k_gram<T, 8>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    default: throw Error{IFEAST_ERR_INVALID_ARG, "gram: unsupported tile"};
+  }
+  IF_HIP(hipGetLastError());
+  const int64_t total = (int64_t)items * g.PW * g.QW;
+  hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
+                     g.PW, g.QW, g.ni, g.active, part, g.G);
+  IF_HIP(hipGetLastError());
+}
+
+template <class T, class TO>
+void launch_apply(hipStream_t st, const ApplyArgs& a) {
+  IF_REQUIRE(a.OW % 16 == 0, "apply: output width must be a multiple of 16");
+  const int nbq = a.OW / 16;
+  const int ntq = (nbq + 7) / 8;
+  const int tbq = (nbq + ntq - 1) / ntq;
+  const int64_t nrt = (a.n + 63) / 64;
+  const int per = (int)((nrt + kXcds - 1) / kXcds);
+  const dim3 grid(per * kXcds, ntq, a.items), block(256);
+  switch (tbq) {
+    case 1: hipLaunchKernelGGL((k_apply<T, TO, 1>), grid, block, 0, st, a, per); break;
+    case 2: hipLaunchKernelGGL((k_apply<T, TO, 2>), grid, block, 0, st, a, per); break;
+    case 3: hipLaunchKernelGGL((k_apply<T, TO, 3>), grid, block, 0, st, a, per); break;
+    case 4: hipLaunchKernelGGL((k_apply<T, TO, 4>), grid, block, 0, st, a, per); break;
+    case 5: hipLaunchKernelGGL((k_apply<T, TO, 5>), grid, block, 0, st, a, per); break;
+    case 6: hipLaunchKernelGGL((k_apply<T, TO, 6>), grid, block, 0, st, a, per); break;
+    case 7: hipLaunchKernelGGL((k_apply<T, TO, 7>), grid, block, 0, st, a, per); break;
+    case 8: hipLaunchKernelGGL((k_apply<T, TO, 8>), grid, block, 0, st, a, per); break;
+    default: throw Error{IFEAST_ERR_INVALID_ARG, "apply: unsupported tile"};
+  }
+  IF_HIP(hipGetLastError());
+}
+
+template size_t gram_partial_bytes<float>(int64_t, int, int, int);
+template size_t gram_partial_bytes<double>(int64_t, int, int, int);
+template void launch_gram<float>(hipStream_t, const GramArgs&, void*, size_t);
+template void launch_gram<double>(hipStream_t, const GramArgs&, void*, size_t);
+template void launch_apply<float, float>(hipStream_t, const ApplyArgs&);
+template void launch_apply<float, double>(hipStream_t, const ApplyArgs&);
+template void launch_apply<double, double>(hipStream_t, const ApplyArgs&);
+
+}  // namespace ifeast

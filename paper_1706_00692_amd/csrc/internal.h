@@ -1,0 +1,210 @@
+// Internal declarations of libifeast: device matrices, the context, and the
+// host-side launchers of every kernel.  Kernels are written for gfx950
+// (CDNA4: 64-lane wavefronts, MFMA, 160 KiB LDS per CU, 8 XCDs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <complex>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ifeast.h"
+
+namespace ifeast {
+
+using cd = std::complex<double>;
+
+// Error carried from deep inside the engine up to the C ABI.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+#define IF_HIP(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::ifeast::Error{e_ == hipErrorOutOfMemory ? IFEAST_ERR_OOM : IFEAST_ERR_DEVICE,  \
+                            std::string(#call) + ": " + hipGetErrorString(e_)};              \
+  } while (0)
+
+#define IF_REQUIRE(cond, msg)                                                                \
+  do {                                                                                       \
+    if (!(cond)) throw ::ifeast::Error{IFEAST_ERR_INVALID_ARG, (msg)};                       \
+  } while (0)
+
+// Device buffer with RAII release.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b);
+  ~DevBuf();
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace ifeast
+
+struct ifeast_matrix {
+  int64_t n = 0, nnz = 0;
+  ifeast::DevBuf rowptr, colind, val, valf;  // int32, int32, double, float
+  double norm1 = 0.0;                        // max column sum of |a_ij|
+  int device = 0;
+};
+
+namespace ifeast {
+struct Server;  // serving loop (serve.cpp)
+}
+
+struct ifeast_ctx {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;
+  std::string last_error;
+  std::mutex mu;  // serialises solves on this context
+  std::unique_ptr<ifeast::Server> server;
+};
+
+namespace ifeast {
+
+// ------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return immediately.
+
+// W[:, s] = z_s B V[:, s] - A V[:, s] for the ns*m0 complex columns (T = float|double).
+template <class T>
+void launch_spmm_shifted(hipStream_t st, const ifeast_matrix* A, const ifeast_matrix* B, int ns, int m0,
+                         const T* zs /*device, 2*ns*/, const int* active /*device ns or null*/,
+                         const T* V, T* W);
+
+// Y = M X for real FP64 n x m blocks (row-major, leading dimension m).
+void launch_spmm_real(hipStream_t st, const ifeast_matrix* M, int m, const double* X, double* Y);
+
+// Tall-skinny Gram products on real views, batched:
+//   G[item] = sum_rows A_item^T B_item,  A_item (n x PW), B_item (n x QW).
+// item = s*ni + i addresses A = A0 + s*a_s + i*a_i, B = B0 + s*b_s (+ i*b_i).
+// Partial sums over row splits are reduced in FP64 into G (double, item-major, PW x QW).
+struct GramArgs {
+  int64_t n;
+  int PW, QW;
+  int ns, ni;  // items = ns * ni
+  const void* A;
+  int64_t lda, a_s, a_i;  // in elements
+  const void* B;
+  int64_t ldb, b_s, b_i;
+  const int* active;  // per s, may be null
+  double* G;          // ns*ni*PW*QW
+};
+template <class T>
+void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes);
+template <class T>
+size_t gram_partial_bytes(int64_t n, int PW, int QW, int items);
+
+// Tall-skinny products on real views, batched over items (z):
+//   O_item = beta O_item + alpha sum_b A_{item,b} (n x KW) * Bm_{item,b} (KW x OW)
+// with b = 0..nb-1 split as (sb, ib) = (b / nbi, b % nbi):
+//   A = A0 + item*a_item + sb*a_s + ib*a_i,  Bm = B0 + item*bm_item + b*KW*OW,
+//   O = O0 + item*o_item.  Blocks whose shift flag (active[sb] or active[item]) is 0 are skipped.
+struct ApplyArgs {
+  int64_t n;
+  int KW, OW;
+  int items, nb, nbi;
+  const void* A;
+  int64_t lda, a_item, a_s, a_i;
+  const void* Bm;  // same type as A
+  int64_t bm_item;
+  void* O;         // TO
+  int64_t ldo, o_item;
+  double alpha, beta;
+  const int* active_item;  // per item, may be null
+  const int* active_sb;    // per sb, may be null
+};
+template <class T, class TO>
+void launch_apply(hipStream_t st, const ApplyArgs& a);
+
+// ---- small dense kernels (one workgroup per shift / per solve), FP64
+// CholQR factor from the Gram of the block: per shift s,
+//   G (2m0 x 2m0 real view of W^H W) -> column scaling, optional shift,
+//   Cholesky -> Tinv (real-ified, type T, 2m0 x 2m0) and Rf (complex m0 x m0,
+//   W = W_new Rf); if `accumulate`, Racc = Rf * Racc_prev.
+template <class T>
+void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, double shift_rel, const int* active,
+                          T* Tinv, cd* Racc, int accumulate, cd* work /*ns x 3 m0^2*/);
+
+// CGS combine: for items (s, i), i < ni: C = complex(G) -> H[s](i-block rows, j-block col) = C
+// (+= C when accumulate), Hr[s, i] = real-ified C (type T) for the update W -= V Hr.
+template <class T>
+void launch_cgs_combine(hipStream_t st, int ns, int ni, int m0, int j, int ldh, const double* G,
+                        const int* active, cd* H, T* Hr, int accumulate);
+
+// Write Racc (m0 x m0 complex) into H[s] at block (row j+1, col j).
+void launch_store_subdiag(hipStream_t st, int ns, int m0, int j, int ldh, const int* active, const cd* Racc, cd* H);
+
+// Block-GMRES least squares, incremental Householder QR on Hbar.
+struct LsqArgs {
+  int ns, m0, k, ldh;
+  cd* H;        // ns x [ldh x k*m0] column-major, (k+1)*m0 rows used
+  cd* Vh;       // ns x k x [2m0 x m0] Householder vectors (column-major)
+  double* tauh; // ns x k x m0 scalars 2/(v^H v)
+  cd* g;        // ns x [(k+1)*m0 x m0] column-major transformed right-hand side
+  cd* y;        // ns x [k*m0 x m0] column-major solution
+  cd* u;        // ns x [(k+1)*m0 x m0] column-major residual coefficients
+  double* res;  // ns x m0 current per-column residual norms
+  const double* tol;  // ns x m0 stopping thresholds
+  int* active;        // ns: shift still iterating in this cycle
+  int* iters;         // ns: block iterations in this cycle
+  int* cycle_done;    // ns: 1 if the shift met its tolerance
+};
+void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S /*ns x m0 x m0 row-major*/);
+void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j);
+void launch_lsq_finish(hipStream_t st, const LsqArgs& a);
+// Real-ified coefficient blocks from y and u for the tall-skinny products:
+//   Yq[s][b] (2m0 x m0, T): Q += Re(V_b (wfac_s y_b))  (wfac = 2w for HALF contours, w otherwise)
+//   Uc[s][b] (2m0 x 2m0, T): T1_s = sum_b V_b u_b
+template <class T>
+void launch_make_coefs(hipStream_t st, const LsqArgs& a, const double* wfac /*2*ns*/, int jmax, T* Yq, T* Uc,
+                       int complex_out);
+
+// Rayleigh-Ritz small eigensolve (symmetric): from GA = Q^T A Q, GB = Q^T B Q
+// produce lam (ascending), C (m0 x m0 row-major, X = Q C), eta = 1/||c_l||.
+// work: 4 m0^2 + 4 m0 doubles.
+void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB, double* lam, double* C,
+                     double* eta, double* work);
+
+// Membership, spurious test and ||R_F|| (Algorithm 2, step 4) on device:
+// flags[j] = IFEAST_FLAG_* bits; out[0] = ||R_F||, out[1] = m (as double).
+struct ClassifyArgs {
+  int m0, nc, half, kind;  // kind: IFEAST_CONTOUR_*
+  double emin, emax, c_re, c_im, r, tau;
+  const double* z;  // device 2*nc
+  const double* w;  // device 2*nc
+};
+void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* resid,
+                     const double* eta, int* flags, double* out);
+
+// ---- elementwise / reductions
+void launch_col_sumsq(hipStream_t st, int64_t n, int m, const double* X, double* out /*m*/, double* partial);
+void launch_scale_cols(hipStream_t st, int64_t n, int m, const double* X, const double* f, double* Y);
+void launch_residual(hipStream_t st, int64_t n, int m, const double* AX, const double* BX, const double* lam,
+                     double* R);
+template <class T>
+void launch_rhs_build(hipStream_t st, int64_t n, int m0, int ns, const double* R, const double* lam,
+                      const double* z /*2*ns*/, T* out);
+void launch_col_sumsq_finish(hipStream_t st, int nblocks, int m, const double* partial, double* out, int do_sqrt);
+int col_sumsq_blocks(int64_t n);
+void launch_fill_zero(hipStream_t st, void* p, size_t bytes);
+
+}  // namespace ifeast

@@ -1,0 +1,799 @@
+// Small dense kernels of the inner solve and the Rayleigh-Ritz step, in FP64.
+//
+// They act on m0 x m0 (or (k+1)m0 x k m0) matrices, run one workgroup per
+// shifted system, and are latency-bound; keeping them on the device keeps
+// the whole inner loop free of host round trips except one status word.
+//
+//  * cholqr_factor: Cholesky of the column-scaled Gram of a block (block
+//    Arnoldi normalisation, Sec. 3.1) and the inverse factor for the update.
+//  * cgs_combine: complex Gram blocks from their real-view products, added to
+//    the block Hessenberg matrix Hbar (Sec. 3.1).
+//  * lsq_*: block GMRES least squares min ||E1 S - Hbar Y|| (Sec. 3.2) by an
+//    incremental Householder QR of Hbar, one block column per Arnoldi step,
+//    with the per-column residual norms the stopping rule needs (Algorithm 2,
+//    step 1).
+//  * rr_small: reduced eigenproblem of the Rayleigh-Ritz step (Algorithm 2,
+//    step 3) by SVQB B-orthonormalisation and cyclic Jacobi.
+//  * classify: membership, filter-gain test and ||R_F|| (Algorithm 2, step 4).
+#include "internal.h"
+
+namespace ifeast {
+
+namespace {
+
+typedef double2 c2;
+__device__ inline c2 cmk(double r, double i) { return make_double2(r, i); }
+__device__ inline c2 cadd(c2 a, c2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__device__ inline c2 csub(c2 a, c2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__device__ inline c2 cmul(c2 a, c2 b) { return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline c2 cconj(c2 a) { return cmk(a.x, -a.y); }
+// conj(a) * b
+__device__ inline c2 cjmul(c2 a, c2 b) { return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+__device__ inline c2 cscale(double s, c2 a) { return cmk(s * a.x, s * a.y); }
+__device__ inline double cabs2(c2 a) { return a.x * a.x + a.y * a.y; }
+__device__ inline c2 cdiv(c2 a, c2 b) {
+  const double d = cabs2(b);
+  return cmk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// Block-wide reductions over 256 threads.
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+__device__ inline double block_max(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = sh[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, sh[i]);
+  __syncthreads();
+  return t;
+}
+
+// Real 2x2 form of complex h acting on interleaved row vectors: [vr, vi] * M = v * h.
+template <class T>
+__device__ inline void store_realified(T* M, int ldm, int a, int b, c2 h) {
+  M[(2 * a) * ldm + 2 * b] = (T)h.x;
+  M[(2 * a) * ldm + 2 * b + 1] = (T)h.y;
+  M[(2 * a + 1) * ldm + 2 * b] = (T)(-h.y);
+  M[(2 * a + 1) * ldm + 2 * b + 1] = (T)h.x;
+}
+
+// complex entry (a, b) of V^H W from the real-view product G = V_r^T W_r (2m x 2m)
+__device__ inline c2 gram_entry(const double* G, int ld, int a, int b) {
+  const double rr = G[(2 * a) * ld + 2 * b], ii = G[(2 * a + 1) * ld + 2 * b + 1];
+  const double ri = G[(2 * a) * ld + 2 * b + 1], ir = G[(2 * a + 1) * ld + 2 * b];
+  return cmk(rr + ii, ri - ir);
+}
+
+// ------------------------------------------------------------ CholQR factor
+template <class T>
+__global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __restrict__ G, double shift_rel,
+                                                       const int* __restrict__ active, T* __restrict__ Tinv,
+                                                       c2* __restrict__ Racc, int accumulate, c2* __restrict__ work) {
+  const int s = blockIdx.x;
+  if (active != nullptr && active[s] == 0) return;
+  const int tid = threadIdx.x, m2 = 2 * m0;
+  const double* Gs = G + (int64_t)s * m2 * m2;
+  c2* L = work + (int64_t)s * 3 * m0 * m0;
+  c2* Ri = L + m0 * m0;
+  c2* Tm = Ri + m0 * m0;
+  T* Tv = Tinv + (int64_t)s * m2 * m2;
+  c2* Ra = Racc + (int64_t)s * m0 * m0;
+  __shared__ double dsc[128];
+  __shared__ double red[8];
+  __shared__ double piv;
+
+  double dmax = 0.0;
+  for (int a = tid; a < m0; a += 256) {
+    const double d = sqrt(fmax(Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1], 0.0));
+    dsc[a] = d;
+    dmax = fmax(dmax, d);
+  }
+  dmax = block_max(dmax, red);
+  for (int a = tid; a < m0; a += 256) {
+    // a zero column keeps unit scaling; its direction is then set by rounding
+    if (!(dsc[a] > 1e-300 + 1e-150 * dmax)) dsc[a] = (dmax > 0.0 ? dmax : 1.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < m0 * m0; idx += 256) {
+    const int a = idx / m0, b = idx % m0;
+    c2 g = cscale(1.0 / (dsc[a] * dsc[b]), gram_entry(Gs, m2, a, b));
+    if (a == b) g = cmk(g.x + shift_rel, 0.0);
+    L[idx] = g;
+  }
+  __syncthreads();
+  // Cholesky G = L L^H (lower triangle of L)
+  for (int c = 0; c < m0; ++c) {
+    if (tid == 0) {
+      const double p = L[c * m0 + c].x;
+      piv = (p > 1e-300) ? sqrt(p) : 1e-150;
+      L[c * m0 + c] = cmk(piv, 0.0);
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int r = c + 1 + tid; r < m0; r += 256) L[r * m0 + c] = cscale(inv, L[r * m0 + c]);
+    __syncthreads();
+    const int nt = m0 - c - 1;
+    for (int idx = tid; idx < nt * nt; idx += 256) {
+      const int r = c + 1 + idx / nt, q = c + 1 + idx % nt;
+      if (q <= r) L[r * m0 + q] = csub(L[r * m0 + q], cmul(L[r * m0 + c], cconj(L[q * m0 + c])));
+    }
+    __syncthreads();
+  }
+  // Ri = (L^H)^{-1}, upper triangular; R'[c][e] = conj(L[e][c])
+  for (int d = tid; d < m0; d += 256) {
+    for (int c = m0 - 1; c > d; --c) Ri[c * m0 + d] = cmk(0.0, 0.0);
+    for (int c = d; c >= 0; --c) {
+      c2 sum = cmk(c == d ? 1.0 : 0.0, 0.0);
+      for (int e = c + 1; e <= d; ++e) sum = csub(sum, cmul(cconj(L[e * m0 + c]), Ri[e * m0 + d]));
+      Ri[c * m0 + d] = cscale(1.0 / L[c * m0 + c].x, sum);
+    }
+  }
+  __syncthreads();
+  // W_new = W D^{-1} Ri  ->  real form of D^{-1} Ri; factor R = L^H D
+  for (int idx = tid; idx < m0 * m0; idx += 256) {
+    const int a = idx / m0, b = idx % m0;
+    store_realified(Tv, m2, a, b, cscale(1.0 / dsc[a], Ri[idx]));
+    Tm[idx] = (b >= a) ? cscale(dsc[b], cconj(L[b * m0 + a])) : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  if (accumulate) {
+    // Racc <- R * Racc (both upper triangular); Ri is free now
+    for (int idx = tid; idx < m0 * m0; idx += 256) {
+      const int a = idx / m0, b = idx % m0;
+      c2 sum = cmk(0.0, 0.0);
+      for (int e = a; e <= b; ++e) sum = cadd(sum, cmul(Tm[a * m0 + e], Ra[e * m0 + b]));
+      Ri[idx] = sum;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < m0 * m0; idx += 256) Ra[idx] = Ri[idx];
+  } else {
+    for (int idx = tid; idx < m0 * m0; idx += 256) Ra[idx] = Tm[idx];
+  }
+}
+
+template <class T>
+__global__ void k_cgs_combine(int ns, int ni, int m0, int j, int ldh, const double* __restrict__ G,
+                              const int* __restrict__ active, c2* __restrict__ H, T* __restrict__ Hr, int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)m0 * m0;
+  if (idx >= (int64_t)ns * ni * per) return;
+  const int item = (int)(idx / per);
+  const int s = item / ni, i = item % ni;
+  if (active != nullptr && active[s] == 0) return;
+  const int a = (int)((idx % per) / m0), b = (int)(idx % m0);
+  const int m2 = 2 * m0;
+  const c2 c = gram_entry(G + (int64_t)item * m2 * m2, m2, a, b);
+  c2* h = H + (int64_t)s * ldh * ((int64_t)(ldh / m0 - 1) * m0) + (int64_t)(j * m0 + b) * ldh + i * m0 + a;
+  *h = accumulate ? cadd(*h, c) : c;
+  store_realified(Hr + (int64_t)item * m2 * m2, m2, a, b, c);
+}
+
+__global__ void k_store_subdiag(int ns, int m0, int j, int ldh, const int* __restrict__ active,
+                                const c2* __restrict__ Racc, c2* __restrict__ H) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)m0 * m0;
+  if (idx >= ns * per) return;
+  const int s = (int)(idx / per);
+  if (active != nullptr && active[s] == 0) return;
+  const int a = (int)((idx % per) / m0), b = (int)(idx % m0);
+  const int kk = ldh / m0 - 1;
+  H[(int64_t)s * ldh * kk * m0 + (int64_t)(j * m0 + b) * ldh + (j + 1) * m0 + a] = Racc[s * per + a * m0 + b];
+}
+
+// -------------------------------------------------------------- least squares
+struct LsqView {
+  c2 *H, *Vh, *g, *y, *u;
+  double *tau, *res;
+  const double* tol;
+};
+
+__device__ inline LsqView lsq_view(const LsqArgs& a, int s) {
+  const int m0 = a.m0, k = a.k, ldh = a.ldh;
+  LsqView v;
+  v.H = reinterpret_cast<c2*>(a.H) + (int64_t)s * ldh * k * m0;
+  v.Vh = reinterpret_cast<c2*>(a.Vh) + (int64_t)s * k * 2 * m0 * m0;
+  v.tau = a.tauh + (int64_t)s * k * m0;
+  v.g = reinterpret_cast<c2*>(a.g) + (int64_t)s * ldh * m0;
+  v.y = reinterpret_cast<c2*>(a.y) + (int64_t)s * k * m0 * m0;
+  v.u = reinterpret_cast<c2*>(a.u) + (int64_t)s * ldh * m0;
+  v.res = a.res + (int64_t)s * m0;
+  v.tol = a.tol + (int64_t)s * m0;
+  return v;
+}
+
+// Apply reflector (v, tau) with support rows [r0, r1) of `x` (column `col`, leading dim ld).
+__device__ inline void apply_reflector(const c2* v, double tau, int r0, int r1, c2* x, int xoff, int ld, int col) {
+  if (tau == 0.0) return;
+  c2 dot = cmk(0.0, 0.0);
+  for (int r = r0; r < r1; ++r) dot = cadd(dot, cjmul(v[r], x[xoff + r + (int64_t)col * ld]));
+  const c2 f = cscale(tau, dot);
+  for (int r = r0; r < r1; ++r) {
+    c2* p = x + xoff + r + (int64_t)col * ld;
+    *p = csub(*p, cmul(f, v[r]));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lsq_init(LsqArgs a, const c2* __restrict__ S) {
+  const int s = blockIdx.x;
+  if (a.active[s] == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, tid = threadIdx.x;
+  for (int64_t idx = tid; idx < (int64_t)ldh * m0; idx += 256) v.g[idx] = cmk(0.0, 0.0);
+  __syncthreads();
+  const c2* Ss = S + (int64_t)s * m0 * m0;
+  for (int idx = tid; idx < m0 * m0; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    v.g[r + (int64_t)c * ldh] = Ss[idx];
+  }
+  __syncthreads();
+  for (int c = tid; c < m0; c += 256) {
+    double ss = 0.0;
+    for (int r = 0; r < m0; ++r) ss += cabs2(v.g[r + (int64_t)c * ldh]);
+    v.res[c] = sqrt(ss);
+  }
+  if (tid == 0) {
+    a.iters[s] = 0;
+    a.cycle_done[s] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lsq_step(LsqArgs a, int j) {
+  const int s = blockIdx.x;
+  if (a.active[s] == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0, tid = threadIdx.x;
+  c2* h = v.H + (int64_t)j * m0 * ldh;  // block column j, column-major, ld ldh
+  __shared__ double red[8];
+  __shared__ double sh_tau;
+  __shared__ int sh_ok;
+
+  // 1. previous steps' reflectors on rows [i m0, (i+2) m0)
+  for (int col = tid; col < m0; col += 256) {
+    for (int i = 0; i < j; ++i) {
+      const c2* Vi = v.Vh + (int64_t)i * m2 * m0;
+      const double* ti = v.tau + i * m0;
+      for (int c = 0; c < m0; ++c) apply_reflector(Vi + (int64_t)c * m2, ti[c], c, m0 + c + 1, h, i * m0, ldh, col);
+    }
+  }
+  __syncthreads();
+  // 2. Householder QR of the slab rows [j m0, (j+2) m0); the lower half is upper triangular
+  c2* Vj = v.Vh + (int64_t)j * m2 * m0;
+  double* tj = v.tau + j * m0;
+  const int base = j * m0;
+  for (int c = 0; c < m0; ++c) {
+    c2* vc = Vj + (int64_t)c * m2;
+    const int r0 = c, r1 = m0 + c + 1;  // support within the slab
+    double ss = 0.0;
+    for (int r = r0 + tid; r < r1; r += 256) ss += cabs2(h[base + r + (int64_t)c * ldh]);
+    ss = block_sum(ss, red);
+    const double nrm = sqrt(ss);
+    const c2 x0 = h[base + r0 + (int64_t)c * ldh];
+    double tau = 0.0;
+    c2 beta = x0;
+    if (nrm > 0.0) {
+      const double ax = sqrt(cabs2(x0));
+      const c2 ph = ax > 0.0 ? cscale(1.0 / ax, x0) : cmk(1.0, 0.0);
+      beta = cscale(-nrm, ph);
+      const c2 v0 = csub(x0, beta);
+      const double vn2 = ss - cabs2(x0) + cabs2(v0);
+      tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      for (int r = tid; r < m2; r += 256)
+        vc[r] = (r == r0) ? v0 : ((r > r0 && r < r1) ? h[base + r + (int64_t)c * ldh] : cmk(0.0, 0.0));
+    } else {
+      for (int r = tid; r < m2; r += 256) vc[r] = cmk(0.0, 0.0);
+    }
+    if (tid == 0) {
+      tj[c] = tau;
+      sh_tau = tau;
+    }
+    __syncthreads();
+    if (tid == 0) h[base + r0 + (int64_t)c * ldh] = (tau != 0.0) ? beta : x0;
+    for (int r = r0 + 1 + tid; r < r1; r += 256)
+      if (sh_tau != 0.0) h[base + r + (int64_t)c * ldh] = cmk(0.0, 0.0);
+    for (int col = c + 1 + tid; col < m0; col += 256) apply_reflector(vc, sh_tau, r0, r1, h, base, ldh, col);
+    __syncthreads();
+  }
+  // 3. the same reflectors on the right-hand side
+  for (int col = tid; col < m0; col += 256)
+    for (int c = 0; c < m0; ++c) apply_reflector(Vj + (int64_t)c * m2, tj[c], c, m0 + c + 1, v.g, base, ldh, col);
+  __syncthreads();
+  // 4. residual norms (last m0 rows) and the stopping rule
+  if (tid == 0) sh_ok = 1;
+  __syncthreads();
+  for (int col = tid; col < m0; col += 256) {
+    double ss = 0.0;
+    for (int r = 0; r < m0; ++r) ss += cabs2(v.g[(j + 1) * m0 + r + (int64_t)col * ldh]);
+    const double rn = sqrt(ss);
+    v.res[col] = rn;
+    if (!(rn <= v.tol[col])) atomicAnd(&sh_ok, 0);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.iters[s] = j + 1;
+    if (sh_ok) {
+      a.cycle_done[s] = 1;
+      a.active[s] = 0;
+    }
+  }
+}
+
+// y = R^{-1} g_top and u = Q_H [0; g_tail] for every shift that ran in this cycle.
+__global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
+  const int s = blockIdx.x;
+  const int J = a.iters[s];
+  if (J == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0, tid = threadIdx.x;
+  const int n = J * m0, ldy = a.k * m0;
+  for (int64_t idx = tid; idx < (int64_t)ldy * m0; idx += 256) {
+    const int r = (int)(idx % ldy), c = (int)(idx / ldy);
+    v.y[idx] = (r < n) ? v.g[r + (int64_t)c * ldh] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int c = n - 1; c >= 0; --c) {
+    const c2 d = v.H[c + (int64_t)c * ldh];
+    const bool ok = cabs2(d) > 1e-300;
+    for (int col = tid; col < m0; col += 256) {
+      c2* yc = v.y + c + (int64_t)col * ldy;
+      *yc = ok ? cdiv(*yc, d) : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < c * m0; idx += 256) {
+      const int r = idx % c, col = idx / c;
+      c2* yr = v.y + r + (int64_t)col * ldy;
+      *yr = csub(*yr, cmul(v.H[r + (int64_t)c * ldh], v.y[c + (int64_t)col * ldy]));
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < (int64_t)ldh * m0; idx += 256) {
+    const int r = (int)(idx % ldh), c = (int)(idx / ldh);
+    v.u[idx] = (r >= n && r < n + m0) ? v.g[idx] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int col = tid; col < m0; col += 256)
+    for (int i = J - 1; i >= 0; --i) {
+      const c2* Vi = v.Vh + (int64_t)i * m2 * m0;
+      const double* ti = v.tau + i * m0;
+      for (int c = m0 - 1; c >= 0; --c)
+        apply_reflector(Vi + (int64_t)c * m2, ti[c], c, m0 + c + 1, v.u, i * m0, ldh, col);
+    }
+}
+
+// Yq[s][b]: (2m0 x m0) real form for Q += Re(V_b (wf y_b)); Uc[s][b]: (2m0 x 2m0) real form of u_b.
+template <class T>
+__global__ void k_make_coefs(LsqArgs a, const double* __restrict__ wfac, int jmax, T* __restrict__ Yq,
+                             T* __restrict__ Uc, int complex_out) {
+  const int s = blockIdx.x, b = blockIdx.y;  // b in [0, jmax]
+  const int J = a.iters[s];
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, m2 = 2 * m0, ldh = a.ldh, ldy = a.k * m0;
+  const c2 wf = cmk(wfac[2 * s], wfac[2 * s + 1]);
+  if (b < jmax) {
+    const int ow = complex_out ? m2 : m0;
+    T* Y = Yq + ((int64_t)s * jmax + b) * m2 * ow;
+    for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) {
+      const int c = idx / m0, d = idx % m0;
+      const c2 yv = (b < J) ? cmul(wf, v.y[b * m0 + c + (int64_t)d * ldy]) : cmk(0.0, 0.0);
+      if (complex_out) {
+        store_realified(Y, m2, c, d, yv);
+      } else {
+        Y[(2 * c) * ow + d] = (T)yv.x;
+        Y[(2 * c + 1) * ow + d] = (T)(-yv.y);
+      }
+    }
+  }
+  T* U = Uc + ((int64_t)s * (jmax + 1) + b) * m2 * m2;
+  for (int idx = threadIdx.x; idx < m0 * m0; idx += blockDim.x) {
+    const int c = idx / m0, d = idx % m0;
+    const c2 uv = (b <= J) ? v.u[b * m0 + c + (int64_t)d * ldh] : cmk(0.0, 0.0);
+    store_realified(U, m2, c, d, uv);
+  }
+}
+
+// ------------------------------------------------------------ Rayleigh-Ritz
+// Cyclic Jacobi with the round-robin pair order on a symmetric m x m matrix
+// held in LDS (row-major, stride m); eigenvectors accumulate in global Vg.
+__device__ void jacobi_eig(double* a, int m, double* Vg, double* red) {
+  __shared__ double cs[64], sn[64];
+  __shared__ int pp[64], qq[64];
+  const int tid = threadIdx.x, half = m / 2;
+  for (int idx = tid; idx < m * m; idx += 256) Vg[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int r = idx / m, c = idx % m;
+      if (r != c) off += a[idx] * a[idx];
+      else dia += a[idx] * a[idx];
+    }
+    off = block_sum(off, red);
+    dia = block_sum(dia, red);
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < half) {
+        auto pos = [&](int t) { return t == 0 ? 0 : 1 + (t - 1 + round) % (m - 1); };
+        const int p = pos(tid), q = pos(m - 1 - tid);
+        const double apq = a[p * m + q], app = a[p * m + p], aqq = a[q * m + q];
+        double c = 1.0, sv = 0.0;
+        if (apq != 0.0) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sv = t * c;
+        }
+        cs[tid] = c;
+        sn[tid] = sv;
+        pp[tid] = p;
+        qq[tid] = q;
+      }
+      __syncthreads();
+      // A <- A J and V <- V J (columns p, q)
+      for (int idx = tid; idx < half * m; idx += 256) {
+        const int i = idx / m, r = idx % m;
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], sv = sn[i];
+        const double ap = a[r * m + p], aq = a[r * m + q];
+        a[r * m + p] = c * ap - sv * aq;
+        a[r * m + q] = sv * ap + c * aq;
+        const double vp = Vg[r * m + p], vq = Vg[r * m + q];
+        Vg[r * m + p] = c * vp - sv * vq;
+        Vg[r * m + q] = sv * vp + c * vq;
+      }
+      __syncthreads();
+      // A <- J^T A (rows p, q)
+      for (int idx = tid; idx < half * m; idx += 256) {
+        const int i = idx / m, col = idx % m;
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], sv = sn[i];
+        const double ap = a[p * m + col], aq = a[q * m + col];
+        a[p * m + col] = c * ap - sv * aq;
+        a[q * m + col] = sv * ap + c * aq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rr_small(int m0, const double* __restrict__ GA, const double* __restrict__ GB,
+                                                  double* __restrict__ lam, double* __restrict__ C,
+                                                  double* __restrict__ eta, double* __restrict__ work) {
+  extern __shared__ double sm[];  // m0 * m0
+  __shared__ double red[8];
+  __shared__ double dsc[128], th[128];
+  __shared__ int order[128];
+  const int tid = threadIdx.x, mm = m0 * m0;
+  double* U = work;
+  double* Tm = work + mm;
+  double* W = work + 2 * mm;
+  double* Ar = work + 3 * mm;
+  // 1. scaled, symmetrised B-Gram
+  for (int a = tid; a < m0; a += 256) {
+    const double d = GB[a * m0 + a];
+    dsc[a] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    sm[idx] = 0.5 * (GB[r * m0 + c] + GB[c * m0 + r]) * dsc[r] * dsc[c];
+  }
+  __syncthreads();
+  jacobi_eig(sm, m0, U, red);
+  // 2. floor tiny eigenvalues (SVQB), T = D U Theta^{-1/2}
+  double tmax = 0.0;
+  for (int a = tid; a < m0; a += 256) tmax = fmax(tmax, sm[a * m0 + a]);
+  tmax = block_max(tmax, red);
+  for (int a = tid; a < m0; a += 256) th[a] = 1.0 / sqrt(fmax(sm[a * m0 + a], 2.220446049250313e-16 * m0 * tmax));
+  __syncthreads();
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    Tm[idx] = dsc[r] * U[idx] * th[c];
+  }
+  __syncthreads();
+  // 3. Ar = T^T GA T (symmetrised), via W = GA T
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    double sum = 0.0;
+    for (int e = 0; e < m0; ++e) sum += 0.5 * (GA[r * m0 + e] + GA[e * m0 + r]) * Tm[e * m0 + c];
+    W[idx] = sum;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    double sum = 0.0;
+    for (int e = 0; e < m0; ++e) sum += Tm[e * m0 + r] * W[e * m0 + c];
+    Ar[idx] = sum;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    sm[idx] = 0.5 * (Ar[r * m0 + c] + Ar[c * m0 + r]);
+  }
+  __syncthreads();
+  jacobi_eig(sm, m0, W, red);
+  // 4. ascending order, C = T W(:, order), eta = 1/||c_l||
+  if (tid == 0) {
+    for (int i = 0; i < m0; ++i) order[i] = i;
+    for (int i = 1; i < m0; ++i) {  // insertion sort on the diagonal
+      const int oi = order[i];
+      const double key = sm[oi * m0 + oi];
+      int k = i - 1;
+      while (k >= 0 && sm[order[k] * m0 + order[k]] > key) {
+        order[k + 1] = order[k];
+        --k;
+      }
+      order[k + 1] = oi;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < mm; idx += 256) {
+    const int r = idx / m0, c = idx % m0;
+    const int oc = order[c];
+    double sum = 0.0;
+    for (int e = 0; e < m0; ++e) sum += Tm[r * m0 + e] * W[e * m0 + oc];
+    C[idx] = sum;
+  }
+  __syncthreads();
+  for (int c = tid; c < m0; c += 256) {
+    lam[c] = sm[order[c] * m0 + order[c]];
+    double ss = 0.0;
+    for (int r = 0; r < m0; ++r) ss += C[r * m0 + c] * C[r * m0 + c];
+    eta[c] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  }
+}
+
+__global__ void k_classify(ClassifyArgs a, const double* __restrict__ lam, const double* __restrict__ resid,
+                           const double* __restrict__ eta, int* __restrict__ flags, double* __restrict__ out) {
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  double rf_in = 0.0, rf_geo = 0.0, rf_all = 0.0, cnt = 0.0, cgeo = 0.0;
+  for (int j = tid; j < a.m0; j += 256) {
+    const double l = lam[j];
+    bool geo;
+    if (a.kind == IFEAST_CONTOUR_CIRCLE) {
+      geo = hypot(l - a.c_re, a.c_im) < a.r;
+    } else {
+      geo = (l > a.emin) && (l < a.emax);
+    }
+    // rho_hat(lambda) = sum_k w_k / (z_k - lambda)  (2 Re for half contours)
+    double rr = 0.0, ri = 0.0;
+    for (int k = 0; k < a.nc; ++k) {
+      const double zr = a.z[2 * k] - l, zi = a.z[2 * k + 1];
+      const double d = zr * zr + zi * zi;
+      const double wr = a.w[2 * k], wi = a.w[2 * k + 1];
+      rr += (wr * zr + wi * zi) / d;
+      ri += (wi * zr - wr * zi) / d;
+    }
+    const double rho = a.half ? 2.0 * fabs(rr) : hypot(rr, ri);
+    const bool ok = eta[j] >= a.tau * rho;
+    int f = 0;
+    if (geo && ok) f |= IFEAST_FLAG_INSIDE;
+    if (geo && !ok) f |= IFEAST_FLAG_SPURIOUS;
+    flags[j] = f;
+    const double rj = resid[j];
+    rf_all = fmax(rf_all, rj);
+    if (geo) {
+      rf_geo = fmax(rf_geo, rj);
+      cgeo += 1.0;
+    }
+    if (geo && ok) {
+      rf_in = fmax(rf_in, rj);
+      cnt += 1.0;
+    }
+  }
+  rf_in = block_max(rf_in, red);
+  rf_geo = block_max(rf_geo, red);
+  rf_all = block_max(rf_all, red);
+  cnt = block_sum(cnt, red);
+  cgeo = block_sum(cgeo, red);
+  if (tid == 0) {
+    out[0] = cnt > 0.0 ? rf_in : (cgeo > 0.0 ? rf_geo : rf_all);
+    out[1] = cnt;
+  }
+}
+
+// ----------------------------------------------------------- elementwise
+__global__ void k_col_sumsq(int64_t n, int m, const double* __restrict__ X, double* __restrict__ partial,
+                            int64_t rows_per_block) {
+  __shared__ double acc[256];
+  const int tid = threadIdx.x;
+  const int lanes = 256 / m;  // rows processed in parallel
+  const int c = tid % m, lr = tid / m;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+  double s = 0.0;
+  if (lr < lanes)
+    for (int64_t r = r0 + lr; r < r1; r += lanes) {
+      const double x = X[r * m + c];
+      s += x * x;
+    }
+  acc[tid] = (lr < lanes) ? s : 0.0;
+  __syncthreads();
+  if (tid < m) {
+    double t = 0.0;
+    for (int l = 0; l < lanes; ++l) t += acc[l * m + tid];
+    partial[(int64_t)blockIdx.x * m + tid] = t;
+  }
+}
+
+__global__ void k_col_sumsq_finish(int nb, int m, const double* __restrict__ partial, double* __restrict__ out,
+                                   int do_sqrt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += partial[(int64_t)b * m + c];
+  out[c] = do_sqrt ? sqrt(t) : t;
+}
+
+__global__ void k_scale_cols(int64_t n, int m, const double* __restrict__ X, const double* __restrict__ f,
+                             double* __restrict__ Y) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * m) return;
+  Y[idx] = X[idx] * f[idx % m];
+}
+
+__global__ void k_residual(int64_t n, int m, const double* __restrict__ AX, const double* __restrict__ BX,
+                           const double* __restrict__ lam, double* __restrict__ R) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * m) return;
+  R[idx] = AX[idx] - BX[idx] * lam[idx % m];
+}
+
+template <class T>
+__global__ void k_rhs_build(int64_t n, int m0, int ns, const double* __restrict__ R, const double* __restrict__ lam,
+                            const double* __restrict__ z, T* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ldc = ns * m0;
+  if (idx >= n * ldc) return;
+  const int64_t row = idx / ldc;
+  const int col = (int)(idx % ldc);
+  const int s = col / m0, j = col % m0;
+  // R_ij / (z_s - lambda_j)
+  const double ar = z[2 * s] - lam[j], ai = z[2 * s + 1];
+  const double d = ar * ar + ai * ai;
+  const double r = R[row * m0 + j];
+  out[2 * idx] = (T)(r * ar / d);
+  out[2 * idx + 1] = (T)(-r * ai / d);
+}
+
+__global__ void k_fill_zero(uint32_t* p, int64_t words) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < words) p[idx] = 0u;
+}
+
+inline unsigned nblocks(int64_t total, int bs = 256) { return (unsigned)((total + bs - 1) / bs); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <class T>
+void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, double shift_rel, const int* active,
+                          T* Tinv, cd* Racc, int accumulate, cd* work) {
+  IF_REQUIRE(m0 <= 128, "cholqr: m0 > 128");
+  hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, active, Tinv,
+                     reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
+  IF_HIP(hipGetLastError());
+}
+template void launch_cholqr_factor<float>(hipStream_t, int, int, const double*, double, const int*, float*, cd*, int,
+                                          cd*);
+template void launch_cholqr_factor<double>(hipStream_t, int, int, const double*, double, const int*, double*, cd*,
+                                           int, cd*);
+
+template <class T>
+void launch_cgs_combine(hipStream_t st, int ns, int ni, int m0, int j, int ldh, const double* G, const int* active,
+                        cd* H, T* Hr, int accumulate) {
+  const int64_t total = (int64_t)ns * ni * m0 * m0;
+  hipLaunchKernelGGL((k_cgs_combine<T>), dim3(nblocks(total)), dim3(256), 0, st, ns, ni, m0, j, ldh, G, active,
+                     reinterpret_cast<c2*>(H), Hr, accumulate);
+  IF_HIP(hipGetLastError());
+}
+template void launch_cgs_combine<float>(hipStream_t, int, int, int, int, int, const double*, const int*, cd*,
+                                        float*, int);
+template void launch_cgs_combine<double>(hipStream_t, int, int, int, int, int, const double*, const int*, cd*,
+                                         double*, int);
+
+void launch_store_subdiag(hipStream_t st, int ns, int m0, int j, int ldh, const int* active, const cd* Racc,
+                          cd* H) {
+  const int64_t total = (int64_t)ns * m0 * m0;
+  hipLaunchKernelGGL(k_store_subdiag, dim3(nblocks(total)), dim3(256), 0, st, ns, m0, j, ldh, active,
+                     reinterpret_cast<const c2*>(Racc), reinterpret_cast<c2*>(H));
+  IF_HIP(hipGetLastError());
+}
+
+void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S) {
+  hipLaunchKernelGGL(k_lsq_init, dim3(a.ns), dim3(256), 0, st, a, reinterpret_cast<const c2*>(S));
+  IF_HIP(hipGetLastError());
+}
+void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
+  hipLaunchKernelGGL(k_lsq_step, dim3(a.ns), dim3(256), 0, st, a, j);
+  IF_HIP(hipGetLastError());
+}
+void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
+  hipLaunchKernelGGL(k_lsq_finish, dim3(a.ns), dim3(256), 0, st, a);
+  IF_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_make_coefs(hipStream_t st, const LsqArgs& a, const double* wfac, int jmax, T* Yq, T* Uc,
+                       int complex_out) {
+  hipLaunchKernelGGL((k_make_coefs<T>), dim3(a.ns, jmax + 1), dim3(256), 0, st, a, wfac, jmax, Yq, Uc, complex_out);
+  IF_HIP(hipGetLastError());
+}
+template void launch_make_coefs<float>(hipStream_t, const LsqArgs&, const double*, int, float*, float*, int);
+template void launch_make_coefs<double>(hipStream_t, const LsqArgs&, const double*, int, double*, double*, int);
+
+void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB, double* lam, double* C, double* eta,
+                     double* work) {
+  IF_REQUIRE(m0 <= 128 && m0 % 2 == 0, "rayleigh-ritz: m0 must be even and <= 128");
+  const size_t lds = (size_t)m0 * m0 * sizeof(double);
+  if (lds > 64 * 1024)
+    IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rr_small), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(256), lds, st, m0, GA, GB, lam, C, eta, work);
+  IF_HIP(hipGetLastError());
+}
+
+void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* resid,
+                     const double* eta, int* flags, double* out) {
+  hipLaunchKernelGGL(k_classify, dim3(1), dim3(256), 0, st, a, lam, resid, eta, flags, out);
+  IF_HIP(hipGetLastError());
+}
+
+int col_sumsq_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)); }
+
+void launch_col_sumsq(hipStream_t st, int64_t n, int m, const double* X, double* out, double* partial) {
+  IF_REQUIRE(m <= 256, "col_sumsq: m > 256");
+  const int nb = col_sumsq_blocks(n);
+  const int64_t rpb = (n + nb - 1) / nb;
+  hipLaunchKernelGGL(k_col_sumsq, dim3(nb), dim3(256), 0, st, n, m, X, partial, rpb);
+  IF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_col_sumsq_finish, dim3(nblocks(m)), dim3(256), 0, st, nb, m, partial, out, 1);
+  IF_HIP(hipGetLastError());
+}
+
+void launch_col_sumsq_finish(hipStream_t st, int nb, int m, const double* partial, double* out, int do_sqrt) {
+  hipLaunchKernelGGL(k_col_sumsq_finish, dim3(nblocks(m)), dim3(256), 0, st, nb, m, partial, out, do_sqrt);
+  IF_HIP(hipGetLastError());
+}
+
+void launch_scale_cols(hipStream_t st, int64_t n, int m, const double* X, const double* f, double* Y) {
+  hipLaunchKernelGGL(k_scale_cols, dim3(nblocks(n * m)), dim3(256), 0, st, n, m, X, f, Y);
+  IF_HIP(hipGetLastError());
+}
+
+void launch_residual(hipStream_t st, int64_t n, int m, const double* AX, const double* BX, const double* lam,
+                     double* R) {
+  hipLaunchKernelGGL(k_residual, dim3(nblocks(n * m)), dim3(256), 0, st, n, m, AX, BX, lam, R);
+  IF_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_rhs_build(hipStream_t st, int64_t n, int m0, int ns, const double* R, const double* lam, const double* z,
+                      T* out) {
+  hipLaunchKernelGGL((k_rhs_build<T>), dim3(nblocks(n * ns * m0)), dim3(256), 0, st, n, m0, ns, R, lam, z, out);
+  IF_HIP(hipGetLastError());
+}
+template void launch_rhs_build<float>(hipStream_t, int64_t, int, int, const double*, const double*, const double*,
+                                      float*);
+template void launch_rhs_build<double>(hipStream_t, int64_t, int, int, const double*, const double*, const double*,
+                                       double*);
+
+void launch_fill_zero(hipStream_t st, void* p, size_t bytes) {
+  IF_REQUIRE(bytes % 4 == 0, "fill_zero: size must be a multiple of 4");
+  const int64_t words = (int64_t)(bytes / 4);
+  if (words == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3(nblocks(words)), dim3(256), 0, st, static_cast<uint32_t*>(p), words);
+  IF_HIP(hipGetLastError());
+}
+
+}  // namespace ifeast

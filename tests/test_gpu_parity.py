@@ -1,0 +1,338 @@
+"""GPU parity: every step of the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: FP64 steps agree with the oracle to rounding amplified by the
+conditioning of the small problems (rtol 1e-9 on the filtered block at
+config-1 size); complex-FP32 inner solves to ~1e-5 relative (single
+precision with a few hundred accumulated operations); converged eigenpairs
+of both paths to the tolerance the method states (relative eigenvalue error
+<= 1e-10, residual <= tol).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.quadrature import contour_nodes
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_cuda):
+    import paper_1706_00692_amd as pk
+
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def _cplx(torch, a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _rand_block(n, w, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, w)) + 1j * rng.standard_normal((n, w))
+
+
+# ------------------------------------------------------------------ SpMM
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["lap2d", "gen27_ragged"])
+def test_spmm_shifted_parity(ctx, torch_cuda, prec, case):
+    import paper_1706_00692_amd as pk
+
+    torch = torch_cuda
+    if case == "lap2d":
+        A, B, m0, ns = W.laplacian_2d(20), None, 16, 8
+    else:
+        A, B, m0, ns = W.spd27(7, 11), W.mass27(7, 12), 16, 3  # n = 343: ragged row tiles
+    z = np.array([0.3 + 0.2j, 1.1 + 0.05j, -0.4 + 1.5j, 0.7 + 0.01j, 2 + 3j, 0.65 + 0.15j, 0.1 + 0.9j, 5 + 0.5j])[:ns]
+    V = _rand_block(A.n, ns * m0, 7)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    Vd = _cplx(torch, V, dt)
+    Wd = torch.zeros_like(Vd)
+    Am = ctx.matrix(A)
+    Bm = None if B is None else ctx.matrix(B)
+    ctx.spmm_shifted(Am, Bm, pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED, z, m0, Vd, Wd)
+    torch.cuda.synchronize()
+    got = Wd.cpu().numpy()
+    As = A.to_scipy()
+    Bs = None if B is None else B.to_scipy()
+    for s in range(ns):
+        sl = slice(s * m0, (s + 1) * m0)
+        want = O.shifted_operator(As, Bs, z[s])(V[:, sl])
+        scale = np.abs(want).max()
+        tol = 1e-14 if prec == "fp64" else 2e-6
+        assert np.abs(got[:, sl] - want).max() <= tol * scale * 10, (s, np.abs(got[:, sl] - want).max() / scale)
+
+
+def test_spmm_full_size_sampled(ctx, torch_cuda):
+    """64^3 Laplacian + potential, 8 shifts x 80 columns, complex FP32: sampled rows against the oracle."""
+    import paper_1706_00692_amd as pk
+
+    torch = torch_cuda
+    N, m0, ns = 64, 80, 8
+    A = W.laplacian_3d(N, W.random_potential(N ** 3, 1002))
+    z = 1.0 + np.exp(1j * np.linspace(0.1, 3.0, ns))
+    g = torch.Generator(device="cuda").manual_seed(5)
+    Vd = torch.randn((A.n, ns * m0), dtype=torch.complex64, device="cuda", generator=g)
+    Wd = torch.empty_like(Vd)
+    Am = ctx.matrix(A)
+    ctx.spmm_shifted(Am, None, pk.PREC_MIXED, z, m0, Vd, Wd)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([np.random.default_rng(3).integers(0, A.n, 200), [0, A.n - 1, 4095, 4096]]))
+    need = np.unique(np.concatenate([A.colind[A.rowptr[r]:A.rowptr[r + 1]] for r in rows] + [rows]))
+    Vn = Vd[torch.from_numpy(need).cuda()].cpu().numpy().astype(np.complex128)
+    pos = {int(c): i for i, c in enumerate(need)}
+    Wn = Wd[torch.from_numpy(rows).cuda()].cpu().numpy()
+    for t, r in enumerate(rows):
+        acc = np.zeros(ns * m0, dtype=complex)
+        for e in range(A.rowptr[r], A.rowptr[r + 1]):
+            acc += np.float32(A.val[e]) * Vn[pos[int(A.colind[e])]]
+        zr = np.repeat(z.astype(np.complex64).astype(np.complex128), m0)
+        want = zr * Vn[pos[int(r)]] - acc
+        assert np.abs(Wn[t] - want).max() <= 1e-5 * max(1.0, np.abs(want).max())
+
+
+# ------------------------------------------------------------- filter step
+def _first_iterate(prob):
+    lam, X, AX, BX, _ = O.rayleigh_ritz(prob.A.to_scipy(), None if prob.B is None else prob.B.to_scipy(), prob.x0())
+    R, r = O.residuals(AX, BX, lam)
+    return lam, X, R, r
+
+
+def _oracle_filter(prob, lam, X, R, k, cycles):
+    A = prob.A.to_scipy()
+    B = None if prob.B is None else prob.B.to_scipy()
+    z, w, half = contour_nodes(prob.contour)
+    D = []
+    for zk in z:
+        rhs = R / (zk - lam)[None, :]
+        if cycles == 1:
+            Dk, _ = O.block_gmres(O.shifted_operator(A, B, zk), rhs, k, 0.0)
+        else:
+            from oracle.krylov import block_gmres_restarted
+
+            Dk, _ = block_gmres_restarted(O.shifted_operator(A, B, zk), rhs, k, 0.0, cycles)
+        D.append(Dk)
+    return O.quad_accumulate(X, lam, D, z, w, half)
+
+
+def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles):
+    import paper_1706_00692_amd as pk
+
+    Am = ctx.matrix(prob.A)
+    Bm = None if prob.B is None else ctx.matrix(prob.B)
+    p = pk.params_struct(prob.m0, max_outer=1, max_inner=k, max_cycles=cycles, alpha=0.0, tol=1e-9,
+                         precision=prec)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    ld = torch.from_numpy(np.ascontiguousarray(lam)).cuda()
+    Rd = torch.from_numpy(np.ascontiguousarray(R)).cuda()
+    Qd = torch.zeros_like(Xd)
+    iters = ctx.filter(Am, Bm, prob.contour, p, Xd, ld, Rd, 1.0, Qd)
+    torch.cuda.synchronize()
+    return Qd.cpu().numpy(), iters
+
+
+@pytest.mark.parametrize("cycles", [1, 3])
+def test_filter_parity_fp64(ctx, torch_cuda, cycles):
+    import paper_1706_00692_amd as pk
+
+    prob = W.config1()
+    lam, X, R, r = _first_iterate(prob)
+    want = _oracle_filter(prob, lam, X, R, prob.max_inner, cycles)
+    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, prob.max_inner, cycles)
+    assert list(iters) == [prob.max_inner * cycles] * 8
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= 1e-9, err
+
+
+def test_filter_parity_mixed(ctx, torch_cuda):
+    import paper_1706_00692_amd as pk
+
+    prob = W.config1()
+    lam, X, R, r = _first_iterate(prob)
+    want = _oracle_filter(prob, lam, X, R, prob.max_inner, 1)
+    got, _ = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_MIXED, prob.max_inner, 1)
+    # the FP32 part is the correction Q - X rho_hat(Lambda)
+    from oracle.quadrature import rho_hat
+
+    z, w, half = contour_nodes(prob.contour)
+    base = X * rho_hat(lam, z, w, half)[None, :]
+    err = np.abs(got - want).max() / np.abs(want - base).max()
+    assert err <= 1e-4, err
+
+
+def test_filter_parity_generalized_ragged(ctx, torch_cuda):
+    import paper_1706_00692_amd as pk
+
+    prob = W.config3_small(N=7, m0=16, emin=0.0, emax=1.0)
+    lam_all = np.sort(np.real(O.dense_reference(prob.A, prob.B, {"kind": "half", "emin": -1, "emax": 1e9})[2]))
+    prob.contour = dict(prob.contour, emin=0.5 * (lam_all[1] + lam_all[2]), emax=0.5 * (lam_all[8] + lam_all[9]))
+    lam, X, R, r = _first_iterate(prob)
+    want = _oracle_filter(prob, lam, X, R, 3, 1)
+    got, _ = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, 3, 1)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= 1e-9, err
+
+
+# --------------------------------------------------------- Rayleigh-Ritz
+@pytest.mark.parametrize("gen", [False, True])
+def test_rayleigh_ritz_parity(ctx, torch_cuda, gen):
+    torch = torch_cuda
+    if gen:
+        A, B = W.spd27(6, 21), W.mass27(6, 22)
+    else:
+        A, B = W.laplacian_3d(9, W.random_potential(729, 5)), None  # n = 729, ragged
+    m0 = 32
+    rng = np.random.default_rng(9)
+    Q = rng.standard_normal((A.n, m0))
+    lam, X, AX, BX, C = O.rayleigh_ritz(A.to_scipy(), None if B is None else B.to_scipy(), Q)
+    R, r = O.residuals(AX, BX, lam)
+    Am = ctx.matrix(A)
+    Bm = None if B is None else ctx.matrix(B)
+    Qd = torch.from_numpy(Q).cuda()
+    out = {k: torch.zeros(v, dtype=torch.float64, device="cuda") for k, v in
+           dict(lam=m0, X=(A.n, m0), R=(A.n, m0), resid=m0, eta=m0).items()}
+    ctx.rayleigh_ritz(Am, Bm, Qd, out["lam"], out["X"], out["R"], out["resid"], out["eta"])
+    torch.cuda.synchronize()
+    gl, gX, gr = out["lam"].cpu().numpy(), out["X"].cpu().numpy(), out["resid"].cpu().numpy()
+    assert np.allclose(gl, lam, rtol=1e-11, atol=1e-12 * np.abs(lam).max())
+    # eigenvectors up to sign (the Ritz values of random Q are simple)
+    sgn = np.sign(np.sum(gX * X, axis=0))
+    assert np.abs(gX * sgn[None, :] - X).max() <= 1e-8 * np.abs(X).max()
+    assert np.allclose(gr, r, rtol=1e-8, atol=1e-12)
+    eta = 1.0 / np.linalg.norm(C, axis=0)
+    assert np.allclose(out["eta"].cpu().numpy(), eta, rtol=1e-8)
+
+
+# ------------------------------------------------------------ full solves
+def _check_against_oracle(prob, res, ref, rel=1e-10):
+    assert res.converged and ref.converged
+    assert res.m == ref.m
+    got, want = np.sort(res.lam_in), np.sort(ref.lam_in)
+    assert np.all(np.abs(got - want) <= rel * np.abs(want)), np.abs(got - want) / np.abs(want)
+    assert res.resid[: res.m].max() <= prob.tol
+    # invariant subspace of the eigenvalues inside: compare as subspaces (clusters are degenerate)
+    Xg, Xr = res.X_in, ref.X_in
+    Bs = None if prob.B is None else prob.B.to_scipy()
+    proj = Xg @ (Xg.T @ (Xr if Bs is None else Bs @ Xr))  # B-orthogonal projection onto span(Xg)
+    sines = np.linalg.norm(Xr - proj, axis=0)
+    assert sines.max() <= 1e-7, sines.max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_config1(ctx, prec):
+    import paper_1706_00692_amd as pk
+
+    prob = W.config1()
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED)
+    ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner, prob.alpha, prob.tol, prob.x0(),
+                   prob.max_outer, max_cycles=prob.max_cycles, inner_rule=prob.inner_rule, tau=prob.tau)
+    _check_against_oracle(prob, res, ref)
+    mu = 2 - 2 * np.cos(np.arange(1, 21) * np.pi / 21)
+    exact = np.sort((mu[:, None] + mu[None, :]).ravel())
+    exact = exact[(exact > 0.5) & (exact < 0.8)]
+    assert np.allclose(np.sort(res.lam_in), exact, rtol=1e-10, atol=0)
+    assert res.status == 0
+
+
+def test_solve_ragged_3d_with_potential(ctx):
+    import paper_1706_00692_amd as pk
+
+    N = 9
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    emin, emax = 0.5 * (lam_all[3] + lam_all[4]), 0.5 * (lam_all[15] + lam_all[16])
+    prob = W.config2_small(N=N, m0=32, emin=emin, emax=emax)
+    res = ctx.solve_problem(prob, precision=pk.PREC_MIXED)
+    ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner, prob.alpha, prob.tol, prob.x0(),
+                   prob.max_outer, max_cycles=prob.max_cycles, inner_rule=prob.inner_rule, tau=prob.tau)
+    _check_against_oracle(prob, res, ref)
+    assert np.allclose(np.sort(res.lam_in), lam_all[4:16], rtol=1e-10, atol=0)
+
+
+def test_solve_generalized_small(ctx):
+    import paper_1706_00692_amd as pk
+
+    prob = W.config3_small(N=6, m0=16)
+    lam_all = np.sort(np.real(O.dense_reference(prob.A, prob.B, {"kind": "half", "emin": -1, "emax": 1e9})[2]))
+    prob.contour = dict(prob.contour, emin=0.5 * (lam_all[1] + lam_all[2]), emax=0.5 * (lam_all[8] + lam_all[9]))
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64)
+    assert res.converged and res.m == 7
+    assert np.allclose(np.sort(res.lam_in), lam_all[2:9], rtol=1e-10, atol=0)
+    B = prob.B.to_scipy()
+    assert np.allclose(res.X_in.T @ (B @ res.X_in), np.eye(7), atol=1e-9)
+
+
+# ------------------------------------------------------- status and errors
+def test_not_converged_and_m0_too_small(ctx):
+    import paper_1706_00692_amd as pk
+
+    prob = W.config1()
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64, max_outer=1)
+    assert res.status == 1 and not res.converged and res.outer_iters == 1
+    prob.contour = dict(prob.contour, emin=0.5, emax=1.2)  # 26 eigenvalues, m0 = 16
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64, max_outer=3)
+    assert res.status in (1, 2)
+    assert res.m <= prob.m0
+
+
+def test_invalid_inputs_rejected(ctx):
+    import paper_1706_00692_amd as pk
+
+    A = W.laplacian_2d(6)
+    bad = W.CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    bad.colind[[0, 1]] = bad.colind[[1, 0]]  # unsorted row
+    with pytest.raises(pk.IFeastError) as e:
+        ctx.matrix(bad)
+    assert e.value.status == -1
+    nan = W.CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    nan.val[3] = np.nan
+    with pytest.raises(pk.IFeastError):
+        ctx.matrix(nan)
+    oob = W.CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    oob.colind[-1] = A.n
+    with pytest.raises(pk.IFeastError):
+        ctx.matrix(oob)
+    prob = W.config1()
+    with pytest.raises(pk.IFeastError) as e:
+        ctx.solve_problem(prob, m0=24)
+    assert e.value.status == -1
+    with pytest.raises(pk.IFeastError) as e:
+        ctx.solve_problem(prob, problem=1)
+    assert e.value.status == -7
+
+
+# ------------------------------------------------------------- serving
+def test_serving_alone_vs_mix(ctx):
+    import paper_1706_00692_amd as pk
+
+    probs = [W.config1()]
+    for N, lo, hi, m0 in [(9, 4, 16, 32), (8, 2, 10, 16)]:
+        lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+        probs.append(W.config2_small(N=N, m0=m0, emin=0.5 * (lam_all[lo - 1] + lam_all[lo]),
+                                     emax=0.5 * (lam_all[hi - 1] + lam_all[hi])))
+    alone = [ctx.solve_problem(p, precision=pk.PREC_MIXED) for p in probs]
+    tickets = []
+    for p in probs:
+        params = pk.params_struct(p.m0, p.max_outer, p.max_inner, p.max_cycles, p.alpha, p.tol, p.tau,
+                                  pk.PREC_MIXED)
+        tickets.append(ctx.submit(p.A, p.B, p.contour, params, p.x0()))
+    for p, t, a in zip(probs, tickets, alone):
+        r = ctx.wait(t, p.n, p.m0, p.max_outer, p.contour["nc"])
+        assert r.converged and r.m == a.m
+        assert np.all(np.abs(r.lam_in - a.lam_in) <= 1e-10 * np.abs(a.lam_in))
+        assert r.resid[: r.m].max() <= p.tol
+        assert r.latency > 0
+    with pytest.raises(pk.IFeastError) as e:
+        ctx.poll(987654321)
+    assert e.value.status == -6

@@ -1,0 +1,191 @@
+"""IFEAST benchmark on one MI355X.
+
+A step is one full IFEAST solve (Algorithm 2: initial Rayleigh-Ritz, outer
+iterations of batched restarted block-GMRES shifted solves, quadrature sum,
+Rayleigh-Ritz and residuals until ||R_F|| <= tol) with A already resident in
+HBM.  The headline value is converged eigenpairs per second of the mixed
+precision path (complex FP32 inner solves, FP64 outer iteration); the FP64
+path is timed beside it on the same inputs.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import workloads as W
+
+    if name == "c1":
+        return W.config1(), "lap2d_20x20_n400_m0_16_gl8_k4"
+    if name == "c2":
+        return W.config2(64), "lap3d_pot_64^3_n262144_m0_80_gl8_k8"
+    if name.startswith("c2_"):
+        N = int(name.split("_")[1])
+        return W.config2(N), f"lap3d_pot_{N}^3_m0_80_gl8_k8"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def spmm_roofline(ctx, pk, torch, Am, prob, reps=20):
+    """Average duration of the batched shifted SpMM (the path's HBM-bound kernel) at the solve's shape."""
+    ns = prob.contour["nc"]
+    m0 = prob.m0
+    n = prob.A.n
+    # shift values only set the arithmetic, not the traffic: any complex numbers do
+    z = 1.0 + 0.05j * np.arange(1, ns + 1)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    V = torch.randn((n, ns * m0), dtype=torch.complex64, device="cuda", generator=g)
+    Wt = torch.empty_like(V)
+    stream = torch.cuda.current_stream()
+    ctx.spmm_shifted(Am, None, pk.PREC_MIXED, z, m0, V, Wt)  # warm
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        ctx.spmm_shifted(Am, None, pk.PREC_MIXED, z, m0, V, Wt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    nnz = prob.A.nnz
+    # algorithmic bytes: CSR (int32 rowptr + int32 colind + FP32 values) + V read once + W written once
+    bytes_ = (n + 1) * 4 + nnz * 8 + 2 * n * ns * m0 * 8
+    return sec, bytes_
+
+
+def cpu_baseline(prob, gpu_res, budget_s=20.0):
+    """Oracle timed on a bounded sample: whole GMRES(k) cycles of single shifts at full size,
+    extrapolated to the cycles the GPU solve ran."""
+    import threadpoolctl
+    import oracle as O
+    from oracle.quadrature import contour_nodes
+
+    A = prob.A.to_scipy()
+    z, w, half = contour_nodes(prob.contour)
+    lam, X, AX, BX, _ = O.rayleigh_ritz(A, None, prob.x0())
+    R, r = O.residuals(AX, BX, lam)
+    t0 = time.perf_counter()
+    cycles = 0
+    s = 0
+    while time.perf_counter() - t0 < budget_s and cycles < 8:
+        zk = z[s % len(z)]
+        O.block_gmres(O.shifted_operator(A, None, zk), R / (zk - lam)[None, :], prob.max_inner, 0.0)
+        cycles += 1
+        s += 1
+    t_cycle = (time.perf_counter() - t0) / cycles
+    total_iters = int(np.sum(gpu_res.inner_hist))
+    total_cycles = max(1.0, total_iters / prob.max_inner)
+    est = gpu_res.m / (t_cycle * total_cycles)
+    info = threadpoolctl.threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    return {"value": est, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{cycles} full-size block-GMRES({prob.max_inner}) cycles of single shifts "
+                      f"({t_cycle:.2f} s each), extrapolated to the {total_cycles:.0f} shift-cycles the GPU solve ran"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); see the design notes for how the "
+              "path shards across GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1706_00692_amd as pk
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    prob, wname = workload(args.workload)
+    log(f"workload {wname}: n={prob.A.n} nnz={prob.A.nnz} m0={prob.m0} nc={prob.contour['nc']} "
+        f"k={prob.max_inner} interval=({prob.contour['emin']}, {prob.contour['emax']})")
+    ctx = pk.Context(0)
+    ctx._use_torch_stream()
+    Am = ctx.matrix(prob.A)
+
+    def solve(prec):
+        t = time.perf_counter()
+        r = ctx.solve_problem(prob, precision=prec, resident=(Am, None))
+        r.extra["wall"] = time.perf_counter() - t
+        return r
+
+    for i in range(args.warmup):
+        r = solve(pk.PREC_MIXED)
+        log(f"warmup {i}: converged={r.converged} m={r.m} outer={r.outer_iters} rf={r.max_resid:.2e} "
+            f"time={r.solve_seconds:.3f}s")
+    torch.cuda.synchronize()
+    lat = []
+    res = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        r = solve(pk.PREC_MIXED)
+        lat.append(time.perf_counter() - ts)
+        res.append(r)
+        log(f"step {i}: converged={r.converged} m={r.m} outer={r.outer_iters} rf={r.max_resid:.2e} "
+            f"seq_matvec={r.seq_matvec} time={r.solve_seconds:.3f}s")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ok = all(r.converged and r.resid[: r.m].max() <= prob.tol for r in res)
+    pairs = sum(r.m for r in res) if ok else 0
+    value = pairs / total
+
+    out = {"metric": "eigenpairs/s at resid<=1e-9 (mixed FP32-inner/FP64-outer IFEAST)", "value": value,
+           "unit": "eigenpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64-inner/f64-outer", "data": "synthetic",
+           "config": {"workload": wname, "n": prob.A.n, "nnz": prob.A.nnz, "m0": prob.m0,
+                      "nc": prob.contour["nc"], "k": prob.max_inner, "max_cycles": prob.max_cycles,
+                      "interval": [prob.contour["emin"], prob.contour["emax"]], "tol": prob.tol,
+                      "eigenpairs": res[0].m, "outer_iters": res[0].outer_iters,
+                      "seq_matvec": res[0].seq_matvec, "total_matvec": res[0].total_matvec},
+           "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+           "converged": ok}
+
+    if not args.no_fp64:
+        r64 = solve(pk.PREC_FP64)
+        log(f"fp64: converged={r64.converged} m={r64.m} outer={r64.outer_iters} time={r64.extra['wall']:.3f}s")
+        ok64 = r64.converged and r64.resid[: r64.m].max() <= prob.tol
+        out["fp64"] = {"eigenpairs_per_s": (r64.m / r64.extra["wall"]) if ok64 else 0.0,
+                       "seconds": r64.extra["wall"], "outer_iters": r64.outer_iters, "converged": bool(ok64)}
+        if ok64 and ok:
+            a, b = np.sort(res[0].lam_in), np.sort(r64.lam_in)
+            if len(a) == len(b):
+                out["mixed_vs_fp64_max_rel_eig_diff"] = float(np.max(np.abs(a - b) / np.abs(b)))
+
+    sec, bytes_ = spmm_roofline(ctx, pk, torch, Am, prob)
+    ach = bytes_ / sec / 1e9
+    out["roofline"] = {"kernel": "spmm_shifted (complex FP32, all shifts)", "bound": "hbm", "achieved": ach,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                       "avg_launch_us": sec * 1e6, "algorithmic_bytes": bytes_}
+    log(f"spmm: {sec*1e6:.1f} us/launch, {ach:.0f} GB/s ({100*ach/HBM_PEAK_GBS:.1f}% of HBM peak)")
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, res[0])
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

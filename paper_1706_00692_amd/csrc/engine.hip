@@ -17,6 +17,8 @@
 #include <cstring>
 #include <numeric>
 #include <random>
+#include <cstdio>
+#include <cstdlib>
 
 namespace ifeast {
 
@@ -178,10 +180,12 @@ Layout layout(const Shape& s) {
   L.y = ns * k * m0 * m0 * 16;
   L.flags = 8 * 64 * 4;
   L.tol = ns * m0 * 8 * 2;
-  const size_t gp_inner = ts == 4 ? gram_partial_bytes<float>(s.n, (int)m2, (int)m2, (int)(ns * k))
-                                  : gram_partial_bytes<double>(s.n, (int)m2, (int)m2, (int)(ns * k));
-  const size_t gp_rr = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
-  L.gpart = std::max(gp_inner, gp_rr);
+  // the split count depends on the item count: take the largest over every step's Gram
+  size_t gp = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
+  for (size_t items = ns; items <= ns * k; items += ns)
+    gp = std::max(gp, ts == 4 ? gram_partial_bytes<float>(s.n, (int)m2, (int)m2, (int)items)
+                              : gram_partial_bytes<double>(s.n, (int)m2, (int)m2, (int)items));
+  L.gpart = gp;
   L.gred = std::max(ns * k * m2 * m2, 2 * m0 * m0) * 8;
   L.Hr = ns * k * m2 * m2 * ts;
   L.Tinv = ns * m2 * m2 * ts;
@@ -203,7 +207,57 @@ size_t total(const Layout& L) {
 
 uint64_t workspace_bytes(const Shape& s) { return (uint64_t)total(layout(s)); }
 
+namespace {
+template <class T>
+__global__ void k_scan(const T* __restrict__ p, int64_t count, unsigned int* __restrict__ bad, double* __restrict__ mx) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  unsigned int b = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)p[i];
+    if (!isfinite(v)) ++b;
+    else m = fmax(m, fabs(v));
+  }
+  sm[threadIdx.x] = m;
+  if (b) atomicAdd(bad, b);
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mx[blockIdx.x] = sm[0];
+}
+}  // namespace
+
+// Stage-by-stage finiteness scan of device buffers (IFEAST_DEBUG=1 only).
+struct DebugScan {
+  bool on = false;
+  DevBuf buf;
+  explicit DebugScan() {
+    const char* e = getenv("IFEAST_DEBUG");
+    on = e && e[0] == '1';
+    if (on) buf = DevBuf(64 * 8 + 8);
+  }
+  template <class T>
+  void operator()(hipStream_t st, const char* what, const T* p, int64_t count, int a = -1, int b = -1) {
+    if (!on || count <= 0) return;
+    unsigned int* bad = reinterpret_cast<unsigned int*>(buf.as<char>() + 64 * 8);
+    IF_HIP(hipMemsetAsync(bad, 0, 4, st));
+    hipLaunchKernelGGL((k_scan<T>), dim3(64), dim3(256), 0, st, p, count, bad, buf.as<double>());
+    IF_HIP(hipGetLastError());
+    double mx[64];
+    unsigned int nb = 0;
+    IF_HIP(hipMemcpyAsync(mx, buf.p, 64 * 8, hipMemcpyDeviceToHost, st));
+    IF_HIP(hipMemcpyAsync(&nb, bad, 4, hipMemcpyDeviceToHost, st));
+    IF_HIP(hipStreamSynchronize(st));
+    double m = 0.0;
+    for (double v : mx) m = std::max(m, v);
+    fprintf(stderr, "[ifeast-debug] %-14s a=%d b=%d max|x|=%.3e nonfinite=%u\n", what, a, b, m, nb);
+  }
+};
+
 struct Engine::Impl {
+  DebugScan dbg;
   Shape sh;
   hipStream_t st;
   Layout L;
@@ -392,6 +446,7 @@ struct Engine::Impl {
     // Q = X rho_hat(Lambda); start blocks R (z_s - Lambda)^{-1}
     launch_scale_cols(st, n, m0, Xd, rhod, Qd);
     launch_rhs_build<T>(st, n, m0, ns, Rd, lamd, zsD.as<double>(), t1);
+    dbg(st, "rhs", t1, n * ldc * 2);
     std::vector<int> run(ns, 1), total_iters(ns, 0);
     LsqArgs la = lsq_args();
     for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
@@ -399,12 +454,15 @@ struct Engine::Impl {
       h2d(d_active, run.data(), ns * sizeof(int));
       // V_1 S = qr(start block)
       cholqr2<T>(t1, t2, Vb, d_run);
+      dbg(st, "V0", Vb, n * ldc * 2, cyc);
+      dbg(st, "S", reinterpret_cast<double*>(Racc.p), (int64_t)ns * m0 * m0 * 2, cyc);
       launch_lsq_init(st, la, Racc.as<cd>());
       int jdone = 0;
       for (int j = 0; j < k; ++j) {
         T* Vj = Vb + (int64_t)j * blk;
         // W = z_s V_j - A V_j (all shifts in one launch)
         launch_spmm_shifted<T>(st, A, B, ns, m0, zsT.as<T>(), d_active, Vj, t1);
+        dbg(st, "W=MV", t1, n * ldc * 2, cyc, j);
         // CGS2 against V_0..V_j
         for (int pass = 0; pass < 2; ++pass) {
           GramArgs gg{n, m2, m2, ns, j + 1, Vb, 2 * ldc, m2, blk, t1, 2 * ldc, m2, 0, d_active, gred.as<double>()};
@@ -415,19 +473,27 @@ struct Engine::Impl {
           launch_apply<T, T>(st, ap);
         }
         // V_{j+1} H_{j+1,j} = qr(W)
+        dbg(st, "W_cgs", t1, n * ldc * 2, cyc, j);
         cholqr2<T>(t1, t2, Vb + (int64_t)(j + 1) * blk, d_active);
+        dbg(st, "V_j+1", Vb + (int64_t)(j + 1) * blk, n * ldc * 2, cyc, j);
+        dbg(st, "Hsub", reinterpret_cast<double*>(Racc.p), (int64_t)ns * m0 * m0 * 2, cyc, j);
         launch_store_subdiag(st, ns, m0, j, ldh, d_active, Racc.as<cd>(), H.as<cd>());
         launch_lsq_step(st, la, j);
+        dbg(st, "lsq_res", la.res, (int64_t)ns * m0, cyc, j);
         jdone = j + 1;
         const std::vector<int> act = d2h_ints(d_active, ns);
         if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) break;
       }
       launch_lsq_finish(st, la);
+      dbg(st, "y", reinterpret_cast<double*>(y.p), (int64_t)ns * k * m0 * m0 * 2, cyc);
+      dbg(st, "u", reinterpret_cast<double*>(u.p), (int64_t)ns * ldh * m0 * 2, cyc);
       launch_make_coefs<T>(st, la, wsD.as<double>(), jdone, Yq.as<T>(), Uc.as<T>(), 0);
+      dbg(st, "Yq", Yq.as<T>(), (int64_t)ns * jdone * m2 * m0, cyc);
       // Q += Re sum_s V_s[0..jdone) Yq_s
       ApplyArgs aq{n,  m2, m0, 1, ns * jdone, jdone, Vb, 2 * ldc, 0, m2, blk, Yq.p, 0, Qd, m0, 0,
                    1.0, 1.0, nullptr, d_run};
       launch_apply<T, double>(st, aq);
+      dbg(st, "Q", Qd, n * m0, cyc);
       const std::vector<int> it = d2h_ints(d_iters, ns);
       const std::vector<int> cd_ = d2h_ints(d_cdone, ns);
       std::vector<int> cont(ns, 0);
@@ -444,6 +510,7 @@ struct Engine::Impl {
       ApplyArgs ar{n, m2, m2, ns, jdone + 1, jdone + 1, Vb, 2 * ldc, m2, 0, blk, Uc.p,
                    (int64_t)(jdone + 1) * m2 * m2, t1, 2 * ldc, m2, 1.0, 0.0, d_cont, nullptr};
       launch_apply<T, T>(st, ar);
+      dbg(st, "restart", t1, n * ldc * 2, cyc);
       run = cont;
     }
     return total_iters;

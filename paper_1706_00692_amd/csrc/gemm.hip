@@ -10,10 +10,12 @@
 // product V_r^T W_r (2m x 2m) and V H is V_r times the 2m x 2m real form of H.
 // Every product is therefore a real GEMM with one long dimension n.
 //
-// MFMA fragment layout used below (16x16x4, 64 lanes, lane l):
+// MFMA fragment layout used below (16x16x4, 64 lanes, lane l), as measured
+// on gfx950 with an in-bounds probe of both builtins:
 //   A operand: A[i = l % 16][k = l / 16]
 //   B operand: B[k = l / 16][j = l % 16]
-//   D (4 values v): D[i = 4 * (l / 16) + v][j = l % 16]
+//   D (4 values v), f32: D[i = 4 * (l / 16) + v][j = l % 16]
+//   D (4 values v), f64: D[i = l / 16 + 4 * v][j = l % 16]
 #include "internal.h"
 
 namespace ifeast {
@@ -30,6 +32,7 @@ template <> struct Mfma<float> {
   __device__ static inline acc mma(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
 };
 template <> struct Mfma<double> {
   using acc = v4d;
@@ -37,6 +40,7 @@ template <> struct Mfma<double> {
   __device__ static inline acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int row(int lk, int v) { return lk + 4 * v; }
 };
 
 constexpr int kXcds = 8;
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
       if (pb * 16 < vp && qb * 16 < vq) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int p = p0 + pb * 16 + 4 * lk + v;
+          const int p = p0 + pb * 16 + Mfma<T>::row(lk, v);
           const int q = q0 + qb * 16 + li;
           out[(int64_t)p * g.QW + q] = acc[t][v];
         }
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
     if (t * 16 < vq) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + wave * 16 + 4 * lk + v;
+        const int64_t row = r0 + wave * 16 + Mfma<T>::row(lk, v);
         const int col = q0 + t * 16 + li;
         if (row < a.n) {
           TO* o = O + row * a.ldo + col;

@@ -77,10 +77,18 @@ __device__ inline c2 gram_entry(const double* G, int ld, int a, int b) {
 }
 
 // ------------------------------------------------------------ CholQR factor
+// A column whose squared norm is at most dead_thr is treated as converged,
+// and a column whose Cholesky pivot (of the unit-diagonal scaled Gram) falls
+// to tau_dep or below is numerically in the span of the columns before it:
+// both get a zero basis column and a zero row of R (for a dependent column
+// its projection onto the earlier columns stays in R's column), so the
+// block Krylov space deflates instead of amplifying rounding noise.  The
+// least squares then gives such columns a zero coefficient.
 template <class T>
 __global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __restrict__ G, double shift_rel,
-                                                       const int* __restrict__ active, T* __restrict__ Tinv,
-                                                       c2* __restrict__ Racc, int accumulate, c2* __restrict__ work) {
+                                                       double dead_thr, double tau_dep, const int* __restrict__ active,
+                                                       T* __restrict__ Tinv, c2* __restrict__ Racc, int accumulate,
+                                                       c2* __restrict__ work) {
   const int s = blockIdx.x;
   if (active != nullptr && active[s] == 0) return;
   const int tid = threadIdx.x, m2 = 2 * m0;
@@ -91,36 +99,44 @@ __global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __r
   T* Tv = Tinv + (int64_t)s * m2 * m2;
   c2* Ra = Racc + (int64_t)s * m0 * m0;
   __shared__ double dsc[128];
-  __shared__ double red[8];
+  __shared__ int dead[128];
   __shared__ double piv;
+  __shared__ int dep;
 
-  double dmax = 0.0;
   for (int a = tid; a < m0; a += 256) {
-    const double d = sqrt(fmax(Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1], 0.0));
-    dsc[a] = d;
-    dmax = fmax(dmax, d);
-  }
-  dmax = block_max(dmax, red);
-  for (int a = tid; a < m0; a += 256) {
-    // a zero column keeps unit scaling; its direction is then set by rounding
-    if (!(dsc[a] > 1e-300 + 1e-150 * dmax)) dsc[a] = (dmax > 0.0 ? dmax : 1.0);
+    const double g = Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1];
+    const bool dd = !(g > dead_thr);
+    dead[a] = dd ? 1 : 0;
+    dsc[a] = dd ? 1.0 : sqrt(g);
   }
   __syncthreads();
   for (int idx = tid; idx < m0 * m0; idx += 256) {
     const int a = idx / m0, b = idx % m0;
-    c2 g = cscale(1.0 / (dsc[a] * dsc[b]), gram_entry(Gs, m2, a, b));
-    if (a == b) g = cmk(g.x + shift_rel, 0.0);
+    c2 g;
+    if (dead[a] || dead[b]) {
+      g = cmk(a == b ? 1.0 : 0.0, 0.0);
+    } else {
+      g = cscale(1.0 / (dsc[a] * dsc[b]), gram_entry(Gs, m2, a, b));
+      if (a == b) g = cmk(g.x + shift_rel, 0.0);
+    }
     L[idx] = g;
   }
   __syncthreads();
-  // Cholesky G = L L^H (lower triangle of L)
+  // Cholesky G = L L^H (lower triangle of L) with deflation of small pivots
   for (int c = 0; c < m0; ++c) {
     if (tid == 0) {
       const double p = L[c * m0 + c].x;
-      piv = (p > 1e-300) ? sqrt(p) : 1e-150;
+      dep = (!dead[c] && !(p > tau_dep)) ? 1 : 0;
+      if (dep) dead[c] = 1;
+      piv = dead[c] ? 1.0 : sqrt(p);
       L[c * m0 + c] = cmk(piv, 0.0);
     }
     __syncthreads();
+    if (dead[c]) {
+      for (int r = c + 1 + tid; r < m0; r += 256) L[r * m0 + c] = cmk(0.0, 0.0);
+      __syncthreads();
+      continue;
+    }
     const double inv = 1.0 / piv;
     for (int r = c + 1 + tid; r < m0; r += 256) L[r * m0 + c] = cscale(inv, L[r * m0 + c]);
     __syncthreads();
@@ -141,11 +157,12 @@ __global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __r
     }
   }
   __syncthreads();
-  // W_new = W D^{-1} Ri  ->  real form of D^{-1} Ri; factor R = L^H D
+  // W_new = W D^{-1} Ri  ->  real form of D^{-1} Ri; factor R = L^H D.  Dead columns:
+  // zero basis column (column of Tinv) and zero row of R (R[a][a] included).
   for (int idx = tid; idx < m0 * m0; idx += 256) {
     const int a = idx / m0, b = idx % m0;
-    store_realified(Tv, m2, a, b, cscale(1.0 / dsc[a], Ri[idx]));
-    Tm[idx] = (b >= a) ? cscale(dsc[b], cconj(L[b * m0 + a])) : cmk(0.0, 0.0);
+    store_realified(Tv, m2, a, b, (dead[b] || dead[a]) ? cmk(0.0, 0.0) : cscale(1.0 / dsc[a], Ri[idx]));
+    Tm[idx] = (b >= a && !dead[a]) ? cscale(dsc[b], cconj(L[b * m0 + a])) : cmk(0.0, 0.0);
   }
   __syncthreads();
   if (accumulate) {
@@ -680,8 +697,14 @@ template <class T>
 void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, double shift_rel, const int* active,
                           T* Tinv, cd* Racc, int accumulate, cd* work) {
   IF_REQUIRE(m0 <= 128, "cholqr: m0 > 128");
-  hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, active, Tinv,
-                     reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
+  // squared norms below this are not resolved by products in T
+  const double dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
+  // pivots of a shifted pass stay above the shift; an unshifted pass follows a shifted
+  // one whose output Gram has pivots of order that shift unless columns are dependent
+  const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+  const double tau_dep = shift_rel > 0.0 ? 0.5 * shift_rel : 0.25 * m0 * eps;
+  hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, dead_thr, tau_dep, active,
+                     Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
   IF_HIP(hipGetLastError());
 }
 template void launch_cholqr_factor<float>(hipStream_t, int, int, const double*, double, const int*, float*, cd*, int,

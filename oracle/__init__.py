@@ -13,6 +13,7 @@ quadrature  nodes, weights and the rational filter (Eq. contour_int_quad, Eq. rh
 krylov      block GMRES on one shifted system (Sec. 2.2, Sec. 3.2)
 feast       Algorithm 2 (IFEAST), Algorithm 1 (FEAST with direct solves),
             Rayleigh-Ritz and residuals, dense reference eigensolves
+reference   low spectra of large 3-D stencils by preconditioned LOBPCG
 
 Every function is pinned by a ``-m "not gpu"`` test against something other
 than itself (closed forms, textbook identities, library solvers, brute
@@ -21,6 +22,7 @@ force); none is "parity unpinned".
 
 from .quadrature import contour_nodes, gauss_legendre_half, trapezoid_half, trapezoid_circle, rho_hat
 from .krylov import block_gmres, shifted_operator
+from .reference import lowest_eigenvalues_lap3d
 from .feast import (
     IFeastResult,
     ifeast,
@@ -48,4 +50,5 @@ __all__ = [
     "inside_contour",
     "dense_reference",
     "quad_accumulate",
+    "lowest_eigenvalues_lap3d",
 ]

@@ -172,7 +172,7 @@ def classify(lam, r, eta, contour, z, w, half, tau):
 
 def ifeast(A, B, contour: dict, m0: int, max_inner: int, alpha: float, tol: float, X0: np.ndarray,
            max_outer: int = 50, mode: str = "ritz", kind: str = "symmetric", max_cycles: int = 1,
-           inner_rule: str = "global", tau: float = 0.1, callback=None) -> IFeastResult:
+           inner_rule: str = "global", tau: float = 0.5, callback=None) -> IFeastResult:
     """IFEAST with block-GMRES(k) inner solves (Algorithm 2), k = max_inner.
 
     ``mode``: "ritz" (Y0 = X (z - Lambda)^{-1}) or "literal" (Y0 = 0).

@@ -146,7 +146,7 @@ def contour_struct(c: dict):
     return s, keep
 
 
-def params_struct(m0, max_outer=50, max_inner=8, max_cycles=20, alpha=1e-2, tol=1e-9, tau=0.1,
+def params_struct(m0, max_outer=50, max_inner=8, max_cycles=20, alpha=1e-2, tol=1e-9, tau=0.5,
                   precision=PREC_FP64, problem=PROBLEM_SYMMETRIC, inner_guess=GUESS_RITZ, inner_rule=INNER_COLUMN,
                   seed=0):
     return ParamsStruct(int(m0), int(max_outer), int(max_inner), int(max_cycles), float(alpha), float(tol),

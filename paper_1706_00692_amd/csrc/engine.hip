@@ -672,9 +672,13 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     stats.m = (int)cls[1];
   };
 
+  const char* vb = getenv("IFEAST_VERBOSE");
+  const bool verbose = vb && (vb[0] == '1' || vb[0] == '2');
+  const bool verbose2 = vb && vb[0] == '2';
   // initial Rayleigh-Ritz on X0 gives Lambda, R and the exact initial ||R_F||
   I.rr(A, B, Q, X, lam, R, resid, eta);
   classify(0.0);
+  if (verbose) fprintf(stderr, "[ifeast] start rf=%.3e m=%d\n", stats.rf, stats.m);
   int status = IFEAST_WARN_NOT_CONVERGED;
   for (int it = 0; it < p.max_outer; ++it) {
     const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, stats.rf, m0);
@@ -692,6 +696,30 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
       mx = std::max(mx, iters[s]);
     }
     stats.seq_matvec += mx;
+    if (verbose) {
+      float ms_now = 0.f;
+      hipEvent_t en;
+      if (hipEventCreate(&en) == hipSuccess) {
+        (void)hipEventRecord(en, st_);
+        (void)hipEventSynchronize(en);
+        (void)hipEventElapsedTime(&ms_now, e0, en);
+        (void)hipEventDestroy(en);
+      }
+      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d t=%.2fs\n", it + 1, stats.rf, stats.m, mx,
+              ms_now * 1e-3);
+      if (verbose2) {
+        std::vector<double> etah(m0), rhoh(m0);
+        IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));
+        IF_HIP(hipMemcpyAsync(rhoh.data(), I.rho.p, m0 * 8, hipMemcpyDeviceToHost, st_));
+        IF_HIP(hipStreamSynchronize(st_));
+        const double w = 0.1 * (C.emax - C.emin);
+        for (int j = 0; j < m0; ++j)
+          if (lamh[j] > C.emin - w && lamh[j] < C.emax + w)
+            fprintf(stderr, "   pair %2d lam=%.8f r=%.2e eta/rho=%.3f flags=%d\n", j, lamh[j], residh[j],
+                    etah[j] / std::max(1e-300, std::fabs(rhoh[j])), flagh[j]);
+      }
+      fflush(stderr);
+    }
     if (stats.m > 0 && stats.rf <= p.tol) {
       stats.converged = 1;
       status = IFEAST_OK;

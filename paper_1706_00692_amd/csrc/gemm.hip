@@ -46,22 +46,40 @@ template <> struct Mfma<double> {
 constexpr int kXcds = 8;
 __device__ inline int xcd_block(int bid, int per) { return (bid % kXcds) * per + bid / kXcds; }
 
+// 16-byte vector of T for global loads
+template <class T> struct V16T;
+template <> struct V16T<float> { using t = float4; static constexpr int N = 4; };
+template <> struct V16T<double> { using t = double2; static constexpr int N = 2; };
+template <class T> __device__ inline void put16(T* dst, const typename V16T<T>::t& v);
+template <> __device__ inline void put16<float>(float* d, const float4& v) { d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w; }
+template <> __device__ inline void put16<double>(double* d, const double2& v) { d[0] = v.x; d[1] = v.y; }
+template <class T> __device__ inline typename V16T<T>::t zero16();
+template <> __device__ inline float4 zero16<float>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <> __device__ inline double2 zero16<double>() { return make_double2(0.0, 0.0); }
+
+// LDS row stride: b32 fragment reads of 4 consecutive rows hit disjoint bank halves
+template <class T> constexpr int lds_ld(int w) { return sizeof(T) == 4 ? w + ((16 - w % 32) + 32) % 32 : w; }
+
 // ------------------------------------------------------------------ Gram
-// grid: x = row split, y = output tile (tp * ntq + tq), z = item.
-// Each workgroup accumulates a (TB*16) x (TB*16) tile of A^T B over its rows
-// and writes it to `partial`; k_gram_reduce sums the splits in FP64.
+// G[item] = A_item^T B_item over a row split.  grid: x = row split,
+// y = output tile, z = item.  The tile is (TB*16) x (TB*16); the 4 waves
+// form a 2 x 2 grid, each owning H x H MFMA blocks (H = ceil(TB/2)).
 template <class T> struct GramCfg { static constexpr int KC = 32; };
 template <> struct GramCfg<double> { static constexpr int KC = 16; };
 
 template <class T, int TB>
 __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t rows_per_split, int ntq,
                                               T* __restrict__ partial) {
+  using V = typename V16T<T>::t;
+  constexpr int VN = V16T<T>::N;
   constexpr int KC = GramCfg<T>::KC;
   constexpr int TP = TB * 16;
-  constexpr int LDS_LD = TP + 4;
-  constexpr int NBW = (TB * TB + 3) / 4;  // MFMA blocks per wavefront
-  __shared__ T sA[KC * LDS_LD];
-  __shared__ T sB[KC * LDS_LD];
+  constexpr int LD = lds_ld<T>(TP);
+  constexpr int H = (TB + 1) / 2;
+  constexpr int NV = KC * TP / VN;             // 16-byte vectors per operand tile
+  constexpr int PER = (NV + 255) / 256;        // per thread
+  __shared__ T sA[KC * LD];
+  __shared__ T sB[KC * LD];
 
   const int item = blockIdx.z;
   const int s = item / g.ni, i = item % g.ni;
@@ -69,62 +87,85 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
   const int split = blockIdx.x;
   const int tp = blockIdx.y / ntq, tq = blockIdx.y % ntq;
   const int p0 = tp * TP, q0 = tq * TP;
-  const int vp = min(TP, g.PW - p0), vq = min(TP, g.QW - q0);  // valid extents (multiples of 16)
+  const int vp = min(TP, g.PW - p0), vq = min(TP, g.QW - q0);
   const int64_t r0 = (int64_t)split * rows_per_split;
   const int64_t r1 = min(g.n, r0 + rows_per_split);
-
+  if (r0 >= r1) {
+    // an empty split still owns its slot of partial sums
+  }
   const T* __restrict__ A = static_cast<const T*>(g.A) + s * g.a_s + i * g.a_i + p0;
   const T* __restrict__ B = static_cast<const T*>(g.B) + s * g.b_s + i * g.b_i + q0;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  typename Mfma<T>::acc acc[NBW];
+  const int wp = wave >> 1, wq = wave & 1;
+  typename Mfma<T>::acc acc[H][H];
 #pragma unroll
-  for (int t = 0; t < NBW; ++t) acc[t] = Mfma<T>::zero();
+  for (int a = 0; a < H; ++a)
+#pragma unroll
+    for (int b = 0; b < H; ++b) acc[a][b] = Mfma<T>::zero();
 
-  for (int64_t rc = r0; rc < r1; rc += KC) {
-    for (int idx = tid; idx < KC * TP; idx += 256) {
-      const int r = idx / TP, c = idx % TP;
-      const int64_t row = rc + r;
-      const bool ok = row < r1;
-      sA[r * LDS_LD + c] = (ok && c < vp) ? A[row * g.lda + c] : T(0);
-      sB[r * LDS_LD + c] = (ok && c < vq) ? B[row * g.ldb + c] : T(0);
-    }
-    __syncthreads();
+  V ra[PER], rb[PER];
+  auto fetch = [&](int64_t rc) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-#pragma unroll
-      for (int t = 0; t < NBW; ++t) {
-        const int b = wave + 4 * t;
-        if (b < TB * TB) {
-          const int pb = b / TB, qb = b % TB;
-          if (pb * 16 < vp && qb * 16 < vq) {
-            const T a = sA[(kk + lk) * LDS_LD + pb * 16 + li];
-            const T bb = sB[(kk + lk) * LDS_LD + qb * 16 + li];
-            acc[t] = Mfma<T>::mma(a, bb, acc[t]);
-          }
+    for (int t = 0; t < PER; ++t) {
+      const int v = tid + 256 * t;
+      ra[t] = zero16<T>();
+      rb[t] = zero16<T>();
+      if (v < NV) {
+        const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
+        const int64_t row = rc + r;
+        if (row < r1) {
+          if (c < vp) ra[t] = *reinterpret_cast<const V*>(A + row * g.lda + c);
+          if (c < vq) rb[t] = *reinterpret_cast<const V*>(B + row * g.ldb + c);
         }
       }
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t rc = r0; rc < r1; rc += KC) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int v = tid + 256 * t;
+      if (v < NV) {
+        const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
+        put16<T>(sA + r * LD + c, ra[t]);
+        put16<T>(sB + r * LD + c, rb[t]);
+      }
+    }
+    __syncthreads();
+    if (rc + KC < r1) fetch(rc + KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T af[H], bf[H];
+#pragma unroll
+      for (int a = 0; a < H; ++a) af[a] = sA[(kk + lk) * LD + (wp * H + a) * 16 + li];
+#pragma unroll
+      for (int b = 0; b < H; ++b) bf[b] = sB[(kk + lk) * LD + (wq * H + b) * 16 + li];
+#pragma unroll
+      for (int a = 0; a < H; ++a)
+#pragma unroll
+        for (int b = 0; b < H; ++b)
+          if ((wp * H + a) < TB && (wq * H + b) < TB) acc[a][b] = Mfma<T>::mma(af[a], bf[b], acc[a][b]);
     }
     __syncthreads();
   }
 
   T* out = partial + ((int64_t)item * nsplit + split) * g.PW * g.QW;
 #pragma unroll
-  for (int t = 0; t < NBW; ++t) {
-    const int b = wave + 4 * t;
-    if (b < TB * TB) {
-      const int pb = b / TB, qb = b % TB;
-      if (pb * 16 < vp && qb * 16 < vq) {
+  for (int a = 0; a < H; ++a)
+#pragma unroll
+    for (int b = 0; b < H; ++b) {
+      const int pb = wp * H + a, qb = wq * H + b;
+      if (pb < TB && qb < TB && pb * 16 < vp && qb * 16 < vq) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int p = p0 + pb * 16 + Mfma<T>::row(lk, v);
           const int q = q0 + qb * 16 + li;
-          out[(int64_t)p * g.QW + q] = acc[t][v];
+          out[(int64_t)p * g.QW + q] = acc[a][b][v];
         }
       }
     }
-  }
 }
 
 template <class T>
@@ -143,97 +184,152 @@ __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, con
 }
 
 inline int gram_tb(int W) {
-  // tile blocks per dimension: at most 8 (128 reals), as few tiles as possible
+  // tile blocks per dimension: at most 10 (160 reals), as few tiles as possible
   const int nb = W / 16;
-  const int nt = (nb + 7) / 8;
+  const int nt = (nb + 9) / 10;
   return (nb + nt - 1) / nt;
 }
 
 inline int gram_nsplit(int64_t n, int items, int tiles) {
-  int64_t want = (2048 + (int64_t)items * tiles - 1) / ((int64_t)items * tiles);
-  int64_t maxs = std::max<int64_t>(1, n / 512);
+  int64_t want = (1024 + (int64_t)items * tiles - 1) / ((int64_t)items * tiles);
+  int64_t maxs = std::max<int64_t>(1, n / 1024);
   return (int)std::max<int64_t>(1, std::min(want, maxs));
 }
 
 // ------------------------------------------------------------------ apply
-// grid: x = 64-row tile (XCD renumbered), y = output column tile, z = item.
-// Wavefront w owns rows [16w, 16w+16) of the tile and TBQ column blocks.
+// O_item = beta O_item + alpha sum_b A_b Bm_b.  grid: x = 128-row tile (XCD
+// renumbered), y = output column tile, z = item.  Wave w owns rows
+// [32w, 32w+32) of the tile (two MFMA row blocks) and TBQ column blocks.
 template <class T> struct ApplyCfg { static constexpr int KC = 32; };
 template <> struct ApplyCfg<double> { static constexpr int KC = 16; };
 
 template <class T, class TO, int TBQ>
 __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
+  using V = typename V16T<T>::t;
+  constexpr int VN = V16T<T>::N;
   constexpr int KC = ApplyCfg<T>::KC;
+  constexpr int RT = 128;
   constexpr int TQ = TBQ * 16;
   constexpr int LDA_S = KC + 4;
-  constexpr int LDB_S = TQ + 4;
-  __shared__ T sA[64 * LDA_S];
+  constexpr int LDB_S = lds_ld<T>(TQ);
+  constexpr int NVA = RT * KC / VN, PERA = (NVA + 255) / 256;
+  constexpr int NVB = KC * TQ / VN, PERB = (NVB + 255) / 256;
+  __shared__ T sA[RT * LDA_S];
   __shared__ T sB[KC * LDB_S];
 
   const int item = blockIdx.z;
   if (a.active_item != nullptr && a.active_item[item] == 0) return;
-  const int64_t nrt = (a.n + 63) / 64;
+  const int64_t nrt = (a.n + RT - 1) / RT;
   const int64_t rt = xcd_block(blockIdx.x, per);
   if (rt >= nrt) return;
-  const int64_t r0 = rt * 64;
+  const int64_t r0 = rt * RT;
   const int q0 = blockIdx.y * TQ;
   const int vq = min(TQ, a.OW - q0);
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  typename Mfma<T>::acc acc[TBQ];
+  typename Mfma<T>::acc acc[2][TBQ];
 #pragma unroll
-  for (int t = 0; t < TBQ; ++t) acc[t] = Mfma<T>::zero();
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int t = 0; t < TBQ; ++t) acc[r][t] = Mfma<T>::zero();
 
   const T* __restrict__ Abase = static_cast<const T*>(a.A) + item * a.a_item;
   const T* __restrict__ Bbase = static_cast<const T*>(a.Bm) + item * a.bm_item;
-  for (int b = 0; b < a.nb; ++b) {
+  const int nkc = (a.KW + KC - 1) / KC;
+  // flattened (block, k-chunk) loop with register prefetch
+  V ra[PERA], rb[PERB];
+  auto fetch = [&](int b, int k0) {
     const int sb = b / a.nbi, ib = b % a.nbi;
-    if (a.active_sb != nullptr && a.active_sb[sb] == 0) continue;
     const T* __restrict__ Ab = Abase + sb * a.a_s + ib * a.a_i;
     const T* __restrict__ Bb = Bbase + (int64_t)b * a.KW * a.OW;
-    for (int k0 = 0; k0 < a.KW; k0 += KC) {
-      for (int idx = tid; idx < 64 * KC; idx += 256) {
-        const int r = idx / KC, c = idx % KC;
+#pragma unroll
+    for (int t = 0; t < PERA; ++t) {
+      const int v = tid + 256 * t;
+      ra[t] = zero16<T>();
+      if (v < NVA) {
+        const int r = v / (KC / VN), c = (v % (KC / VN)) * VN;
         const int64_t row = r0 + r;
-        sA[r * LDA_S + c] = (row < a.n && k0 + c < a.KW) ? Ab[row * a.lda + k0 + c] : T(0);
+        if (row < a.n && k0 + c < a.KW) ra[t] = *reinterpret_cast<const V*>(Ab + row * a.lda + k0 + c);
       }
-      for (int idx = tid; idx < KC * TQ; idx += 256) {
-        const int r = idx / TQ, c = idx % TQ;
-        sB[r * LDB_S + c] = (k0 + r < a.KW && c < vq) ? Bb[(int64_t)(k0 + r) * a.OW + q0 + c] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < PERB; ++t) {
+      const int v = tid + 256 * t;
+      rb[t] = zero16<T>();
+      if (v < NVB) {
+        const int r = v / (TQ / VN), c = (v % (TQ / VN)) * VN;
+        if (k0 + r < a.KW && c < vq) rb[t] = *reinterpret_cast<const V*>(Bb + (int64_t)(k0 + r) * a.OW + q0 + c);
       }
-      __syncthreads();
+    }
+  };
+  auto skip = [&](int b) { return a.active_sb != nullptr && a.active_sb[b / a.nbi] == 0; };
+  int b = 0, kc = 0;
+  while (b < a.nb && skip(b)) ++b;
+  if (b < a.nb) fetch(b, 0);
+  while (b < a.nb) {
 #pragma unroll
-      for (int kk = 0; kk < KC; kk += 4) {
-        const T av = sA[(wave * 16 + li) * LDA_S + kk + lk];
+    for (int t = 0; t < PERA; ++t) {
+      const int v = tid + 256 * t;
+      if (v < NVA) {
+        const int r = v / (KC / VN), c = (v % (KC / VN)) * VN;
+        put16<T>(sA + r * LDA_S + c, ra[t]);
+      }
+    }
 #pragma unroll
-        for (int t = 0; t < TBQ; ++t) {
-          if (t * 16 < vq) {
-            const T bv = sB[(kk + lk) * LDB_S + t * 16 + li];
-            acc[t] = Mfma<T>::mma(av, bv, acc[t]);
-          }
+    for (int t = 0; t < PERB; ++t) {
+      const int v = tid + 256 * t;
+      if (v < NVB) {
+        const int r = v / (TQ / VN), c = (v % (TQ / VN)) * VN;
+        put16<T>(sB + r * LDB_S + c, rb[t]);
+      }
+    }
+    __syncthreads();
+    // next (block, chunk)
+    int nb_ = b, nk = kc + 1;
+    if (nk >= nkc) {
+      nk = 0;
+      ++nb_;
+      while (nb_ < a.nb && skip(nb_)) ++nb_;
+    }
+    if (nb_ < a.nb) fetch(nb_, nk * KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T af[2];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) af[r] = sA[(wave * 32 + r * 16 + li) * LDA_S + kk + lk];
+#pragma unroll
+      for (int t = 0; t < TBQ; ++t) {
+        if (t * 16 < vq) {
+          const T bv = sB[(kk + lk) * LDB_S + t * 16 + li];
+#pragma unroll
+          for (int r = 0; r < 2; ++r) acc[r][t] = Mfma<T>::mma(af[r], bv, acc[r][t]);
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
+    b = nb_;
+    kc = nk;
   }
 
   TO* __restrict__ O = static_cast<TO*>(a.O) + item * a.o_item;
 #pragma unroll
-  for (int t = 0; t < TBQ; ++t) {
-    if (t * 16 < vq) {
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + wave * 16 + Mfma<T>::row(lk, v);
-        const int col = q0 + t * 16 + li;
-        if (row < a.n) {
-          TO* o = O + row * a.ldo + col;
-          const TO val = (TO)(a.alpha * (double)acc[t][v]);
-          *o = (a.beta == 0.0) ? val : (TO)(a.beta * (double)(*o)) + val;
+    for (int t = 0; t < TBQ; ++t) {
+      if (t * 16 < vq) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = r0 + wave * 32 + r * 16 + Mfma<T>::row(lk, v);
+          const int col = q0 + t * 16 + li;
+          if (row < a.n) {
+            TO* o = O + row * a.ldo + col;
+            const TO val = (TO)(a.alpha * (double)acc[r][t][v]);
+            *o = (a.beta == 0.0) ? val : (TO)(a.beta * (double)(*o)) + val;
+          }
         }
       }
     }
-  }
 }
 
 }  // namespace
@@ -269,6 +365,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     case 6: hipLaunchKernelGGL((k_gram<T, 6>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
     case 7: hipLaunchKernelGGL((k_gram<T, 7>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
     case 8: hipLaunchKernelGGL((k_gram<T, 8>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 9: hipLaunchKernelGGL((k_gram<T, 9>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
+    case 10: hipLaunchKernelGGL((k_gram<T, 10>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
     default: throw Error{IFEAST_ERR_INVALID_ARG, "gram: unsupported tile"};
   }
   IF_HIP(hipGetLastError());
@@ -282,9 +380,9 @@ template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a) {
   IF_REQUIRE(a.OW % 16 == 0, "apply: output width must be a multiple of 16");
   const int nbq = a.OW / 16;
-  const int ntq = (nbq + 7) / 8;
+  const int ntq = (nbq + 9) / 10;
   const int tbq = (nbq + ntq - 1) / ntq;
-  const int64_t nrt = (a.n + 63) / 64;
+  const int64_t nrt = (a.n + 127) / 128;
   const int per = (int)((nrt + kXcds - 1) / kXcds);
   const dim3 grid(per * kXcds, ntq, a.items), block(256);
   switch (tbq) {
@@ -296,6 +394,8 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
     case 6: hipLaunchKernelGGL((k_apply<T, TO, 6>), grid, block, 0, st, a, per); break;
     case 7: hipLaunchKernelGGL((k_apply<T, TO, 7>), grid, block, 0, st, a, per); break;
     case 8: hipLaunchKernelGGL((k_apply<T, TO, 8>), grid, block, 0, st, a, per); break;
+    case 9: hipLaunchKernelGGL((k_apply<T, TO, 9>), grid, block, 0, st, a, per); break;
+    case 10: hipLaunchKernelGGL((k_apply<T, TO, 10>), grid, block, 0, st, a, per); break;
     default: throw Error{IFEAST_ERR_INVALID_ARG, "apply: unsupported tile"};
   }
   IF_HIP(hipGetLastError());

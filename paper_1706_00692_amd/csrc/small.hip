@@ -230,15 +230,70 @@ __device__ inline LsqView lsq_view(const LsqArgs& a, int s) {
   return v;
 }
 
-// Apply reflector (v, tau) with support rows [r0, r1) of `x` (column `col`, leading dim ld).
-__device__ inline void apply_reflector(const c2* v, double tau, int r0, int r1, c2* x, int xoff, int ld, int col) {
-  if (tau == 0.0) return;
-  c2 dot = cmk(0.0, 0.0);
-  for (int r = r0; r < r1; ++r) dot = cadd(dot, cjmul(v[r], x[xoff + r + (int64_t)col * ld]));
-  const c2 f = cscale(tau, dot);
-  for (int r = r0; r < r1; ++r) {
-    c2* p = x + xoff + r + (int64_t)col * ld;
-    *p = csub(*p, cmul(f, v[r]));
+// ---- wave-level helpers: one 64-lane wavefront owns one column
+__device__ inline c2 wave_csum(c2 v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+__device__ inline double wave_dsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// x[r] -= tau v[r] (v^H x) over the support rows [r0, r1); x is a wave-owned column
+// (LDS or global), v a reflector vector in global memory.
+__device__ inline void wave_reflect(const c2* __restrict__ v, double tau, int r0, int r1, c2* x, int lane) {
+  c2 d = cmk(0.0, 0.0);
+  for (int r = r0 + lane; r < r1; r += 64) d = cadd(d, cjmul(v[r], x[r]));
+  d = wave_csum(d);
+  const c2 f = cscale(tau, d);
+  for (int r = r0 + lane; r < r1; r += 64) x[r] = csub(x[r], cmul(f, v[r]));
+  // row ownership moves between lanes from one reflector to the next
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Apply reflectors c = c_begin..c_end-1 (in order, or reversed) of one step to a wave-owned
+// column x (LDS); reflector c lives in v + c*ld with support rows [c, m0 + c].  The next
+// reflector's vector is loaded into registers while the current one is applied.
+__device__ inline void wave_reflect_run(const c2* __restrict__ V, const double* __restrict__ tau, int m0, int ld,
+                                        c2* x, int lane, bool reverse) {
+  constexpr int R = 3;  // support m0 + 1 <= 129 rows -> at most 3 rows per lane
+  c2 cur[R], nxt[R];
+  auto load = [&](int c, c2* dst) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int r = c + lane + 64 * t;
+      dst[t] = (r <= m0 + c) ? V[(int64_t)c * ld + r] : cmk(0.0, 0.0);
+    }
+  };
+  int c = reverse ? m0 - 1 : 0;
+  const int step = reverse ? -1 : 1;
+  load(c, cur);
+  for (int it = 0; it < m0; ++it, c += step) {
+    const int cn = c + step;
+    if (it + 1 < m0) load(cn, nxt);
+    const double tv = tau[c];
+    if (tv != 0.0) {
+      c2 d = cmk(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int r = c + lane + 64 * t;
+        if (r <= m0 + c) d = cadd(d, cjmul(cur[t], x[r]));
+      }
+      d = wave_csum(d);
+      const c2 f = cscale(tv, d);
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int r = c + lane + 64 * t;
+        if (r <= m0 + c) x[r] = csub(x[r], cmul(f, cur[t]));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) cur[t] = nxt[t];
   }
 }
 
@@ -266,75 +321,102 @@ __global__ __launch_bounds__(256) void k_lsq_init(LsqArgs a, const c2* __restric
   }
 }
 
-__global__ __launch_bounds__(256) void k_lsq_step(LsqArgs a, int j) {
+// Step j, part 1: the reflectors of steps 0..j-1 on the new block column j of Hbar.
+// grid (ns, ceil(m0/4)); wave w of block y owns column 4y + w, staged in LDS.
+__global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
+  extern __shared__ c2 colbuf[];  // 4 x (j+2) m0
+  const int s = blockIdx.x;
+  if (a.active[s] == 0 || j == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = blockIdx.y * 4 + wave;
+  if (col >= m0) return;
+  const int rows = (j + 2) * m0;
+  c2* x = colbuf + wave * rows;
+  c2* h = v.H + (int64_t)(j * m0 + col) * ldh;
+  for (int r = lane; r < rows; r += 64) x[r] = h[r];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int i = 0; i < j; ++i)
+    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + i * m0, lane, false);
+  for (int r = lane; r < rows; r += 64) h[r] = x[r];
+}
+
+// Step j, part 2: Householder QR of the slab rows [j m0, (j+2) m0) of block column j
+// (its lower half is upper triangular), the same reflectors on the right-hand side,
+// per-column residual norms and the stopping rule.  One workgroup per shift.
+__global__ __launch_bounds__(256) void k_lsq_qr(LsqArgs a, int j) {
   const int s = blockIdx.x;
   if (a.active[s] == 0) return;
   const LsqView v = lsq_view(a, s);
-  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0, tid = threadIdx.x;
-  c2* h = v.H + (int64_t)j * m0 * ldh;  // block column j, column-major, ld ldh
-  __shared__ double red[8];
-  __shared__ double sh_tau;
-  __shared__ int sh_ok;
-
-  // 1. previous steps' reflectors on rows [i m0, (i+2) m0)
-  for (int col = tid; col < m0; col += 256) {
-    for (int i = 0; i < j; ++i) {
-      const c2* Vi = v.Vh + (int64_t)i * m2 * m0;
-      const double* ti = v.tau + i * m0;
-      for (int c = 0; c < m0; ++c) apply_reflector(Vi + (int64_t)c * m2, ti[c], c, m0 + c + 1, h, i * m0, ldh, col);
-    }
-  }
-  __syncthreads();
-  // 2. Householder QR of the slab rows [j m0, (j+2) m0); the lower half is upper triangular
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int base = j * m0;
+  c2* h = v.H + (int64_t)j * m0 * ldh + base;  // slab (row r, col c) at h[r + c * ldh]
   c2* Vj = v.Vh + (int64_t)j * m2 * m0;
   double* tj = v.tau + j * m0;
-  const int base = j * m0;
+  __shared__ double sh_tau;
+  __shared__ int sh_ok;
   for (int c = 0; c < m0; ++c) {
     c2* vc = Vj + (int64_t)c * m2;
-    const int r0 = c, r1 = m0 + c + 1;  // support within the slab
-    double ss = 0.0;
-    for (int r = r0 + tid; r < r1; r += 256) ss += cabs2(h[base + r + (int64_t)c * ldh]);
-    ss = block_sum(ss, red);
-    const double nrm = sqrt(ss);
-    const c2 x0 = h[base + r0 + (int64_t)c * ldh];
-    double tau = 0.0;
-    c2 beta = x0;
-    if (nrm > 0.0) {
-      const double ax = sqrt(cabs2(x0));
-      const c2 ph = ax > 0.0 ? cscale(1.0 / ax, x0) : cmk(1.0, 0.0);
-      beta = cscale(-nrm, ph);
-      const c2 v0 = csub(x0, beta);
-      const double vn2 = ss - cabs2(x0) + cabs2(v0);
-      tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-      for (int r = tid; r < m2; r += 256)
-        vc[r] = (r == r0) ? v0 : ((r > r0 && r < r1) ? h[base + r + (int64_t)c * ldh] : cmk(0.0, 0.0));
-    } else {
-      for (int r = tid; r < m2; r += 256) vc[r] = cmk(0.0, 0.0);
-    }
-    if (tid == 0) {
-      tj[c] = tau;
-      sh_tau = tau;
+    const int r0 = c, r1 = m0 + c + 1;
+    if (wave == 0) {
+      c2* xc = h + (int64_t)c * ldh;
+      double ss = 0.0;
+      for (int r = r0 + lane; r < r1; r += 64) ss += cabs2(xc[r]);
+      ss = wave_dsum(ss);
+      const double nrm = sqrt(ss);
+      const c2 x0 = xc[r0];
+      double tau = 0.0;
+      c2 beta = x0, v0 = cmk(0.0, 0.0);
+      if (nrm > 0.0) {
+        const double ax = sqrt(cabs2(x0));
+        const c2 ph = ax > 0.0 ? cscale(1.0 / ax, x0) : cmk(1.0, 0.0);
+        beta = cscale(-nrm, ph);
+        v0 = csub(x0, beta);
+        const double vn2 = ss - cabs2(x0) + cabs2(v0);
+        tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      }
+      for (int r = lane; r < m2; r += 64) {
+        c2 val = cmk(0.0, 0.0);
+        if (tau != 0.0) val = (r == r0) ? v0 : ((r > r0 && r < r1) ? xc[r] : cmk(0.0, 0.0));
+        vc[r] = val;
+      }
+      if (lane == 0) {
+        tj[c] = tau;
+        sh_tau = tau;
+      }
+      // the column becomes (beta, 0, ..., 0) on its support
+      if (tau != 0.0)
+        for (int r = r0 + lane; r < r1; r += 64) xc[r] = (r == r0) ? beta : cmk(0.0, 0.0);
     }
     __syncthreads();
-    if (tid == 0) h[base + r0 + (int64_t)c * ldh] = (tau != 0.0) ? beta : x0;
-    for (int r = r0 + 1 + tid; r < r1; r += 256)
-      if (sh_tau != 0.0) h[base + r + (int64_t)c * ldh] = cmk(0.0, 0.0);
-    for (int col = c + 1 + tid; col < m0; col += 256) apply_reflector(vc, sh_tau, r0, r1, h, base, ldh, col);
+    const double tau = sh_tau;
+    if (tau != 0.0)
+      for (int col = c + 1 + wave; col < m0; col += 4) wave_reflect(vc, tau, r0, r1, h + (int64_t)col * ldh, lane);
     __syncthreads();
   }
-  // 3. the same reflectors on the right-hand side
-  for (int col = tid; col < m0; col += 256)
-    for (int c = 0; c < m0; ++c) apply_reflector(Vj + (int64_t)c * m2, tj[c], c, m0 + c + 1, v.g, base, ldh, col);
-  __syncthreads();
-  // 4. residual norms (last m0 rows) and the stopping rule
+  // the same reflectors on the right-hand side columns
+  for (int col = wave; col < m0; col += 4) {
+    c2* gc = v.g + base + (int64_t)col * ldh;
+    for (int c = 0; c < m0; ++c) {
+      const double tau = tj[c];
+      if (tau != 0.0) wave_reflect(Vj + (int64_t)c * m2, tau, c, m0 + c + 1, gc, lane);
+    }
+  }
   if (tid == 0) sh_ok = 1;
   __syncthreads();
-  for (int col = tid; col < m0; col += 256) {
+  // residual norms: the last m0 rows of the transformed right-hand side
+  for (int col = wave; col < m0; col += 4) {
+    const c2* gc = v.g + (int64_t)(j + 1) * m0 + (int64_t)col * ldh;
     double ss = 0.0;
-    for (int r = 0; r < m0; ++r) ss += cabs2(v.g[(j + 1) * m0 + r + (int64_t)col * ldh]);
-    const double rn = sqrt(ss);
-    v.res[col] = rn;
-    if (!(rn <= v.tol[col])) atomicAnd(&sh_ok, 0);
+    for (int r = lane; r < m0; r += 64) ss += cabs2(gc[r]);
+    ss = wave_dsum(ss);
+    if (lane == 0) {
+      const double rn = sqrt(ss);
+      v.res[col] = rn;
+      if (!(rn <= v.tol[col])) atomicAnd(&sh_ok, 0);
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -346,46 +428,173 @@ __global__ __launch_bounds__(256) void k_lsq_step(LsqArgs a, int j) {
   }
 }
 
-// y = R^{-1} g_top and u = Q_H [0; g_tail] for every shift that ran in this cycle.
+// The same step with the slab held in LDS, packed: column c keeps its rows
+// 0..m0+c (the rest of the slab is zero), 1.5 m0^2 complex numbers in all.
+// The right-hand side slab is then transformed in LDS column chunks.
+__global__ __launch_bounds__(256) void k_lsq_qr_lds(LsqArgs a, int j) {
+  extern __shared__ c2 lds[];
+  const int s = blockIdx.x;
+  if (a.active[s] == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int base = j * m0;
+  const int P = m0 * m0 + m0 * (m0 + 1) / 2;
+  c2* sl = lds;           // packed slab
+  c2* vb = lds + P;       // current reflector (2 m0)
+  auto off = [&](int col) { return col * (m0 + 1) + col * (col - 1) / 2; };  // start of column col
+  c2* h = v.H + (int64_t)j * m0 * ldh + base;
+  c2* Vj = v.Vh + (int64_t)j * m2 * m0;
+  double* tj = v.tau + j * m0;
+  __shared__ double sh_tau;
+  __shared__ int sh_ok;
+  for (int col = wave; col < m0; col += 4) {
+    c2* dst = sl + off(col);
+    const c2* src = h + (int64_t)col * ldh;
+    for (int r = lane; r <= m0 + col; r += 64) dst[r] = src[r];
+  }
+  __syncthreads();
+  for (int c = 0; c < m0; ++c) {
+    c2* xc = sl + off(c);
+    const int r0 = c, r1 = m0 + c + 1;
+    if (wave == 0) {
+      double ss = 0.0;
+      for (int r = r0 + lane; r < r1; r += 64) ss += cabs2(xc[r]);
+      ss = wave_dsum(ss);
+      const double nrm = sqrt(ss);
+      const c2 x0 = xc[r0];
+      double tau = 0.0;
+      c2 beta = x0, v0 = cmk(0.0, 0.0);
+      if (nrm > 0.0) {
+        const double ax = sqrt(cabs2(x0));
+        const c2 ph = ax > 0.0 ? cscale(1.0 / ax, x0) : cmk(1.0, 0.0);
+        beta = cscale(-nrm, ph);
+        v0 = csub(x0, beta);
+        const double vn2 = ss - cabs2(x0) + cabs2(v0);
+        tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      }
+      for (int r = lane; r < m2; r += 64) {
+        c2 val = cmk(0.0, 0.0);
+        if (tau != 0.0) val = (r == r0) ? v0 : ((r > r0 && r < r1) ? xc[r] : cmk(0.0, 0.0));
+        vb[r] = val;
+        Vj[(int64_t)c * m2 + r] = val;
+      }
+      if (lane == 0) {
+        tj[c] = tau;
+        sh_tau = tau;
+      }
+      if (tau != 0.0)
+        for (int r = r0 + lane; r < r1; r += 64) xc[r] = (r == r0) ? beta : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    const double tau = sh_tau;
+    if (tau != 0.0) {
+      for (int col = c + 1 + wave; col < m0; col += 4) {
+        c2* x = sl + off(col);
+        c2 d = cmk(0.0, 0.0);
+        for (int r = r0 + lane; r < r1; r += 64) d = cadd(d, cjmul(vb[r], x[r]));
+        d = wave_csum(d);
+        const c2 f = cscale(tau, d);
+        for (int r = r0 + lane; r < r1; r += 64) x[r] = csub(x[r], cmul(f, vb[r]));
+      }
+    }
+    __syncthreads();
+  }
+  // R block column back to global (rows 0..m0+col of each slab column)
+  for (int col = wave; col < m0; col += 4) {
+    const c2* src = sl + off(col);
+    c2* dst = h + (int64_t)col * ldh;
+    for (int r = lane; r <= m0 + col; r += 64) dst[r] = src[r];
+  }
+  __syncthreads();
+  // right-hand side slab: column chunks in LDS, reflectors staged one at a time
+  const int CH = max(4, (P / m2) / 4 * 4);
+  for (int c0 = 0; c0 < m0; c0 += CH) {
+    const int nc = min(CH, m0 - c0);
+    for (int idx = tid; idx < nc * m2; idx += 256) {
+      const int cc = idx / m2, r = idx % m2;
+      sl[cc * m2 + r] = v.g[base + r + (int64_t)(c0 + cc) * ldh];
+    }
+    for (int c = 0; c < m0; ++c) {
+      __syncthreads();
+      for (int r = tid; r < m2; r += 256) vb[r] = Vj[(int64_t)c * m2 + r];
+      __syncthreads();
+      const double tau = tj[c];
+      if (tau == 0.0) continue;
+      const int r0 = c, r1 = m0 + c + 1;
+      for (int cc = wave; cc < nc; cc += 4) {
+        c2* x = sl + cc * m2;
+        c2 d = cmk(0.0, 0.0);
+        for (int r = r0 + lane; r < r1; r += 64) d = cadd(d, cjmul(vb[r], x[r]));
+        d = wave_csum(d);
+        const c2 f = cscale(tau, d);
+        for (int r = r0 + lane; r < r1; r += 64) x[r] = csub(x[r], cmul(f, vb[r]));
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nc * m2; idx += 256) {
+      const int cc = idx / m2, r = idx % m2;
+      v.g[base + r + (int64_t)(c0 + cc) * ldh] = sl[cc * m2 + r];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) sh_ok = 1;
+  __syncthreads();
+  for (int col = wave; col < m0; col += 4) {
+    const c2* gc = v.g + (int64_t)(j + 1) * m0 + (int64_t)col * ldh;
+    double ss = 0.0;
+    for (int r = lane; r < m0; r += 64) ss += cabs2(gc[r]);
+    ss = wave_dsum(ss);
+    if (lane == 0) {
+      const double rn = sqrt(ss);
+      v.res[col] = rn;
+      if (!(rn <= v.tol[col])) atomicAnd(&sh_ok, 0);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.iters[s] = j + 1;
+    if (sh_ok) {
+      a.cycle_done[s] = 1;
+      a.active[s] = 0;
+    }
+  }
+}
+
+// y = R^{-1} g_top (column-oriented back substitution, one wave per right-hand side)
+// and u = Q_H [0; g_tail] (reflectors in reverse order).  grid (ns, ceil(m0/4)).
 __global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
+  extern __shared__ c2 colbuf[];  // 4 x ldh
   const int s = blockIdx.x;
   const int J = a.iters[s];
   if (J == 0) return;
   const LsqView v = lsq_view(a, s);
-  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0, tid = threadIdx.x;
-  const int n = J * m0, ldy = a.k * m0;
-  for (int64_t idx = tid; idx < (int64_t)ldy * m0; idx += 256) {
-    const int r = (int)(idx % ldy), c = (int)(idx / ldy);
-    v.y[idx] = (r < n) ? v.g[r + (int64_t)c * ldh] : cmk(0.0, 0.0);
-  }
-  __syncthreads();
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0, ldy = a.k * m0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = blockIdx.y * 4 + wave;
+  if (col >= m0) return;
+  const int n = J * m0;
+  c2* x = colbuf + wave * ldh;
+  const c2* gc = v.g + (int64_t)col * ldh;
+  for (int r = lane; r < n; r += 64) x[r] = gc[r];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   for (int c = n - 1; c >= 0; --c) {
-    const c2 d = v.H[c + (int64_t)c * ldh];
-    const bool ok = cabs2(d) > 1e-300;
-    for (int col = tid; col < m0; col += 256) {
-      c2* yc = v.y + c + (int64_t)col * ldy;
-      *yc = ok ? cdiv(*yc, d) : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < c * m0; idx += 256) {
-      const int r = idx % c, col = idx / c;
-      c2* yr = v.y + r + (int64_t)col * ldy;
-      *yr = csub(*yr, cmul(v.H[r + (int64_t)c * ldh], v.y[c + (int64_t)col * ldy]));
-    }
-    __syncthreads();
+    const c2* Rc = v.H + (int64_t)c * ldh;  // column c of R
+    const c2 d = Rc[c];
+    const c2 yc = cabs2(d) > 1e-300 ? cdiv(x[c], d) : cmk(0.0, 0.0);
+    for (int r = lane; r < c; r += 64) x[r] = csub(x[r], cmul(Rc[r], yc));
+    if (lane == 0) x[c] = yc;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-  for (int64_t idx = tid; idx < (int64_t)ldh * m0; idx += 256) {
-    const int r = (int)(idx % ldh), c = (int)(idx / ldh);
-    v.u[idx] = (r >= n && r < n + m0) ? v.g[idx] : cmk(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int col = tid; col < m0; col += 256)
-    for (int i = J - 1; i >= 0; --i) {
-      const c2* Vi = v.Vh + (int64_t)i * m2 * m0;
-      const double* ti = v.tau + i * m0;
-      for (int c = m0 - 1; c >= 0; --c)
-        apply_reflector(Vi + (int64_t)c * m2, ti[c], c, m0 + c + 1, v.u, i * m0, ldh, col);
-    }
+  c2* yc = v.y + (int64_t)col * ldy;
+  for (int r = lane; r < ldy; r += 64) yc[r] = r < n ? x[r] : cmk(0.0, 0.0);
+  // u = Q_H [0; g_tail]
+  for (int r = lane; r < ldh; r += 64) x[r] = (r >= n && r < n + m0) ? gc[r] : cmk(0.0, 0.0);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int i = J - 1; i >= 0; --i)
+    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + i * m0, lane, true);
+  c2* uc = v.u + (int64_t)col * ldh;
+  for (int r = lane; r < ldh; r += 64) uc[r] = x[r];
 }
 
 // Yq[s][b]: (2m0 x m0) real form for Q += Re(V_b (wf y_b)); Uc[s][b]: (2m0 x 2m0) real form of u_b.
@@ -428,7 +637,7 @@ __device__ void jacobi_eig(double* a, int m, double* Vg, double* red) {
   const int tid = threadIdx.x, half = m / 2;
   for (int idx = tid; idx < m * m; idx += 256) Vg[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int idx = tid; idx < m * m; idx += 256) {
       const int r = idx / m, c = idx % m;
@@ -437,7 +646,8 @@ __device__ void jacobi_eig(double* a, int m, double* Vg, double* red) {
     }
     off = block_sum(off, red);
     dia = block_sum(dia, red);
-    if (off <= 1e-32 * dia || off == 0.0) break;
+    // off-diagonal mass at rounding level of the diagonal: (m * eps)^2 relative
+    if (off <= (double)m * m * 4.9e-32 * dia || off == 0.0) break;
     for (int round = 0; round < m - 1; ++round) {
       if (tid < half) {
         auto pos = [&](int t) { return t == 0 ? 0 : 1 + (t - 1 + round) % (m - 1); };
@@ -738,11 +948,39 @@ void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S) {
   IF_HIP(hipGetLastError());
 }
 void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
-  hipLaunchKernelGGL(k_lsq_step, dim3(a.ns), dim3(256), 0, st, a, j);
+  if (j > 0) {
+    const size_t lds = (size_t)4 * (j + 2) * a.m0 * sizeof(c2);
+    if (lds > 64 * 1024)
+      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_prev), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(k_lsq_prev, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a, j);
+    IF_HIP(hipGetLastError());
+  }
+  // packed slab in LDS when it fits the workgroup's LDS
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
+  const size_t P = (size_t)a.m0 * a.m0 + (size_t)a.m0 * (a.m0 + 1) / 2;
+  const size_t lds = (P + 2 * (size_t)a.m0) * sizeof(c2);
+  if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
+    if (lds > 64 * 1024)
+      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_qr_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_lsq_qr_lds, dim3(a.ns), dim3(256), lds, st, a, j);
+  } else {
+    hipLaunchKernelGGL(k_lsq_qr, dim3(a.ns), dim3(256), 0, st, a, j);
+  }
   IF_HIP(hipGetLastError());
 }
 void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
-  hipLaunchKernelGGL(k_lsq_finish, dim3(a.ns), dim3(256), 0, st, a);
+  const size_t lds = (size_t)4 * a.ldh * sizeof(c2);
+  if (lds > 64 * 1024)
+    IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_finish), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  hipLaunchKernelGGL(k_lsq_finish, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a);
   IF_HIP(hipGetLastError());
 }
 

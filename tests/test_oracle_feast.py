@@ -163,3 +163,12 @@ def test_ifeast_nonhermitian_small_closed_form():
     assert np.abs(res.lam_in.imag).max() < 1e-8
     d = O.feast_direct(p.A, None, p.contour, p.x0(), 1e-10, 10, kind="general")
     assert d.converged and np.allclose(np.sort(d.lam_in.real), want, rtol=1e-9, atol=0)
+
+
+def test_lobpcg_reference_matches_dense():
+    N = 10
+    A = W.laplacian_3d(N, W.random_potential(N ** 3, 1002))
+    vals, res = O.lowest_eigenvalues_lap3d(A, N, 24)
+    dense = np.linalg.eigvalsh(A.to_dense())[:20]
+    assert np.allclose(vals[:20], dense, rtol=1e-10, atol=0)
+    assert res[:20].max() < 1e-7

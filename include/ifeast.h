@@ -98,6 +98,9 @@ typedef struct {
   double alpha;        /* inner tolerance factor, 0 <= alpha < 1 */
   double tol;          /* eigen-residual tolerance on ||R_F|| */
   double spurious_tau; /* a Ritz pair inside C counts when its filter gain >= tau |rho_hat(lambda)| */
+  double reorth_eta;   /* block Gram-Schmidt in the Arnoldi step: a second classical pass runs for a shift
+                          when some column kept less than this fraction of its norm in the first one;
+                          0 selects 0.1, >= 1 always runs two passes */
   int precision;       /* IFEAST_PREC_* */
   int problem;         /* IFEAST_PROBLEM_* */
   int inner_guess;     /* IFEAST_GUESS_* */
@@ -177,6 +180,26 @@ int ifeast_submit(ifeast_ctx *ctx, const ifeast_csr *A, const ifeast_csr *B, con
                   const ifeast_params *p, const double *X0, uint64_t *ticket);
 int ifeast_poll(ifeast_ctx *ctx, uint64_t ticket, int *done);
 int ifeast_wait(ifeast_ctx *ctx, uint64_t ticket, ifeast_result *res, double *latency_s);
+
+/* ------------------------------------------------------- kernel timing */
+/* Classes of kernels whose launches are timed when timing is on. */
+enum { IFEAST_KERNEL_SPMM = 0,   /* batched shifted SpMM (Algorithm 2, step 1) */
+       IFEAST_KERNEL_GRAM = 1,   /* Gram products of the block orthogonalization (CGS, Cholesky QR) */
+       IFEAST_KERNEL_UPDATE = 2, /* block updates W -= V H, W R^-1 and restart combinations */
+       IFEAST_KERNEL_QACC = 3,   /* quadrature accumulation Q += Re sum_s wf_s V_s y_s */
+       IFEAST_KERNEL_OUTER = 4 };/* FP64 products of the Rayleigh-Ritz step */
+typedef struct {
+  int64_t launches;
+  double seconds;  /* sum of launch durations, from HIP events on the context's stream */
+  double flops;    /* algorithmic floating-point operations of those launches (active shifts only) */
+  double bytes;    /* algorithmic device-memory bytes: every operand read once, every result written once */
+} ifeast_kernel_stat;
+/* enable != 0: reset the totals and time every later compute call on this
+ * context (two events per timed launch, flushed every 256 launches);
+ * 0: stop timing.  Totals survive until the next ifeast_set_timing. */
+int ifeast_set_timing(ifeast_ctx *ctx, int enable);
+/* Totals of class `kind` (IFEAST_KERNEL_*) since timing was last enabled. */
+int ifeast_kernel_stats(ifeast_ctx *ctx, int kind, ifeast_kernel_stat *out);
 
 /* ------------------------------------------------- steps (device pointers) */
 /* One launch of the batched shifted product for all systems

@@ -39,7 +39,8 @@ class ContourStruct(C.Structure):
 
 class ParamsStruct(C.Structure):
     _fields_ = [("m0", C.c_int), ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_cycles", C.c_int),
-                ("alpha", C.c_double), ("tol", C.c_double), ("spurious_tau", C.c_double), ("precision", C.c_int),
+                ("alpha", C.c_double), ("tol", C.c_double), ("spurious_tau", C.c_double),
+                ("reorth_eta", C.c_double), ("precision", C.c_int),
                 ("problem", C.c_int), ("inner_guess", C.c_int), ("inner_rule", C.c_int), ("seed", C.c_uint64)]
 
 
@@ -54,6 +55,15 @@ class IFeastError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class KernelStatStruct(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+KERNEL_SPMM, KERNEL_GRAM, KERNEL_UPDATE, KERNEL_QACC, KERNEL_OUTER = 0, 1, 2, 3, 4
+KERNEL_NAMES = {KERNEL_SPMM: "spmm", KERNEL_GRAM: "gram", KERNEL_UPDATE: "update", KERNEL_QACC: "qacc",
+                KERNEL_OUTER: "outer"}
 
 
 def library_path() -> str:
@@ -97,6 +107,8 @@ def load_library():
         "ifeast_filter_dev": (i32, [vp, vp, vp, C.POINTER(ContourStruct), C.POINTER(ParamsStruct), vp, vp, vp, dbl,
                                     vp, vp]),
         "ifeast_rayleigh_ritz_dev": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
+        "ifeast_set_timing": (i32, [vp, i32]),
+        "ifeast_kernel_stats": (i32, [vp, i32, C.POINTER(KernelStatStruct)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -148,9 +160,10 @@ def contour_struct(c: dict):
 
 def params_struct(m0, max_outer=50, max_inner=8, max_cycles=20, alpha=1e-2, tol=1e-9, tau=0.5,
                   precision=PREC_FP64, problem=PROBLEM_SYMMETRIC, inner_guess=GUESS_RITZ, inner_rule=INNER_COLUMN,
-                  seed=0):
+                  seed=0, reorth_eta=0.0):
     return ParamsStruct(int(m0), int(max_outer), int(max_inner), int(max_cycles), float(alpha), float(tol),
-                        float(tau), int(precision), int(problem), int(inner_guess), int(inner_rule), int(seed))
+                        float(tau), float(reorth_eta), int(precision), int(problem), int(inner_guess),
+                        int(inner_rule), int(seed))
 
 
 def _params_from(p, precision):
@@ -336,6 +349,19 @@ class Context:
         return bufs.result(st, nc, lat.value)
 
     # ------------------------------------------------- device-pointer steps
+    def set_timing(self, enable: bool = True):
+        """Reset the per-kernel-class totals and time later compute calls (HIP events on the stream)."""
+        self._check(self.lib.ifeast_set_timing(self.h, int(bool(enable))))
+
+    def kernel_stats(self) -> dict:
+        """{class name: {launches, seconds, flops, bytes}} accumulated since set_timing(True)."""
+        out = {}
+        for k, name in KERNEL_NAMES.items():
+            st = KernelStatStruct()
+            self._check(self.lib.ifeast_kernel_stats(self.h, k, C.byref(st)))
+            out[name] = {"launches": int(st.launches), "seconds": st.seconds, "flops": st.flops, "bytes": st.bytes}
+        return out
+
     def spmm_shifted(self, A: Matrix, B: Matrix | None, precision: int, z, m0: int, V, W):
         """W = z_s B V_s - A V_s for all shifts (torch tensors on the device, complex64/complex128)."""
         self._use_torch_stream()

@@ -41,6 +41,34 @@ struct DeviceGuard {
   ~DeviceGuard() { (void)hipSetDevice(prev); }
 };
 
+// Installs a kernel timer for the calling thread while a compute call runs on a
+// context with timing on, then folds its totals into the context (caller holds ctx->mu).
+struct TimingScope {
+  ifeast_ctx* ctx;
+  std::unique_ptr<KernelTimer> t;
+  explicit TimingScope(ifeast_ctx* c) : ctx(c) {
+    if (ctx->timing) {
+      t.reset(new KernelTimer());
+      current_timer() = t.get();
+    }
+  }
+  ~TimingScope() {
+    if (!t) return;
+    current_timer() = nullptr;
+    try {
+      t->flush();
+    } catch (...) {
+      return;  // a device error is reported by the call itself
+    }
+    for (int k = 0; k < KC_N; ++k) {
+      ctx->kstats[k].launches += t->acc[k].launches;
+      ctx->kstats[k].seconds += t->acc[k].seconds;
+      ctx->kstats[k].flops += t->acc[k].flops;
+      ctx->kstats[k].bytes += t->acc[k].bytes;
+    }
+  }
+};
+
 void check_csr(const ifeast_csr* M) {
   IF_REQUIRE(M != nullptr && M->rowptr != nullptr && M->colind != nullptr && M->val != nullptr, "null CSR pointer");
   IF_REQUIRE(M->n > 0 && M->n < (int64_t(1) << 31), "n must be in [1, 2^31)");
@@ -231,6 +259,7 @@ int ifeast_solve_resident(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, C, p));
+    TimingScope ts(ctx);
     return eng.solve(A, B, *C, *p, X0, res);
   });
 }
@@ -254,6 +283,30 @@ int ifeast_solve(ifeast_ctx* ctx, const ifeast_csr* A, const ifeast_csr* B, cons
   return st;
 }
 
+int ifeast_set_timing(ifeast_ctx* ctx, int enable) {
+  return guarded(ctx, [&]() -> int {
+    IF_REQUIRE(ctx != nullptr, "null context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->timing = enable != 0;
+    for (auto& k : ctx->kstats) k = KernelStat{};
+    return IFEAST_OK;
+  });
+}
+
+int ifeast_kernel_stats(ifeast_ctx* ctx, int kind, ifeast_kernel_stat* out) {
+  return guarded(ctx, [&]() -> int {
+    IF_REQUIRE(ctx != nullptr && out != nullptr, "null argument");
+    IF_REQUIRE(kind >= 0 && kind < KC_N, "unknown kernel class");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const KernelStat& k = ctx->kstats[kind];
+    out->launches = k.launches;
+    out->seconds = k.seconds;
+    out->flops = k.flops;
+    out->bytes = k.bytes;
+    return IFEAST_OK;
+  });
+}
+
 int ifeast_spmm_shifted_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_matrix* B, int precision, int ns,
                             const double* z, int m0, const void* V, void* W) {
   return guarded(ctx, [&]() -> int {
@@ -262,6 +315,7 @@ int ifeast_spmm_shifted_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeas
     IF_REQUIRE(ns >= 1 && ns <= 64 && m0 >= 2 && m0 % 2 == 0, "ns in [1, 64] and even m0 required");
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
+    TimingScope ts(ctx);
     hipStream_t st = ctx->stream;
     if (precision == IFEAST_PREC_MIXED) {
       std::vector<float> zf(2 * ns);
@@ -294,6 +348,7 @@ int ifeast_filter_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_matr
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, C, p));
+    TimingScope ts(ctx);
     std::vector<int> it;
     eng.filter(A, B, *C, *p, X, lam, R, rf, Q, &it);
     if (inner_iters)
@@ -321,6 +376,7 @@ int ifeast_rayleigh_ritz_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifea
     p.max_inner = 1;
     p.precision = IFEAST_PREC_FP64;
     Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, &C, &p));
+    TimingScope ts(ctx);
     eng.rayleigh_ritz(A, B, Q, lam, X, R, resid, eta);
     IF_HIP(hipStreamSynchronize(ctx->stream));
     return IFEAST_OK;

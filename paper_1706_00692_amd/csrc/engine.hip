@@ -131,6 +131,7 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
   IF_REQUIRE(p.max_outer >= 1 && p.max_inner >= 1 && p.max_cycles >= 1, "iteration limits must be >= 1");
   IF_REQUIRE(p.alpha >= 0.0 && p.alpha < 1.0, "alpha must be in [0, 1)");
   IF_REQUIRE(p.tol > 0.0, "tol must be positive");
+  IF_REQUIRE(p.reorth_eta >= 0.0, "reorth_eta must be >= 0");
   IF_REQUIRE(p.precision == IFEAST_PREC_FP64 || p.precision == IFEAST_PREC_MIXED, "unknown precision");
   IF_REQUIRE(p.inner_rule == IFEAST_INNER_GLOBAL || p.inner_rule == IFEAST_INNER_COLUMN, "unknown inner rule");
   if (p.problem != IFEAST_PROBLEM_SYMMETRIC)
@@ -156,7 +157,7 @@ namespace {
 struct Layout {
   // byte sizes of every buffer of the workspace
   size_t X, Q, AQ, BQ, R, vec, mm, rrwork, colpart;
-  size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, Hr, Tinv, Racc, chol, Yq, Uc, zs;
+  size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gw, Hr, Tinv, Racc, chol, Yq, Uc, zs;
 };
 
 Layout layout(const Shape& s) {
@@ -178,7 +179,7 @@ Layout layout(const Shape& s) {
   L.tauh = ns * k * m0 * 8;
   L.g = L.u = ns * ldh * m0 * 16;
   L.y = ns * k * m0 * m0 * 16;
-  L.flags = 8 * 64 * 4;
+  L.flags = 16 * 64 * 4;
   L.tol = ns * m0 * 8 * 2;
   // the split count depends on the item count: take the largest over every step's Gram
   size_t gp = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
@@ -187,6 +188,7 @@ Layout layout(const Shape& s) {
                               : gram_partial_bytes<double>(s.n, (int)m2, (int)m2, (int)items));
   L.gpart = gp;
   L.gred = std::max(ns * k * m2 * m2, 2 * m0 * m0) * 8;
+  L.gw = ns * m2 * m2 * 8;
   L.Hr = ns * k * m2 * m2 * ts;
   L.Tinv = ns * m2 * m2 * ts;
   L.Racc = ns * m0 * m0 * 16;
@@ -199,7 +201,7 @@ Layout layout(const Shape& s) {
 
 size_t total(const Layout& L) {
   return 3 * L.X + L.AQ + L.BQ + L.R + 8 * L.vec + 3 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
-         L.tauh + 2 * L.g + L.y + L.flags + L.tol + L.gpart + L.gred + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq + L.Uc +
+         L.tauh + 2 * L.g + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq + L.Uc +
          3 * L.zs;
 }
 
@@ -264,13 +266,16 @@ struct Engine::Impl {
   // outer, FP64
   DevBuf X, Q, Xn, AQ, BQ, R, lam, resid, eta, rho, C, GA, GB, rrwork, colpart, clsout;
   // inner
-  DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
+  DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gwb, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
   int* d_active = nullptr;  // ns
   int* d_run = nullptr;     // ns
   int* d_cont = nullptr;    // ns
   int* d_iters = nullptr;   // ns
   int* d_cdone = nullptr;   // ns
   int* d_cls = nullptr;     // m0 flags
+  int* d_need = nullptr;    // ns flags: second Gram-Schmidt pass needed
+  double reorth_eta = 0.1;  // keep-fraction below which a second pass runs (>= 1: always)
+  int64_t reorth_steps = 0; // shift-steps that ran a second pass
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
 
   Impl(hipStream_t s, const Shape& shape) : sh(shape), st(s), L(layout(shape)) {
@@ -303,6 +308,7 @@ struct Engine::Impl {
     tol = DevBuf(L.tol);
     gpart = DevBuf(L.gpart);
     gred = DevBuf(L.gred);
+    gwb = DevBuf(L.gw);
     Hr = DevBuf(L.Hr);
     Tinv = DevBuf(L.Tinv);
     Racc = DevBuf(L.Racc);
@@ -319,6 +325,7 @@ struct Engine::Impl {
     d_iters = f + 192;
     d_cdone = f + 256;
     d_cls = f + 320;
+    d_need = f + 448;
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
     // stale basis blocks of shifts that stopped early are multiplied by zero
@@ -340,13 +347,13 @@ struct Engine::Impl {
       launch_spmm_real(st, B, m0, Qin, BQ.as<double>());
       bq = BQ.as<double>();
     }
-    GramArgs ga{n, m0, m0, 1, 1, Qin, m0, 0, 0, aq, m0, 0, 0, nullptr, GA.as<double>()};
+    GramArgs ga{n, m0, m0, 1, 1, Qin, m0, 0, 0, aq, m0, 0, 0, nullptr, GA.as<double>(), KC_OUTER};
     launch_gram<double>(st, ga, gpart.p, gpart.bytes);
-    GramArgs gb{n, m0, m0, 1, 1, Qin, m0, 0, 0, bq, m0, 0, 0, nullptr, GB.as<double>()};
+    GramArgs gb{n, m0, m0, 1, 1, Qin, m0, 0, 0, bq, m0, 0, 0, nullptr, GB.as<double>(), KC_OUTER};
     launch_gram<double>(st, gb, gpart.p, gpart.bytes);
     launch_rr_small(st, m0, GA.as<double>(), GB.as<double>(), lamv, C.as<double>(), etav, rrwork.as<double>());
     // X = Q C, AX = AQ C (into R), BX = BQ C (into Xn scratch unless B = I)
-    ApplyArgs ap{n, m0, m0, 1, 1, 1, Qin, m0, 0, 0, 0, C.p, 0, Xout, m0, 0, 1.0, 0.0, nullptr, nullptr};
+    ApplyArgs ap{n, m0, m0, 1, 1, 1, Qin, m0, 0, 0, 0, C.p, 0, Xout, m0, 0, 1.0, 0.0, nullptr, nullptr, KC_OUTER};
     launch_apply<double, double>(st, ap);
     ApplyArgs aa = ap;
     aa.A = aq;
@@ -367,16 +374,22 @@ struct Engine::Impl {
   // ---------------------------------------------------------- CholQR2
   // dst_s = orthonormal basis of src_s (n x m0 complex, per shift), Racc_s = R factor.
   template <class T>
-  void cholqr2(const T* src, T* tmp, T* dst, const int* act) {
+  void cholqr2(const T* src, T* tmp, T* dst, const int* act, const double* G0 = nullptr) {
     const int64_t n = sh.n;
     const int m0 = sh.m0, m2 = 2 * m0, ns = sh.ns;
     const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
     const T* in = src;
     for (int pass = 0; pass < 2; ++pass) {
       T* out = pass == 0 ? tmp : dst;
-      GramArgs gg{n, m2, m2, ns, 1, in, 2 * ldc, m2, 0, in, 2 * ldc, m2, 0, act, gred.as<double>()};
-      launch_gram<T>(st, gg, gpart.p, gpart.bytes);
-      launch_cholqr_factor<T>(st, ns, m0, gred.as<double>(), pass == 0 ? 4.0 * m0 * eps : 0.0, act, Tinv.as<T>(),
+      // G0: the Gram of src, already computed for every active shift
+      const double* G = gred.as<double>();
+      if (pass == 0 && G0 != nullptr) {
+        G = G0;
+      } else {
+        GramArgs gg{n, m2, m2, ns, 1, in, 2 * ldc, m2, 0, in, 2 * ldc, m2, 0, act, gred.as<double>()};
+        launch_gram<T>(st, gg, gpart.p, gpart.bytes);
+      }
+      launch_cholqr_factor<T>(st, ns, m0, G, pass == 0 ? 4.0 * m0 * eps : 0.0, act, Tinv.as<T>(),
                               Racc.as<cd>(), pass, chol.as<cd>());
       ApplyArgs ap{n, m2, m2, ns, 1, 1, in, 2 * ldc, m2, 0, 0, Tinv.p, (int64_t)m2 * m2, out, 2 * ldc, m2,
                    1.0, 0.0, act, nullptr};
@@ -403,6 +416,12 @@ struct Engine::Impl {
     a.iters = d_iters;
     a.cycle_done = d_cdone;
     return a;
+  }
+
+  // host-known population of a device flag array, for the kernel timer's accounting
+  static void note(const int* flags, const std::vector<int>& h) {
+    if (KernelTimer* kt = current_timer())
+      kt->set_count(flags, (int)std::count_if(h.begin(), h.end(), [](int v) { return v != 0; }));
   }
 
   std::vector<int> d2h_ints(const int* d, int cnt) {
@@ -449,9 +468,12 @@ struct Engine::Impl {
     dbg(st, "rhs", t1, n * ldc * 2);
     std::vector<int> run(ns, 1), total_iters(ns, 0);
     LsqArgs la = lsq_args();
+    reorth_eta = p.reorth_eta > 0.0 ? p.reorth_eta : 0.1;
     for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
       h2d(d_run, run.data(), ns * sizeof(int));
       h2d(d_active, run.data(), ns * sizeof(int));
+      note(d_run, run);
+      note(d_active, run);
       // V_1 S = qr(start block)
       cholqr2<T>(t1, t2, Vb, d_run);
       dbg(st, "V0", Vb, n * ldc * 2, cyc);
@@ -463,18 +485,42 @@ struct Engine::Impl {
         // W = z_s V_j - A V_j (all shifts in one launch)
         launch_spmm_shifted<T>(st, A, B, ns, m0, zsT.as<T>(), d_active, Vj, t1);
         dbg(st, "W=MV", t1, n * ldc * 2, cyc, j);
-        // CGS2 against V_0..V_j
-        for (int pass = 0; pass < 2; ++pass) {
-          GramArgs gg{n, m2, m2, ns, j + 1, Vb, 2 * ldc, m2, blk, t1, 2 * ldc, m2, 0, d_active, gred.as<double>()};
+        // classical Gram-Schmidt against V_0..V_j; the second pass runs only for the shifts
+        // whose block kept less than the fraction reorth_eta of some column's norm
+        auto cgs_pass = [&](const int* act, int accumulate) {
+          GramArgs gg{n, m2, m2, ns, j + 1, Vb, 2 * ldc, m2, blk, t1, 2 * ldc, m2, 0, act, gred.as<double>()};
           launch_gram<T>(st, gg, gpart.p, gpart.bytes);
-          launch_cgs_combine<T>(st, ns, j + 1, m0, j, ldh, gred.as<double>(), d_active, H.as<cd>(), Hr.as<T>(), pass);
+          launch_cgs_combine<T>(st, ns, j + 1, m0, j, ldh, gred.as<double>(), act, H.as<cd>(), Hr.as<T>(),
+                                accumulate);
           ApplyArgs ap{n,   m2,  m2,  ns,     j + 1,         j + 1, Vb, 2 * ldc, m2,      0,        blk,
-                       Hr.p, (int64_t)(j + 1) * m2 * m2, t1, 2 * ldc, m2, -1.0, 1.0, d_active, nullptr};
+                       Hr.p, (int64_t)(j + 1) * m2 * m2, t1, 2 * ldc, m2, -1.0, 1.0, act, nullptr};
           launch_apply<T, T>(st, ap);
+        };
+        cgs_pass(d_active, 0);
+        if (reorth_eta >= 1.0) {
+          cgs_pass(d_active, 1);
+          reorth_steps += ns;
+        }
+        // Gram of the projected block; it is also Cholesky-QR's first Gram when no second pass runs
+        // (its own buffer: a second pass reuses gred for the coefficients of every block)
+        GramArgs gw{n, m2, m2, ns, 1, t1, 2 * ldc, m2, 0, t1, 2 * ldc, m2, 0, d_active, gwb.as<double>()};
+        launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+        if (reorth_eta < 1.0) {
+          launch_reorth_check(st, ns, m0, j, ldh, reorth_eta, gwb.as<double>(), d_active, H.as<cd>(), d_need);
+          const std::vector<int> need = d2h_ints(d_need, ns);
+          const int nneed = (int)std::count_if(need.begin(), need.end(), [](int v) { return v != 0; });
+          if (nneed > 0) {
+            note(d_need, need);
+            cgs_pass(d_need, 1);
+            GramArgs gn = gw;
+            gn.active = d_need;
+            launch_gram<T>(st, gn, gpart.p, gpart.bytes);
+            reorth_steps += nneed;
+          }
         }
         // V_{j+1} H_{j+1,j} = qr(W)
         dbg(st, "W_cgs", t1, n * ldc * 2, cyc, j);
-        cholqr2<T>(t1, t2, Vb + (int64_t)(j + 1) * blk, d_active);
+        cholqr2<T>(t1, t2, Vb + (int64_t)(j + 1) * blk, d_active, gwb.as<double>());
         dbg(st, "V_j+1", Vb + (int64_t)(j + 1) * blk, n * ldc * 2, cyc, j);
         dbg(st, "Hsub", reinterpret_cast<double*>(Racc.p), (int64_t)ns * m0 * m0 * 2, cyc, j);
         launch_store_subdiag(st, ns, m0, j, ldh, d_active, Racc.as<cd>(), H.as<cd>());
@@ -482,6 +528,7 @@ struct Engine::Impl {
         dbg(st, "lsq_res", la.res, (int64_t)ns * m0, cyc, j);
         jdone = j + 1;
         const std::vector<int> act = d2h_ints(d_active, ns);
+        note(d_active, act);
         if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) break;
       }
       launch_lsq_finish(st, la);
@@ -491,7 +538,7 @@ struct Engine::Impl {
       dbg(st, "Yq", Yq.as<T>(), (int64_t)ns * jdone * m2 * m0, cyc);
       // Q += Re sum_s V_s[0..jdone) Yq_s
       ApplyArgs aq{n,  m2, m0, 1, ns * jdone, jdone, Vb, 2 * ldc, 0, m2, blk, Yq.p, 0, Qd, m0, 0,
-                   1.0, 1.0, nullptr, d_run};
+                   1.0, 1.0, nullptr, d_run, KC_QACC};
       launch_apply<T, double>(st, aq);
       dbg(st, "Q", Qd, n * m0, cyc);
       const std::vector<int> it = d2h_ints(d_iters, ns);
@@ -507,6 +554,7 @@ struct Engine::Impl {
       if (!any) break;
       // restart residual: T1_s = sum_b V_s[b] u_s[b], b = 0..jdone
       h2d(d_cont, cont.data(), ns * sizeof(int));
+      note(d_cont, cont);
       ApplyArgs ar{n, m2, m2, ns, jdone + 1, jdone + 1, Vb, 2 * ldc, m2, 0, blk, Uc.p,
                    (int64_t)(jdone + 1) * m2 * m2, t1, 2 * ldc, m2, 1.0, 0.0, d_cont, nullptr};
       launch_apply<T, T>(st, ar);
@@ -705,8 +753,8 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         (void)hipEventElapsedTime(&ms_now, e0, en);
         (void)hipEventDestroy(en);
       }
-      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d t=%.2fs\n", it + 1, stats.rf, stats.m, mx,
-              ms_now * 1e-3);
+      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld t=%.2fs\n", it + 1, stats.rf,
+              stats.m, mx, (long long)I.reorth_steps, ms_now * 1e-3);
       if (verbose2) {
         std::vector<double> etah(m0), rhoh(m0);
         IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));

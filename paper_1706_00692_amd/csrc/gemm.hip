@@ -356,6 +356,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   rps = (rps + KC - 1) / KC * KC;
   const dim3 grid(nsplit, ntp * ntq, items), block(256);
   T* part = static_cast<T*>(partial);
+  KernelTimer* kt = current_timer();
+  const int tok = kt ? kt->begin(st) : -1;
   switch (tb) {
     case 1: hipLaunchKernelGGL((k_gram<T, 1>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
     case 2: hipLaunchKernelGGL((k_gram<T, 2>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
@@ -370,6 +372,15 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     default: throw Error{IFEAST_ERR_INVALID_ARG, "gram: unsupported tile"};
   }
   IF_HIP(hipGetLastError());
+  if (kt) {
+    // algorithmic: every active item's A block once; B once per item, or once per shift when the
+    // blocks of a shift share it (b_i == 0); the self Gram (A == B, one block) reads one block
+    const int nact = kt->count(g.active, g.ns);
+    const double eff = (double)nact * g.ni;
+    const double ra = (double)g.n * g.PW * sizeof(T) * eff;
+    const double rb = (g.A == g.B && g.ni == 1) ? 0.0 : (double)g.n * g.QW * sizeof(T) * (g.b_i == 0 ? nact : eff);
+    kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, ra + rb);
+  }
   const int64_t total = (int64_t)items * g.PW * g.QW;
   hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
                      g.PW, g.QW, g.ni, g.active, part, g.G);
@@ -385,6 +396,8 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   const int64_t nrt = (a.n + 127) / 128;
   const int per = (int)((nrt + kXcds - 1) / kXcds);
   const dim3 grid(per * kXcds, ntq, a.items), block(256);
+  KernelTimer* kt = current_timer();
+  const int tok = kt ? kt->begin(st) : -1;
   switch (tbq) {
     case 1: hipLaunchKernelGGL((k_apply<T, TO, 1>), grid, block, 0, st, a, per); break;
     case 2: hipLaunchKernelGGL((k_apply<T, TO, 2>), grid, block, 0, st, a, per); break;
@@ -399,6 +412,15 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
     default: throw Error{IFEAST_ERR_INVALID_ARG, "apply: unsupported tile"};
   }
   IF_HIP(hipGetLastError());
+  if (kt) {
+    // algorithmic: each active (item, block) reads its n x KW slab once; O is written once per
+    // active item (and read first when beta != 0)
+    const double it = kt->count(a.active_item, a.items);
+    const double bl = a.active_sb ? (double)kt->count(a.active_sb, a.nb / a.nbi) * a.nbi : (double)a.nb;
+    const double fl = 2.0 * a.n * a.KW * a.OW * it * bl;
+    const double by = (double)a.n * a.KW * sizeof(T) * it * bl + (double)a.n * a.OW * sizeof(TO) * it * (a.beta != 0.0 ? 2 : 1);
+    kt->end(tok, a.kclass, fl, by);
+  }
 }
 
 template size_t gram_partial_bytes<float>(int64_t, int, int, int);

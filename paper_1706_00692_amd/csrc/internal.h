@@ -58,12 +58,63 @@ struct DevBuf {
 
 }  // namespace ifeast
 
+namespace ifeast {
+// Autotuned shifted-SpMM schedule key: block width (complex columns), element size, B present.
+struct SpmmKey {
+  int width, elem;
+  bool hasB;
+  bool operator<(const SpmmKey& o) const {
+    return width != o.width ? width < o.width : elem != o.elem ? elem < o.elem : hasB < o.hasB;
+  }
+};
+}  // namespace ifeast
+
 struct ifeast_matrix {
   int64_t n = 0, nnz = 0;
   ifeast::DevBuf rowptr, colind, val, valf;  // int32, int32, double, float
   double norm1 = 0.0;                        // max column sum of |a_ij|
   int device = 0;
+  mutable std::mutex tune_mu;                        // guards sched
+  mutable std::map<ifeast::SpmmKey, int> sched;      // autotuned SpMM schedule per product shape
 };
+
+namespace ifeast {
+// Per-kernel-class timing with HIP events on the launching stream.  When a
+// timer is installed for the calling thread, the launchers bracket each
+// launch of the classes below with two events and account its algorithmic
+// FLOPs and HBM bytes (active shifts only, from the host-known population of
+// each device flag array registered with set_count).
+enum KClass { KC_SPMM = 0, KC_GRAM = 1, KC_UPDATE = 2, KC_QACC = 3, KC_OUTER = 4, KC_N = 5 };
+struct KernelStat {
+  int64_t launches = 0;
+  double seconds = 0.0, flops = 0.0, bytes = 0.0;
+};
+struct KernelTimer {
+  KernelStat acc[KC_N];
+  std::map<const int*, int> counts;
+  struct Pending {
+    int ev;  // index of the start event; ev + 1 ends it
+    int cls;
+    double flops, bytes;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pend;
+  int next = 0;
+  ~KernelTimer();
+  int begin(hipStream_t st);
+  void end(int tok, int cls, double flops, double bytes);
+  void flush();
+  void set_count(const int* flags, int cnt) { counts[flags] = cnt; }
+  int count(const int* flags, int full) const {
+    if (flags == nullptr) return full;
+    auto it = counts.find(flags);
+    return it == counts.end() ? full : it->second;
+  }
+  hipStream_t stream = nullptr;
+};
+KernelTimer*& current_timer();
+const char* spmm_schedule_name(int idx);
+}  // namespace ifeast
 
 namespace ifeast {
 struct Server;  // serving loop (serve.cpp)
@@ -71,6 +122,8 @@ struct Server;  // serving loop (serve.cpp)
 
 struct ifeast_ctx {
   int device = 0;
+  bool timing = false;
+  ifeast::KernelStat kstats[ifeast::KC_N];
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
@@ -107,6 +160,7 @@ struct GramArgs {
   int64_t ldb, b_s, b_i;
   const int* active;  // per s, may be null
   double* G;          // ns*ni*PW*QW
+  int kclass = KC_GRAM;  // timing class (KC_GRAM or KC_OUTER)
 };
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes);
@@ -131,6 +185,7 @@ struct ApplyArgs {
   double alpha, beta;
   const int* active_item;  // per item, may be null
   const int* active_sb;    // per sb, may be null
+  int kclass = KC_UPDATE;  // timing class (KC_UPDATE or KC_QACC)
 };
 template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a);
@@ -149,6 +204,11 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
 template <class T>
 void launch_cgs_combine(hipStream_t st, int ns, int ni, int m0, int j, int ldh, const double* G,
                         const int* active, cd* H, T* Hr, int accumulate);
+
+// need[s] = 1 when the block of shift s kept less than eta of some column's norm in the
+// first Gram-Schmidt pass (G = W1^H W1 as a real-view Gram, H column block j).
+void launch_reorth_check(hipStream_t st, int ns, int m0, int j, int ldh, double eta, const double* G,
+                         const int* active, const cd* H, int* need);
 
 // Write Racc (m0 x m0 complex) into H[s] at block (row j+1, col j).
 void launch_store_subdiag(hipStream_t st, int ns, int m0, int j, int ldh, const int* active, const cd* Racc, cd* H);

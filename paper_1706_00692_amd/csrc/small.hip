@@ -197,6 +197,33 @@ __global__ void k_cgs_combine(int ns, int ni, int m0, int j, int ldh, const doub
   store_realified(Hr + (int64_t)item * m2 * m2, m2, a, b, c);
 }
 
+// Per shift: does the block after one classical Gram-Schmidt pass need a second one?
+// ||W0 e_c||^2 = ||H e_c||^2 + ||W1 e_c||^2 (V orthonormal); a second pass is needed when some
+// live column kept less than a fraction eta of its norm.  G = W1^H W1 (real view), H column
+// block j of Hbar (rows 0..(j+1) m0).
+__global__ void k_reorth_check(int m0, int j, int ldh, double eta2, const double* __restrict__ G,
+                               const int* __restrict__ active, const c2* __restrict__ H, int* __restrict__ need) {
+  const int s = blockIdx.x;
+  if (active != nullptr && active[s] == 0) {
+    if (threadIdx.x == 0) need[s] = 0;
+    return;
+  }
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int m2 = 2 * m0, kk = ldh / m0 - 1;
+  const double* Gs = G + (int64_t)s * m2 * m2;
+  const c2* Hs = H + (int64_t)s * ldh * kk * m0 + (int64_t)j * m0 * ldh;
+  for (int c = threadIdx.x; c < m0; c += blockDim.x) {
+    const double w1 = Gs[(2 * c) * m2 + 2 * c] + Gs[(2 * c + 1) * m2 + 2 * c + 1];
+    double h = 0.0;
+    for (int r = 0; r < (j + 1) * m0; ++r) h += cabs2(Hs[r + (int64_t)c * ldh]);
+    if (w1 > 1e-30 && w1 < eta2 * (w1 + h)) atomicOr(&any, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) need[s] = any;
+}
+
 __global__ void k_store_subdiag(int ns, int m0, int j, int ldh, const int* __restrict__ active,
                                 const c2* __restrict__ Racc, c2* __restrict__ H) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -934,6 +961,13 @@ template void launch_cgs_combine<float>(hipStream_t, int, int, int, int, int, co
                                         float*, int);
 template void launch_cgs_combine<double>(hipStream_t, int, int, int, int, int, const double*, const int*, cd*,
                                          double*, int);
+
+void launch_reorth_check(hipStream_t st, int ns, int m0, int j, int ldh, double eta, const double* G,
+                         const int* active, const cd* H, int* need) {
+  hipLaunchKernelGGL(k_reorth_check, dim3(ns), dim3(128), 0, st, m0, j, ldh, eta * eta, G, active,
+                     reinterpret_cast<const c2*>(H), need);
+  IF_HIP(hipGetLastError());
+}
 
 void launch_store_subdiag(hipStream_t st, int ns, int m0, int j, int ldh, const int* active, const cd* Racc,
                           cd* H) {

@@ -15,6 +15,9 @@
 // XCD and hit its L2.
 #include "internal.h"
 
+#include <cstdio>
+#include <cstdlib>
+
 namespace ifeast {
 
 namespace {
@@ -54,7 +57,37 @@ template <class V> __device__ inline V vzero();
 template <> __device__ inline float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 template <> __device__ inline double2 vzero<double2>() { return make_double2(0.0, 0.0); }
 
-template <class T, bool HAS_B>
+// acc[u] += sum over the CSR entries [e0, e1) of val[e] * V[col[e]] at vector column vb + 64u.
+// KC entries are fetched per round (row indices and values are wave-uniform scalar loads), then
+// U x KC independent 16-byte loads are issued before any of them is used: a 7-point row is one
+// round of KC = 8.  Entries past e1 repeat the last column with value 0 so every load stays in bounds.
+template <class T, class V16, int U, int KC>
+__device__ inline void row_gather(int e0, int e1, const int* __restrict__ ci, const T* __restrict__ va,
+                                  const V16* __restrict__ Vv, int nvec, int vb, const bool (&on)[U], V16 (&acc)[U]) {
+  for (int e = e0; e < e1; e += KC) {
+    int c[KC];
+    T a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int ek = e + k < e1 ? e + k : e1 - 1;
+      c[k] = ci[ek];
+      a[k] = e + k < e1 ? va[ek] : T(0);
+    }
+    V16 x[U][KC];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < KC; ++k) x[u][k] = on[u] ? Vv[(int64_t)c[k] * nvec + vb + 64 * u] : vzero<V16>();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < KC; ++k) axpy(a[k], x[u][k], acc[u]);
+  }
+}
+
+// One wavefront per row; lane l handles the 16-byte vectors vb + 64u (u < U) of the row, looping
+// over the row in strides of 64 U vectors.
+template <class T, bool HAS_B, int U, int KC>
 __global__ __launch_bounds__(256) void k_spmm_shifted(int n, int per, const int* __restrict__ rp,
                                                       const int* __restrict__ ci, const T* __restrict__ va,
                                                       const int* __restrict__ brp, const int* __restrict__ bci,
@@ -68,25 +101,34 @@ __global__ __launch_bounds__(256) void k_spmm_shifted(int n, int per, const int*
   int row = lb * 4 + wave;
   if (row >= n) return;
   row = __builtin_amdgcn_readfirstlane(row);
-  const int ldc = ns * m0;  // complex numbers per row
-  const int nvec = ldc / C;  // 16-byte vectors per row
+  const int nvec = ns * m0 / C;  // 16-byte vectors per row
   const V16* __restrict__ Vv = reinterpret_cast<const V16*>(V);
   V16* __restrict__ Wv = reinterpret_cast<V16*>(W);
   const int e0 = rp[row], e1 = rp[row + 1];
-  for (int vc = lane; vc < nvec; vc += 64) {
-    const int s = (vc * C) / m0;
-    if (active != nullptr && active[s] == 0) continue;
-    V16 acc = vzero<V16>();
-    for (int e = e0; e < e1; ++e) axpy(va[e], Vv[(int64_t)ci[e] * nvec + vc], acc);
-    V16 self;
-    if (HAS_B) {
-      self = vzero<V16>();
-      const int f0 = brp[row], f1 = brp[row + 1];
-      for (int e = f0; e < f1; ++e) axpy(bva[e], Vv[(int64_t)bci[e] * nvec + vc], self);
-    } else {
-      self = Vv[(int64_t)row * nvec + vc];
+  for (int vb = lane; vb < nvec; vb += 64 * U) {
+    bool on[U];
+    int sh[U];
+    V16 acc[U], self[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int vc = vb + 64 * u;
+      sh[u] = vc < nvec ? (vc * C) / m0 : 0;
+      on[u] = vc < nvec && (active == nullptr || active[sh[u]] != 0);
+      acc[u] = vzero<V16>();
+      self[u] = vzero<V16>();
     }
-    Wv[(int64_t)row * nvec + vc] = zs_minus(zs[2 * s], zs[2 * s + 1], self, acc);
+    row_gather<T, V16, U, KC>(e0, e1, ci, va, Vv, nvec, vb, on, acc);
+    if (HAS_B) {
+      row_gather<T, V16, U, KC>(brp[row], brp[row + 1], bci, bva, Vv, nvec, vb, on, self);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (on[u]) self[u] = Vv[(int64_t)row * nvec + vb + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (on[u])
+        Wv[(int64_t)row * nvec + vb + 64 * u] = zs_minus(zs[2 * sh[u]], zs[2 * sh[u] + 1], self[u], acc[u]);
   }
 }
 
@@ -109,7 +151,43 @@ __global__ __launch_bounds__(256) void k_spmm_real(int n, int per, const int* __
   }
 }
 
+// Schedules the autotuner chooses from: (U, KC) = vectors per lane per pass, CSR entries per round.
+struct Sched {
+  int U, KC;
+};
+constexpr Sched kSched[] = {{1, 8}, {2, 8}, {3, 8}, {5, 4}, {2, 4}, {4, 4}, {1, 4}, {3, 4}};
+constexpr int kNSched = sizeof(kSched) / sizeof(kSched[0]);
+
+template <class T, bool HAS_B>
+void launch_sched(int idx, hipStream_t st, dim3 grid, int n, int per, const int* rp, const int* ci, const T* va,
+                  const int* brp, const int* bci, const T* bva, int ns, int m0, const T* zs, const int* active,
+                  const T* V, T* W) {
+#define IF_SPMM_CASE(I, U_, KC_)                                                                          \
+  case I:                                                                                                 \
+    hipLaunchKernelGGL((k_spmm_shifted<T, HAS_B, U_, KC_>), grid, dim3(256), 0, st, n, per, rp, ci, va,  \
+                       brp, bci, bva, ns, m0, zs, active, V, W);                                          \
+    break;
+  switch (idx) {
+    IF_SPMM_CASE(0, 1, 8)
+    IF_SPMM_CASE(1, 2, 8)
+    IF_SPMM_CASE(2, 3, 8)
+    IF_SPMM_CASE(3, 5, 4)
+    IF_SPMM_CASE(4, 2, 4)
+    IF_SPMM_CASE(5, 4, 4)
+    IF_SPMM_CASE(6, 1, 4)
+    IF_SPMM_CASE(7, 3, 4)
+    default:
+      throw Error{IFEAST_ERR_INVALID_ARG, "unknown SpMM schedule"};
+  }
+#undef IF_SPMM_CASE
+}
+
 }  // namespace
+
+const char* spmm_schedule_name(int idx) {
+  static const char* names[] = {"U1xK8", "U2xK8", "U3xK8", "U5xK4", "U2xK4", "U4xK4", "U1xK4", "U3xK4"};
+  return idx >= 0 && idx < kNSched ? names[idx] : "?";
+}
 
 template <class T>
 void launch_spmm_shifted(hipStream_t st, const ifeast_matrix* A, const ifeast_matrix* B, int ns, int m0,
@@ -117,19 +195,78 @@ void launch_spmm_shifted(hipStream_t st, const ifeast_matrix* A, const ifeast_ma
   const int64_t n = A->n;
   const int64_t nblk = (n + 3) / 4;
   const int per = xcd_per(nblk);
-  const dim3 grid(per * kXcds), block(256);
+  const dim3 grid(per * kXcds);
   const T* va = (sizeof(T) == 4) ? reinterpret_cast<const T*>(A->valf.p) : reinterpret_cast<const T*>(A->val.p);
-  if (B == nullptr) {
-    hipLaunchKernelGGL((k_spmm_shifted<T, false>), grid, block, 0, st, (int)n, per, A->rowptr.as<int>(),
-                       A->colind.as<int>(), va, nullptr, nullptr, nullptr, ns, m0, zs, active, V, W);
-  } else {
-    const T* vb =
-        (sizeof(T) == 4) ? reinterpret_cast<const T*>(B->valf.p) : reinterpret_cast<const T*>(B->val.p);
-    hipLaunchKernelGGL((k_spmm_shifted<T, true>), grid, block, 0, st, (int)n, per, A->rowptr.as<int>(),
-                       A->colind.as<int>(), va, B->rowptr.as<int>(), B->colind.as<int>(), vb, ns, m0, zs, active,
-                       V, W);
+  const int* brp = B ? B->rowptr.as<int>() : nullptr;
+  const int* bci = B ? B->colind.as<int>() : nullptr;
+  const T* bva = B ? ((sizeof(T) == 4) ? reinterpret_cast<const T*>(B->valf.p) : reinterpret_cast<const T*>(B->val.p))
+                   : nullptr;
+  auto run = [&](int idx) {
+    if (B == nullptr)
+      launch_sched<T, false>(idx, st, grid, (int)n, per, A->rowptr.as<int>(), A->colind.as<int>(), va, nullptr,
+                             nullptr, nullptr, ns, m0, zs, active, V, W);
+    else
+      launch_sched<T, true>(idx, st, grid, (int)n, per, A->rowptr.as<int>(), A->colind.as<int>(), va, brp, bci,
+                            bva, ns, m0, zs, active, V, W);
+    IF_HIP(hipGetLastError());
+  };
+  // Autotuner: the first product of a given (matrix, B, width, precision) times every schedule on the
+  // caller's stream (each launch computes the same W) and keeps the fastest for this matrix.
+  const SpmmKey key{ns * m0, (int)sizeof(T), B != nullptr};
+  int idx = -1;
+  {
+    std::lock_guard<std::mutex> lk(A->tune_mu);
+    auto it = A->sched.find(key);
+    if (it != A->sched.end()) idx = it->second;
   }
-  IF_HIP(hipGetLastError());
+  if (idx < 0) {
+    const char* forced = getenv("IFEAST_SPMM_SCHED");
+    if (forced != nullptr) {
+      idx = atoi(forced);
+      IF_REQUIRE(idx >= 0 && idx < kNSched, "IFEAST_SPMM_SCHED out of range");
+    } else {
+      hipEvent_t e0, e1;
+      IF_HIP(hipEventCreate(&e0));
+      IF_HIP(hipEventCreate(&e1));
+      float best = 1e30f;
+      std::vector<float> times(kNSched, 0.f);
+      for (int c = 0; c < kNSched; ++c) {
+        run(c);  // warm
+        IF_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; ++r) run(c);
+        IF_HIP(hipEventRecord(e1, st));
+        IF_HIP(hipEventSynchronize(e1));
+        IF_HIP(hipEventElapsedTime(&times[c], e0, e1));
+        if (times[c] < best) {
+          best = times[c];
+          idx = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (getenv("IFEAST_VERBOSE") != nullptr) {
+        fprintf(stderr, "[ifeast] spmm autotune n=%lld width=%d %s:", (long long)n, ns * m0,
+                sizeof(T) == 4 ? "c32" : "c64");
+        for (int c = 0; c < kNSched; ++c) fprintf(stderr, " %s=%.1fus", spmm_schedule_name(c), times[c] * 1e3f / 3);
+        fprintf(stderr, " -> %s\n", spmm_schedule_name(idx));
+      }
+    }
+    std::lock_guard<std::mutex> lk(A->tune_mu);
+    A->sched[key] = idx;
+  }
+  KernelTimer* kt = current_timer();
+  const int tok = kt ? kt->begin(st) : -1;
+  run(idx);
+  if (kt) {
+    // algorithmic bytes: the CSR of A (and B) once, V read once and W written once for active shifts
+    const int nact = kt->count(active, ns);
+    const double csr = (double)(n + 1) * 4 + (double)A->nnz * (4 + sizeof(T)) +
+                       (B ? (double)(n + 1) * 4 + (double)B->nnz * (4 + sizeof(T)) : 0.0);
+    const double vw = 2.0 * (double)n * nact * m0 * 2 * sizeof(T);
+    const double fl = (double)nact * m0 * 8.0 * ((double)A->nnz + (B ? (double)B->nnz : (double)n)) +
+                      6.0 * (double)n * nact * m0;
+    kt->end(tok, KC_SPMM, fl, csr + vw);
+  }
 }
 
 template void launch_spmm_shifted<float>(hipStream_t, const ifeast_matrix*, const ifeast_matrix*, int, int,

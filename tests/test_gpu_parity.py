@@ -75,6 +75,62 @@ def test_spmm_shifted_parity(ctx, torch_cuda, prec, case):
         assert np.abs(got[:, sl] - want).max() <= tol * scale * 10, (s, np.abs(got[:, sl] - want).max() / scale)
 
 
+@pytest.mark.parametrize("sched", range(8))
+def test_spmm_every_schedule(torch_cuda, sched, monkeypatch):
+    """Each autotuner candidate (forced through IFEAST_SPMM_SCHED on a fresh matrix) against the oracle,
+    on widths that leave partial passes: 3 x 18 complex columns (FP32: 27 vectors, FP64: 54) and B present."""
+    import paper_1706_00692_amd as pk
+
+    torch = torch_cuda
+    monkeypatch.setenv("IFEAST_SPMM_SCHED", str(sched))
+    c = pk.Context(0)
+    try:
+        for prec, dt, tol in [(pk.PREC_MIXED, torch.complex64, 2e-5), (pk.PREC_FP64, torch.complex128, 1e-13)]:
+            for A, B, m0, ns in [(W.spd27(7, 31), W.mass27(7, 32), 18, 3), (W.laplacian_2d(19), None, 80, 5)]:
+                z = np.array([0.3 + 0.2j, 1.1 + 0.05j, -0.4 + 1.5j, 0.7 + 0.01j, 2 + 3j])[:ns]
+                V = _rand_block(A.n, ns * m0, 17)
+                Vd = _cplx(torch, V, dt)
+                Wd = torch.zeros_like(Vd)
+                Am = c.matrix(A)
+                Bm = None if B is None else c.matrix(B)
+                c.spmm_shifted(Am, Bm, prec, z, m0, Vd, Wd)
+                torch.cuda.synchronize()
+                got = Wd.cpu().numpy()
+                for s in range(ns):
+                    sl = slice(s * m0, (s + 1) * m0)
+                    want = O.shifted_operator(A.to_scipy(), None if B is None else B.to_scipy(), z[s])(V[:, sl])
+                    err = np.abs(got[:, sl] - want).max() / np.abs(want).max()
+                    assert err <= tol, (sched, prec, A.n, s, err)
+    finally:
+        c.close()
+
+
+def test_kernel_timing_accounting(torch_cuda):
+    """Timed SpMM launches: count and algorithmic bytes per launch (CSR once, V read once, W written once)."""
+    import paper_1706_00692_amd as pk
+
+    torch = torch_cuda
+    c = pk.Context(0)
+    try:
+        A, m0, ns = W.laplacian_2d(30), 32, 4
+        Am = c.matrix(A)
+        Vd = _cplx(torch, _rand_block(A.n, ns * m0, 3), torch.complex64)
+        Wd = torch.empty_like(Vd)
+        z = [0.5 + 0.1j] * ns
+        c.spmm_shifted(Am, None, pk.PREC_MIXED, z, m0, Vd, Wd)  # autotune, untimed
+        c.set_timing(True)
+        for _ in range(3):
+            c.spmm_shifted(Am, None, pk.PREC_MIXED, z, m0, Vd, Wd)
+        st = c.kernel_stats()
+        c.set_timing(False)
+        assert st["spmm"]["launches"] == 3 and st["spmm"]["seconds"] > 0
+        want = (A.n + 1) * 4 + A.nnz * 8 + 2 * A.n * ns * m0 * 8
+        assert st["spmm"]["bytes"] == pytest.approx(3 * want, rel=1e-12)
+        assert st["gram"]["launches"] == 0
+    finally:
+        c.close()
+
+
 def test_spmm_full_size_sampled(ctx, torch_cuda):
     """64^3 Laplacian + potential, 8 shifts x 80 columns, complex FP32: sampled rows against the oracle."""
     import paper_1706_00692_amd as pk
@@ -127,13 +183,13 @@ def _oracle_filter(prob, lam, X, R, k, cycles):
     return O.quad_accumulate(X, lam, D, z, w, half)
 
 
-def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles):
+def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles, reorth_eta=0.0):
     import paper_1706_00692_amd as pk
 
     Am = ctx.matrix(prob.A)
     Bm = None if prob.B is None else ctx.matrix(prob.B)
     p = pk.params_struct(prob.m0, max_outer=1, max_inner=k, max_cycles=cycles, alpha=0.0, tol=1e-9,
-                         precision=prec)
+                         precision=prec, reorth_eta=reorth_eta)
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     ld = torch.from_numpy(np.ascontiguousarray(lam)).cuda()
     Rd = torch.from_numpy(np.ascontiguousarray(R)).cuda()
@@ -143,14 +199,15 @@ def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles):
     return Qd.cpu().numpy(), iters
 
 
-@pytest.mark.parametrize("cycles", [1, 3])
-def test_filter_parity_fp64(ctx, torch_cuda, cycles):
+@pytest.mark.parametrize("cycles,reorth", [(1, 0.0), (3, 0.0), (1, 2.0), (3, 2.0)])
+def test_filter_parity_fp64(ctx, torch_cuda, cycles, reorth):
+    """reorth 0: the default selective second Gram-Schmidt pass; 2.0: always two passes."""
     import paper_1706_00692_amd as pk
 
     prob = W.config1()
     lam, X, R, r = _first_iterate(prob)
     want = _oracle_filter(prob, lam, X, R, prob.max_inner, cycles)
-    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, prob.max_inner, cycles)
+    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, prob.max_inner, cycles, reorth)
     assert list(iters) == [prob.max_inner * cycles] * 8
     err = np.abs(got - want).max() / np.abs(want).max()
     assert err <= 1e-9, err

@@ -75,6 +75,25 @@ def roofline_of(name, k, mixed):
             "algorithmic_flops_per_launch": k["flops_per_launch"]}
 
 
+def copy_calibration(torch, mib=1024, reps=3):
+    """A plain device copy of known size (outside the timed region): HBM counters of profiling runs
+    are scaled by what they read for it.  Returns GB/s."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    return {"bytes_read": mib << 20, "bytes_written": mib << 20, "GBs": 2 * (mib << 20) / sec / 1e9}
+
+
 def cpu_baseline(prob, gpu_res, budget_s=20.0):
     """Oracle timed on a bounded sample: whole GMRES(k) cycles of single shifts at full size,
     extrapolated to the cycles the GPU solve ran."""
@@ -200,6 +219,8 @@ def main():
             if len(a) == len(b):
                 out["mixed_vs_fp64_max_rel_eig_diff"] = float(np.max(np.abs(a - b) / np.abs(b)))
 
+    out["copy_calibration"] = copy_calibration(torch)
+    log(f"copy calibration: {out['copy_calibration']}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, res[0])
         log(f"cpu baseline: {out['cpu_baseline']}")

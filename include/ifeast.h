@@ -99,8 +99,10 @@ typedef struct {
   double tol;          /* eigen-residual tolerance on ||R_F|| */
   double spurious_tau; /* a Ritz pair inside C counts when its filter gain >= tau |rho_hat(lambda)| */
   double reorth_eta;   /* block Gram-Schmidt in the Arnoldi step: a second classical pass runs for a shift
-                          when some column kept less than this fraction of its norm in the first one;
-                          0 selects 0.1, >= 1 always runs two passes */
+                          when some column kept less than this fraction of its norm in the first one,
+                          and the block is normalised by one Cholesky-QR pass when its Gram is certified
+                          well conditioned (two passes otherwise); 0 selects 0.1; >= 1 always runs two
+                          Gram-Schmidt and two Cholesky-QR passes */
   int precision;       /* IFEAST_PREC_* */
   int problem;         /* IFEAST_PROBLEM_* */
   int inner_guess;     /* IFEAST_GUESS_* */

@@ -274,6 +274,11 @@ struct Engine::Impl {
   int* d_cdone = nullptr;   // ns
   int* d_cls = nullptr;     // m0 flags
   int* d_need = nullptr;    // ns flags: second Gram-Schmidt pass needed
+  int* d_single = nullptr;  // ns flags: one Cholesky-QR pass is enough
+  int* d_two = nullptr;     // ns flags: two Cholesky-QR passes
+  double single_gersh = 0.5;
+  double dead_thr = 1e-280;
+  int64_t single_steps = 0; // shift-steps normalised with one Cholesky-QR pass
   double reorth_eta = 0.1;  // keep-fraction below which a second pass runs (>= 1: always)
   int64_t reorth_steps = 0; // shift-steps that ran a second pass
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
@@ -326,6 +331,8 @@ struct Engine::Impl {
     d_cdone = f + 256;
     d_cls = f + 320;
     d_need = f + 448;
+    d_single = f + 512;
+    d_two = f + 576;
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
     // stale basis blocks of shifts that stopped early are multiplied by zero
@@ -469,6 +476,10 @@ struct Engine::Impl {
     std::vector<int> run(ns, 1), total_iters(ns, 0);
     LsqArgs la = lsq_args();
     reorth_eta = p.reorth_eta > 0.0 ? p.reorth_eta : 0.1;
+    // one Cholesky-QR pass leaves the basis orthonormal to about kappa^2 u: kappa <= 9 in FP32
+    // (GMRES steps that stop at a relative residual of alpha), kappa <= 3 in FP64
+    single_gersh = sizeof(T) == 4 ? 0.8 : 0.5;
+    dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
     for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
       h2d(d_run, run.data(), ns * sizeof(int));
       h2d(d_active, run.data(), ns * sizeof(int));
@@ -497,30 +508,46 @@ struct Engine::Impl {
           launch_apply<T, T>(st, ap);
         };
         cgs_pass(d_active, 0);
-        if (reorth_eta >= 1.0) {
+        const bool always = reorth_eta >= 1.0;
+        if (always) {
           cgs_pass(d_active, 1);
           reorth_steps += ns;
         }
-        // Gram of the projected block; it is also Cholesky-QR's first Gram when no second pass runs
-        // (its own buffer: a second pass reuses gred for the coefficients of every block)
+        // Gram of the projected block (its own buffer: a second pass reuses gred); it is the
+        // first Cholesky-QR Gram of every shift that needs no second Gram-Schmidt pass
         GramArgs gw{n, m2, m2, ns, 1, t1, 2 * ldc, m2, 0, t1, 2 * ldc, m2, 0, d_active, gwb.as<double>()};
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-        if (reorth_eta < 1.0) {
-          launch_reorth_check(st, ns, m0, j, ldh, reorth_eta, gwb.as<double>(), d_active, H.as<cd>(), d_need);
-          const std::vector<int> need = d2h_ints(d_need, ns);
-          const int nneed = (int)std::count_if(need.begin(), need.end(), [](int v) { return v != 0; });
-          if (nneed > 0) {
-            note(d_need, need);
-            cgs_pass(d_need, 1);
-            GramArgs gn = gw;
-            gn.active = d_need;
-            launch_gram<T>(st, gn, gpart.p, gpart.bytes);
-            reorth_steps += nneed;
-          }
+        launch_orth_check(st, ns, m0, j, ldh, always ? 0.0 : reorth_eta, always ? -1.0 : single_gersh, dead_thr,
+                          gwb.as<double>(), d_active, H.as<cd>(), d_need, d_single, d_two);
+        const std::vector<int> fl = d2h_ints(d_need, 3 * 64);
+        const std::vector<int> need(fl.begin(), fl.begin() + ns), single(fl.begin() + 64, fl.begin() + 64 + ns),
+            two(fl.begin() + 128, fl.begin() + 128 + ns);
+        auto count = [](const std::vector<int>& v) { return (int)std::count_if(v.begin(), v.end(), [](int x) { return x != 0; }); };
+        if (count(need) > 0) {
+          note(d_need, need);
+          cgs_pass(d_need, 1);
+          GramArgs gn = gw;
+          gn.active = d_need;
+          launch_gram<T>(st, gn, gpart.p, gpart.bytes);
+          reorth_steps += count(need);
         }
-        // V_{j+1} H_{j+1,j} = qr(W)
+        // V_{j+1} H_{j+1,j} = qr(W): one unshifted Cholesky-QR pass where the Gram is certified
+        // well conditioned, two passes (the first shifted) elsewhere
+        T* dst = Vb + (int64_t)(j + 1) * blk;
         dbg(st, "W_cgs", t1, n * ldc * 2, cyc, j);
-        cholqr2<T>(t1, t2, Vb + (int64_t)(j + 1) * blk, d_active, gwb.as<double>());
+        if (count(single) > 0) {
+          note(d_single, single);
+          launch_cholqr_factor<T>(st, ns, m0, gwb.as<double>(), 0.0, d_single, Tinv.as<T>(), Racc.as<cd>(), 0,
+                                  chol.as<cd>());
+          ApplyArgs ap{n, m2, m2, ns, 1, 1, t1, 2 * ldc, m2, 0, 0, Tinv.p, (int64_t)m2 * m2, dst, 2 * ldc, m2,
+                       1.0, 0.0, d_single, nullptr};
+          launch_apply<T, T>(st, ap);
+          single_steps += count(single);
+        }
+        if (count(two) > 0) {
+          note(d_two, two);
+          cholqr2<T>(t1, t2, dst, d_two, gwb.as<double>());
+        }
         dbg(st, "V_j+1", Vb + (int64_t)(j + 1) * blk, n * ldc * 2, cyc, j);
         dbg(st, "Hsub", reinterpret_cast<double*>(Racc.p), (int64_t)ns * m0 * m0 * 2, cyc, j);
         launch_store_subdiag(st, ns, m0, j, ldh, d_active, Racc.as<cd>(), H.as<cd>());
@@ -753,8 +780,8 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         (void)hipEventElapsedTime(&ms_now, e0, en);
         (void)hipEventDestroy(en);
       }
-      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld t=%.2fs\n", it + 1, stats.rf,
-              stats.m, mx, (long long)I.reorth_steps, ms_now * 1e-3);
+      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld t=%.2fs\n", it + 1,
+              stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps, ms_now * 1e-3);
       if (verbose2) {
         std::vector<double> etah(m0), rhoh(m0);
         IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));

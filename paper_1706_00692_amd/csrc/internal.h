@@ -205,10 +205,13 @@ template <class T>
 void launch_cgs_combine(hipStream_t st, int ns, int ni, int m0, int j, int ldh, const double* G,
                         const int* active, cd* H, T* Hr, int accumulate);
 
-// need[s] = 1 when the block of shift s kept less than eta of some column's norm in the
-// first Gram-Schmidt pass (G = W1^H W1 as a real-view Gram, H column block j).
-void launch_reorth_check(hipStream_t st, int ns, int m0, int j, int ldh, double eta, const double* G,
-                         const int* active, const cd* H, int* need);
+// Per shift s, from the Gram G of the block after one Gram-Schmidt pass (real view) and
+// that pass's coefficients (column block j of Hbar): need[s] = a second pass is needed
+// (some column kept less than eta of its norm); single[s] = one unshifted Cholesky-QR pass
+// is enough (no second pass, no negligible column, Gershgorin radius of the scaled Gram
+// <= gersh); twopass[s] = active and not single.
+void launch_orth_check(hipStream_t st, int ns, int m0, int j, int ldh, double eta, double gersh, double dead_thr,
+                       const double* G, const int* active, const cd* H, int* need, int* single, int* twopass);
 
 // Write Racc (m0 x m0 complex) into H[s] at block (row j+1, col j).
 void launch_store_subdiag(hipStream_t st, int ns, int m0, int j, int ldh, const int* active, const cd* Racc, cd* H);

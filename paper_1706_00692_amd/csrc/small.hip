@@ -17,6 +17,8 @@
 //  * classify: membership, filter-gain test and ||R_F|| (Algorithm 2, step 4).
 #include "internal.h"
 
+#include <cstdlib>
+
 namespace ifeast {
 
 namespace {
@@ -180,6 +182,108 @@ __global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __r
   }
 }
 
+// Same factorisation with the lower triangle of L packed in LDS (row r at r(r+1)/2):
+// Cholesky, the update Racc <- R Racc, then L is inverted in place (trailing block
+// first: column j of L^{-1} below the diagonal is -(L22^{-1} l) / l_jj) and
+// Tinv = D^{-1} (L^{-1})^H is written out.  One workgroup per shift.
+__device__ inline int pk(int r, int c) { return r * (r + 1) / 2 + c; }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cholqr_lds(int m0, const double* __restrict__ G, double shift_rel,
+                                                    double dead_thr, double tau_dep, const int* __restrict__ active,
+                                                    T* __restrict__ Tinv, c2* __restrict__ Racc, int accumulate,
+                                                    c2* __restrict__ work) {
+  const int s = blockIdx.x;
+  if (active != nullptr && active[s] == 0) return;
+  extern __shared__ c2 lds_c2[];
+  c2* L = lds_c2;                       // m0 (m0 + 1) / 2
+  c2* x = L + m0 * (m0 + 1) / 2;        // m0
+  const int tid = threadIdx.x, m2 = 2 * m0;
+  const double* Gs = G + (int64_t)s * m2 * m2;
+  T* Tv = Tinv + (int64_t)s * m2 * m2;
+  c2* Ra = Racc + (int64_t)s * m0 * m0;
+  c2* tmp = work + (int64_t)s * 3 * m0 * m0;
+  __shared__ double dsc[128];
+  __shared__ int dead[128];
+  __shared__ double piv;
+
+  for (int a = tid; a < m0; a += 256) {
+    const double g = Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1];
+    const bool dd = !(g > dead_thr);
+    dead[a] = dd ? 1 : 0;
+    dsc[a] = dd ? 1.0 : sqrt(g);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < m0 * m0; idx += 256) {
+    const int a = idx / m0, b = idx % m0;
+    if (b > a) continue;
+    c2 g;
+    if (dead[a] || dead[b]) {
+      g = cmk(a == b ? 1.0 : 0.0, 0.0);
+    } else {
+      g = cscale(1.0 / (dsc[a] * dsc[b]), gram_entry(Gs, m2, a, b));
+      if (a == b) g = cmk(g.x + shift_rel, 0.0);
+    }
+    L[pk(a, b)] = g;
+  }
+  __syncthreads();
+  // right-looking Cholesky with deflation of small pivots
+  for (int c = 0; c < m0; ++c) {
+    if (tid == 0) {
+      const double p = L[pk(c, c)].x;
+      if (!dead[c] && !(p > tau_dep)) dead[c] = 1;
+      piv = dead[c] ? 1.0 : sqrt(p);
+      L[pk(c, c)] = cmk(piv, 0.0);
+    }
+    __syncthreads();
+    const bool dc = dead[c] != 0;
+    const double inv = 1.0 / piv;
+    for (int r = c + 1 + tid; r < m0; r += 256) L[pk(r, c)] = dc ? cmk(0.0, 0.0) : cscale(inv, L[pk(r, c)]);
+    __syncthreads();
+    if (dc) continue;
+    const int nt = m0 - c - 1;
+    for (int idx = tid; idx < nt * nt; idx += 256) {
+      const int r = c + 1 + idx / nt, q = c + 1 + idx % nt;
+      if (q <= r) L[pk(r, q)] = csub(L[pk(r, q)], cmul(L[pk(r, c)], cconj(L[pk(q, c)])));
+    }
+    __syncthreads();
+  }
+  // R = L^H D with zero rows for dead columns; Racc <- R Racc (upper triangular)
+  for (int idx = tid; idx < m0 * m0; idx += 256) {
+    const int a = idx / m0, b = idx % m0;
+    c2 v = cmk(0.0, 0.0);
+    if (b >= a && !dead[a]) {
+      if (accumulate) {
+        for (int e = a; e <= b; ++e) v = cadd(v, cmul(cscale(dsc[e], cconj(L[pk(e, a)])), Ra[e * m0 + b]));
+      } else {
+        v = cscale(dsc[b], cconj(L[pk(b, a)]));
+      }
+    }
+    tmp[idx] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < m0 * m0; idx += 256) Ra[idx] = tmp[idx];
+  // L <- L^{-1} in place, trailing block first
+  for (int j = m0 - 1; j >= 0; --j) {
+    for (int i = j + 1 + tid; i < m0; i += 256) x[i] = L[pk(i, j)];
+    if (tid == 0) L[pk(j, j)] = cmk(1.0 / L[pk(j, j)].x, 0.0);
+    __syncthreads();
+    const double ljj = L[pk(j, j)].x;
+    for (int i = j + 1 + tid; i < m0; i += 256) {
+      c2 v = cmk(0.0, 0.0);
+      for (int k = j + 1; k <= i; ++k) v = cadd(v, cmul(L[pk(i, k)], x[k]));
+      L[pk(i, j)] = cscale(-ljj, v);
+    }
+    __syncthreads();
+  }
+  // Tinv = D^{-1} Ri with Ri = (L^{-1})^H; dead columns and rows are zero
+  for (int idx = tid; idx < m0 * m0; idx += 256) {
+    const int a = idx / m0, b = idx % m0;
+    const c2 v = (b < a || dead[a] || dead[b]) ? cmk(0.0, 0.0) : cscale(1.0 / dsc[a], cconj(L[pk(b, a)]));
+    store_realified(Tv, m2, a, b, v);
+  }
+}
+
 template <class T>
 __global__ void k_cgs_combine(int ns, int ni, int m0, int j, int ldh, const double* __restrict__ G,
                               const int* __restrict__ active, c2* __restrict__ H, T* __restrict__ Hr, int accumulate) {
@@ -197,19 +301,27 @@ __global__ void k_cgs_combine(int ns, int ni, int m0, int j, int ldh, const doub
   store_realified(Hr + (int64_t)item * m2 * m2, m2, a, b, c);
 }
 
-// Per shift: does the block after one classical Gram-Schmidt pass need a second one?
-// ||W0 e_c||^2 = ||H e_c||^2 + ||W1 e_c||^2 (V orthonormal); a second pass is needed when some
-// live column kept less than a fraction eta of its norm.  G = W1^H W1 (real view), H column
-// block j of Hbar (rows 0..(j+1) m0).
-__global__ void k_reorth_check(int m0, int j, int ldh, double eta2, const double* __restrict__ G,
-                               const int* __restrict__ active, const c2* __restrict__ H, int* __restrict__ need) {
+// Per shift, from the Gram G = W1^H W1 (real view) of the block after one classical
+// Gram-Schmidt pass and the coefficients H of that pass (column block j of Hbar):
+//  * need[s]: a second Gram-Schmidt pass is needed, because some live column kept less
+//    than the fraction eta of its norm (||W0 e_c||^2 = ||H e_c||^2 + ||W1 e_c||^2);
+//  * single[s]: one unshifted Cholesky-QR pass suffices, because no second pass is needed,
+//    no column is negligible and Gershgorin's theorem puts every eigenvalue of the
+//    unit-diagonal scaled Gram in [1 - delta, 1 + delta] with delta <= gersh (so the
+//    Q factor of one pass is orthonormal to about kappa^2 u, kappa <= (1 + gersh) / (1 - gersh));
+//  * twopass[s] = active and not single.
+__global__ void k_orth_check(int m0, int j, int ldh, double eta2, double gersh, double dead_thr,
+                             const double* __restrict__ G, const int* __restrict__ active,
+                             const c2* __restrict__ H, int* __restrict__ need, int* __restrict__ single,
+                             int* __restrict__ twopass) {
   const int s = blockIdx.x;
   if (active != nullptr && active[s] == 0) {
-    if (threadIdx.x == 0) need[s] = 0;
+    if (threadIdx.x == 0) need[s] = single[s] = twopass[s] = 0;
     return;
   }
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
+  __shared__ int any_need, any_bad;
+  __shared__ double dsc[128];
+  if (threadIdx.x == 0) any_need = any_bad = 0;
   __syncthreads();
   const int m2 = 2 * m0, kk = ldh / m0 - 1;
   const double* Gs = G + (int64_t)s * m2 * m2;
@@ -218,10 +330,23 @@ __global__ void k_reorth_check(int m0, int j, int ldh, double eta2, const double
     const double w1 = Gs[(2 * c) * m2 + 2 * c] + Gs[(2 * c + 1) * m2 + 2 * c + 1];
     double h = 0.0;
     for (int r = 0; r < (j + 1) * m0; ++r) h += cabs2(Hs[r + (int64_t)c * ldh]);
-    if (w1 > 1e-30 && w1 < eta2 * (w1 + h)) atomicOr(&any, 1);
+    if (w1 > 1e-30 && w1 < eta2 * (w1 + h)) atomicOr(&any_need, 1);
+    if (!(w1 > dead_thr)) atomicOr(&any_bad, 1);
+    dsc[c] = sqrt(fmax(w1, 1e-300));
   }
   __syncthreads();
-  if (threadIdx.x == 0) need[s] = any;
+  for (int r = threadIdx.x; r < m0; r += blockDim.x) {
+    double off = 0.0;
+    for (int c = 0; c < m0; ++c)
+      if (c != r) off += sqrt(cabs2(gram_entry(Gs, m2, r, c))) / (dsc[r] * dsc[c]);
+    if (!(off <= gersh)) atomicOr(&any_bad, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    need[s] = any_need;
+    single[s] = (any_need == 0 && any_bad == 0) ? 1 : 0;
+    twopass[s] = single[s] ? 0 : 1;
+  }
 }
 
 __global__ void k_store_subdiag(int ns, int m0, int j, int ldh, const int* __restrict__ active,
@@ -455,11 +580,13 @@ __global__ __launch_bounds__(256) void k_lsq_qr(LsqArgs a, int j) {
   }
 }
 
-// The same step with the slab held in LDS, packed: column c keeps its rows
-// 0..m0+c (the rest of the slab is zero), 1.5 m0^2 complex numbers in all.
-// The right-hand side slab is then transformed in LDS column chunks.
-__global__ __launch_bounds__(256) void k_lsq_qr_lds(LsqArgs a, int j) {
+// The same factorisation with the slab held in LDS, packed: column c keeps its rows
+// 0..m0+c (the rest of the slab is zero), 1.5 m0^2 complex numbers in all.  16 waves:
+// wave 0 forms reflector c while the others wait, then all waves apply it to the
+// columns to its right.  The right-hand side is left to k_lsq_rhs.
+__global__ __launch_bounds__(1024) void k_lsq_qr_lds(LsqArgs a, int j) {
   extern __shared__ c2 lds[];
+  constexpr int NW = 16;
   const int s = blockIdx.x;
   if (a.active[s] == 0) return;
   const LsqView v = lsq_view(a, s);
@@ -474,8 +601,7 @@ __global__ __launch_bounds__(256) void k_lsq_qr_lds(LsqArgs a, int j) {
   c2* Vj = v.Vh + (int64_t)j * m2 * m0;
   double* tj = v.tau + j * m0;
   __shared__ double sh_tau;
-  __shared__ int sh_ok;
-  for (int col = wave; col < m0; col += 4) {
+  for (int col = wave; col < m0; col += NW) {
     c2* dst = sl + off(col);
     const c2* src = h + (int64_t)col * ldh;
     for (int r = lane; r <= m0 + col; r += 64) dst[r] = src[r];
@@ -516,7 +642,7 @@ __global__ __launch_bounds__(256) void k_lsq_qr_lds(LsqArgs a, int j) {
     __syncthreads();
     const double tau = sh_tau;
     if (tau != 0.0) {
-      for (int col = c + 1 + wave; col < m0; col += 4) {
+      for (int col = c + 1 + wave; col < m0; col += NW) {
         c2* x = sl + off(col);
         c2 d = cmk(0.0, 0.0);
         for (int r = r0 + lane; r < r1; r += 64) d = cadd(d, cjmul(vb[r], x[r]));
@@ -528,60 +654,52 @@ __global__ __launch_bounds__(256) void k_lsq_qr_lds(LsqArgs a, int j) {
     __syncthreads();
   }
   // R block column back to global (rows 0..m0+col of each slab column)
-  for (int col = wave; col < m0; col += 4) {
+  for (int col = wave; col < m0; col += NW) {
     const c2* src = sl + off(col);
     c2* dst = h + (int64_t)col * ldh;
     for (int r = lane; r <= m0 + col; r += 64) dst[r] = src[r];
   }
-  __syncthreads();
-  // right-hand side slab: column chunks in LDS, reflectors staged one at a time
-  const int CH = max(4, (P / m2) / 4 * 4);
-  for (int c0 = 0; c0 < m0; c0 += CH) {
-    const int nc = min(CH, m0 - c0);
-    for (int idx = tid; idx < nc * m2; idx += 256) {
-      const int cc = idx / m2, r = idx % m2;
-      sl[cc * m2 + r] = v.g[base + r + (int64_t)(c0 + cc) * ldh];
-    }
-    for (int c = 0; c < m0; ++c) {
-      __syncthreads();
-      for (int r = tid; r < m2; r += 256) vb[r] = Vj[(int64_t)c * m2 + r];
-      __syncthreads();
-      const double tau = tj[c];
-      if (tau == 0.0) continue;
-      const int r0 = c, r1 = m0 + c + 1;
-      for (int cc = wave; cc < nc; cc += 4) {
-        c2* x = sl + cc * m2;
-        c2 d = cmk(0.0, 0.0);
-        for (int r = r0 + lane; r < r1; r += 64) d = cadd(d, cjmul(vb[r], x[r]));
-        d = wave_csum(d);
-        const c2 f = cscale(tau, d);
-        for (int r = r0 + lane; r < r1; r += 64) x[r] = csub(x[r], cmul(f, vb[r]));
-      }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nc * m2; idx += 256) {
-      const int cc = idx / m2, r = idx % m2;
-      v.g[base + r + (int64_t)(c0 + cc) * ldh] = sl[cc * m2 + r];
-    }
-    __syncthreads();
+}
+
+// Step j, part 3: the reflectors of step j on the right-hand side slab, one wave per
+// column (staged in LDS), and that column's residual norm (the last m0 rows of the
+// transformed slab).  grid (ns, ceil(m0/4)).
+__global__ __launch_bounds__(256) void k_lsq_rhs(LsqArgs a, int j) {
+  __shared__ c2 colbuf[4 * 256];  // 4 x 2 m0
+  const int s = blockIdx.x;
+  if (a.active[s] == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = blockIdx.y * 4 + wave;
+  if (col >= m0) return;
+  c2* x = colbuf + wave * m2;
+  c2* gc = v.g + j * m0 + (int64_t)col * ldh;
+  for (int r = lane; r < m2; r += 64) x[r] = gc[r];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  wave_reflect_run(v.Vh + (int64_t)j * m2 * m0, v.tau + j * m0, m0, m2, x, lane, false);
+  double ss = 0.0;
+  for (int r = lane; r < m2; r += 64) {
+    gc[r] = x[r];
+    if (r >= m0) ss += cabs2(x[r]);
   }
-  if (tid == 0) sh_ok = 1;
-  __syncthreads();
-  for (int col = wave; col < m0; col += 4) {
-    const c2* gc = v.g + (int64_t)(j + 1) * m0 + (int64_t)col * ldh;
-    double ss = 0.0;
-    for (int r = lane; r < m0; r += 64) ss += cabs2(gc[r]);
-    ss = wave_dsum(ss);
-    if (lane == 0) {
-      const double rn = sqrt(ss);
-      v.res[col] = rn;
-      if (!(rn <= v.tol[col])) atomicAnd(&sh_ok, 0);
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
+  ss = wave_dsum(ss);
+  if (lane == 0) v.res[col] = sqrt(ss);
+}
+
+// Step j, part 4: the stopping rule of the shift (every column's residual at or below
+// its threshold ends the cycle).  One wave per shift.
+__global__ void k_lsq_stop(LsqArgs a, int j) {
+  const int s = blockIdx.x;
+  if (a.active[s] == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int lane = threadIdx.x;
+  int bad = 0;
+  for (int c = lane; c < a.m0; c += 64) bad |= !(v.res[c] <= v.tol[c]);
+  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o);
+  if (lane == 0) {
     a.iters[s] = j + 1;
-    if (sh_ok) {
+    if (!bad) {
       a.cycle_done[s] = 1;
       a.active[s] = 0;
     }
@@ -940,8 +1058,23 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
   // one whose output Gram has pivots of order that shift unless columns are dependent
   const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   const double tau_dep = shift_rel > 0.0 ? 0.5 * shift_rel : 0.25 * m0 * eps;
-  hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, dead_thr, tau_dep, active,
-                     Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
+  const size_t lds = ((size_t)m0 * (m0 + 1) / 2 + m0) * sizeof(c2);
+  if ((int64_t)lds + 2048 <= (int64_t)max_lds && getenv("IFEAST_CHOLQR_GLOBAL") == nullptr) {
+    if (lds > 64 * 1024)
+      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_cholqr_lds<T>), dim3(ns), dim3(256), lds, st, m0, G, shift_rel, dead_thr, tau_dep, active,
+                       Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
+  } else {
+    hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, dead_thr, tau_dep,
+                       active, Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
+  }
   IF_HIP(hipGetLastError());
 }
 template void launch_cholqr_factor<float>(hipStream_t, int, int, const double*, double, const int*, float*, cd*, int,
@@ -962,10 +1095,11 @@ template void launch_cgs_combine<float>(hipStream_t, int, int, int, int, int, co
 template void launch_cgs_combine<double>(hipStream_t, int, int, int, int, int, const double*, const int*, cd*,
                                          double*, int);
 
-void launch_reorth_check(hipStream_t st, int ns, int m0, int j, int ldh, double eta, const double* G,
-                         const int* active, const cd* H, int* need) {
-  hipLaunchKernelGGL(k_reorth_check, dim3(ns), dim3(128), 0, st, m0, j, ldh, eta * eta, G, active,
-                     reinterpret_cast<const c2*>(H), need);
+void launch_orth_check(hipStream_t st, int ns, int m0, int j, int ldh, double eta, double gersh, double dead_thr,
+                       const double* G, const int* active, const cd* H, int* need, int* single, int* twopass) {
+  IF_REQUIRE(m0 <= 128, "orth check: m0 > 128");
+  hipLaunchKernelGGL(k_orth_check, dim3(ns), dim3(128), 0, st, m0, j, ldh, eta * eta, gersh, dead_thr, G, active,
+                     reinterpret_cast<const c2*>(H), need, single, twopass);
   IF_HIP(hipGetLastError());
 }
 
@@ -999,11 +1133,15 @@ void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
   }
   const size_t P = (size_t)a.m0 * a.m0 + (size_t)a.m0 * (a.m0 + 1) / 2;
   const size_t lds = (P + 2 * (size_t)a.m0) * sizeof(c2);
-  if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
+  if ((int64_t)lds + 1024 <= (int64_t)max_lds && getenv("IFEAST_LSQ_GLOBAL") == nullptr) {
     if (lds > 64 * 1024)
       IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_qr_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_lsq_qr_lds, dim3(a.ns), dim3(256), lds, st, a, j);
+    hipLaunchKernelGGL(k_lsq_qr_lds, dim3(a.ns), dim3(1024), lds, st, a, j);
+    IF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lsq_rhs, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a, j);
+    IF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lsq_stop, dim3(a.ns), dim3(64), 0, st, a, j);
   } else {
     hipLaunchKernelGGL(k_lsq_qr, dim3(a.ns), dim3(256), 0, st, a, j);
   }

@@ -53,6 +53,17 @@ __device__ inline float4 zs_minus(float zr, float zi, const float4& s, const flo
 __device__ inline double2 zs_minus(double zr, double zi, const double2& s, const double2& acc) {
   return make_double2(zr * s.x - zi * s.y - acc.x, zr * s.y + zi * s.x - acc.y);
 }
+// non-temporal 16-byte stores (results that are not read again by this kernel)
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+__device__ inline void nt_store(const float4& v, float4* p) {
+  const nf4 t = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(t, reinterpret_cast<nf4*>(p));
+}
+__device__ inline void nt_store(const double2& v, double2* p) {
+  const nd2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<nd2*>(p));
+}
 template <class V> __device__ inline V vzero();
 template <> __device__ inline float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 template <> __device__ inline double2 vzero<double2>() { return make_double2(0.0, 0.0); }
@@ -132,6 +143,76 @@ __global__ __launch_bounds__(256) void k_spmm_shifted(int n, int per, const int*
   }
 }
 
+// Column-sliced variant.  The block is cut into slices of LPR 16-byte vectors
+// (32 complex FP32 numbers for LPR = 16); a group of LPR lanes handles one row of
+// one slice and a wavefront 64 / LPR rows.  XCD x owns the rows [x R, (x+1) R) and
+// sweeps them slice after slice, so the rows a stencil reads far from the
+// diagonal (the neighbour planes of a 3-D grid) were fetched by the same XCD a
+// few thousand rows earlier in the same slice and are still in its L2: the reuse
+// distance in bytes shrinks by the number of slices.  Each group fetches KC CSR
+// entries of its row with one coalesced load and broadcasts them with lane
+// shuffles; W is stored with non-temporal stores so it does not evict V from L2.
+template <class T, bool HAS_B, int LPR, int KC>
+__device__ inline void slab_gather(int e0, int e1, int g, const int* __restrict__ ci, const T* __restrict__ va,
+                                   const typename Vec16<T>::type* __restrict__ Vv, int nvec, int vc,
+                                   typename Vec16<T>::type& acc) {
+  static_assert(KC <= LPR, "one load per group fetches the round's entries");
+  for (int e = e0; e < e1; e += KC) {
+    const int my = e + g;
+    const bool have = g < KC && my < e1;
+    const int cl = have ? ci[my] : 0;
+    const T al = have ? va[my] : T(0);
+    int c[KC];
+    T a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      c[k] = __shfl(cl, k, LPR);
+      a[k] = __shfl(al, k, LPR);
+    }
+    typename Vec16<T>::type x[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) x[k] = Vv[(int64_t)c[k] * nvec + vc];  // c = 0, a = 0 past the row's end
+#pragma unroll
+    for (int k = 0; k < KC; ++k) axpy(a[k], x[k], acc);
+  }
+}
+
+template <class T, bool HAS_B, int LPR, int KC>
+__global__ __launch_bounds__(256) void k_spmm_slab(int n, int rows_xcd, int rbx, int nslices,
+                                                   const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const T* __restrict__ va, const int* __restrict__ brp,
+                                                   const int* __restrict__ bci, const T* __restrict__ bva, int ns,
+                                                   int m0, const T* __restrict__ zs, const int* __restrict__ active,
+                                                   const T* __restrict__ V, T* __restrict__ W) {
+  using V16 = typename Vec16<T>::type;
+  constexpr int C = Vec16<T>::C;
+  constexpr int RPW = 64 / LPR;  // rows per wavefront
+  constexpr int RPB = 4 * RPW;   // rows per workgroup
+  const int xcd = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+  const int slice = i / rbx, rb = i % rbx;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane % LPR;
+  const int rlo = xcd * rows_xcd;
+  const int rhi = min(n, rlo + rows_xcd);
+  const int row = rlo + rb * RPB + wave * RPW + lane / LPR;
+  const int nvec = ns * m0 / C;
+  const int vc = slice * LPR + g;
+  // whole groups leave together (the shuffles stay inside a group)
+  if (slice >= nslices || row >= rhi) return;
+  const bool live = vc < nvec;
+  const int vcc = live ? vc : nvec - 1;  // lanes past the block width load a valid vector and store nothing
+  const int s = (vcc * C) / m0;
+  const V16* __restrict__ Vv = reinterpret_cast<const V16*>(V);
+  V16 acc = vzero<V16>(), self = vzero<V16>();
+  slab_gather<T, HAS_B, LPR, KC>(rp[row], rp[row + 1], g, ci, va, Vv, nvec, vcc, acc);
+  if (HAS_B)
+    slab_gather<T, HAS_B, LPR, KC>(brp[row], brp[row + 1], g, bci, bva, Vv, nvec, vcc, self);
+  else
+    self = Vv[(int64_t)row * nvec + vcc];
+  if (live && (active == nullptr || active[s] != 0))
+    nt_store(zs_minus(zs[2 * s], zs[2 * s + 1], self, acc), reinterpret_cast<V16*>(W) + (int64_t)row * nvec + vc);
+}
+
 __global__ __launch_bounds__(256) void k_spmm_real(int n, int per, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const double* __restrict__ va, int m,
                                                    const double* __restrict__ X, double* __restrict__ Y) {
@@ -151,63 +232,96 @@ __global__ __launch_bounds__(256) void k_spmm_real(int n, int per, const int* __
   }
 }
 
-// Schedules the autotuner chooses from: (U, KC) = vectors per lane per pass, CSR entries per round.
+// Schedules the autotuner chooses from: whole rows per wavefront with U vectors per lane per
+// pass, or column slices of LPR vectors; KC = CSR entries fetched per round.
 struct Sched {
-  int U, KC;
+  bool slab;
+  int U_or_LPR, KC;
+  const char* name;
 };
-constexpr Sched kSched[] = {{1, 8}, {2, 8}, {3, 8}, {5, 4}, {2, 4}, {4, 4}, {1, 4}, {3, 4}};
+constexpr Sched kSched[] = {{false, 1, 8, "row-U1-K8"}, {false, 2, 4, "row-U2-K4"}, {false, 3, 4, "row-U3-K4"},
+                            {true, 8, 8, "slab8-K8"},   {true, 16, 8, "slab16-K8"}, {true, 32, 8, "slab32-K8"},
+                            {true, 16, 16, "slab16-K16"}, {true, 8, 4, "slab8-K4"}};
 constexpr int kNSched = sizeof(kSched) / sizeof(kSched[0]);
 
+struct SpmmOperands {
+  int n, ns, m0;
+  const int *rp, *ci;
+  const void* va;
+  const int *brp, *bci;
+  const void* bva;
+  const void* zs;
+  const int* active;
+  const void* V;
+  void* W;
+};
+
+template <class T, bool HAS_B, int U, int KC>
+void launch_row(hipStream_t st, const SpmmOperands& o) {
+  const int64_t nblk = (o.n + 3) / 4;
+  const int per = xcd_per(nblk);
+  hipLaunchKernelGGL((k_spmm_shifted<T, HAS_B, U, KC>), dim3(per * kXcds), dim3(256), 0, st, o.n, per, o.rp, o.ci,
+                     (const T*)o.va, o.brp, o.bci, (const T*)o.bva, o.ns, o.m0, (const T*)o.zs, o.active,
+                     (const T*)o.V, (T*)o.W);
+}
+
+template <class T, bool HAS_B, int LPR, int KC>
+void launch_slab(hipStream_t st, const SpmmOperands& o) {
+  constexpr int C = Vec16<T>::C;
+  constexpr int RPB = 4 * (64 / LPR);
+  const int nvec = o.ns * o.m0 / C;
+  const int nslices = (nvec + LPR - 1) / LPR;
+  const int rows_xcd = (o.n + kXcds - 1) / kXcds;
+  const int rbx = (rows_xcd + RPB - 1) / RPB;
+  const int64_t blocks = (int64_t)kXcds * nslices * rbx;
+  IF_REQUIRE(blocks < (int64_t(1) << 31), "SpMM grid too large");
+  hipLaunchKernelGGL((k_spmm_slab<T, HAS_B, LPR, KC>), dim3((unsigned)blocks), dim3(256), 0, st, o.n, rows_xcd, rbx,
+                     nslices, o.rp, o.ci, (const T*)o.va, o.brp, o.bci, (const T*)o.bva, o.ns, o.m0,
+                     (const T*)o.zs, o.active, (const T*)o.V, (T*)o.W);
+}
+
 template <class T, bool HAS_B>
-void launch_sched(int idx, hipStream_t st, dim3 grid, int n, int per, const int* rp, const int* ci, const T* va,
-                  const int* brp, const int* bci, const T* bva, int ns, int m0, const T* zs, const int* active,
-                  const T* V, T* W) {
-#define IF_SPMM_CASE(I, U_, KC_)                                                                          \
-  case I:                                                                                                 \
-    hipLaunchKernelGGL((k_spmm_shifted<T, HAS_B, U_, KC_>), grid, dim3(256), 0, st, n, per, rp, ci, va,  \
-                       brp, bci, bva, ns, m0, zs, active, V, W);                                          \
-    break;
+void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
   switch (idx) {
-    IF_SPMM_CASE(0, 1, 8)
-    IF_SPMM_CASE(1, 2, 8)
-    IF_SPMM_CASE(2, 3, 8)
-    IF_SPMM_CASE(3, 5, 4)
-    IF_SPMM_CASE(4, 2, 4)
-    IF_SPMM_CASE(5, 4, 4)
-    IF_SPMM_CASE(6, 1, 4)
-    IF_SPMM_CASE(7, 3, 4)
-    default:
-      throw Error{IFEAST_ERR_INVALID_ARG, "unknown SpMM schedule"};
+    case 0: launch_row<T, HAS_B, 1, 8>(st, o); break;
+    case 1: launch_row<T, HAS_B, 2, 4>(st, o); break;
+    case 2: launch_row<T, HAS_B, 3, 4>(st, o); break;
+    case 3: launch_slab<T, HAS_B, 8, 8>(st, o); break;
+    case 4: launch_slab<T, HAS_B, 16, 8>(st, o); break;
+    case 5: launch_slab<T, HAS_B, 32, 8>(st, o); break;
+    case 6: launch_slab<T, HAS_B, 16, 16>(st, o); break;
+    case 7: launch_slab<T, HAS_B, 8, 4>(st, o); break;
+    default: throw Error{IFEAST_ERR_INVALID_ARG, "unknown SpMM schedule"};
   }
-#undef IF_SPMM_CASE
 }
 
 }  // namespace
 
-const char* spmm_schedule_name(int idx) {
-  static const char* names[] = {"U1xK8", "U2xK8", "U3xK8", "U5xK4", "U2xK4", "U4xK4", "U1xK4", "U3xK4"};
-  return idx >= 0 && idx < kNSched ? names[idx] : "?";
-}
+const char* spmm_schedule_name(int idx) { return idx >= 0 && idx < kNSched ? kSched[idx].name : "?"; }
 
 template <class T>
 void launch_spmm_shifted(hipStream_t st, const ifeast_matrix* A, const ifeast_matrix* B, int ns, int m0,
                          const T* zs, const int* active, const T* V, T* W) {
   const int64_t n = A->n;
-  const int64_t nblk = (n + 3) / 4;
-  const int per = xcd_per(nblk);
-  const dim3 grid(per * kXcds);
-  const T* va = (sizeof(T) == 4) ? reinterpret_cast<const T*>(A->valf.p) : reinterpret_cast<const T*>(A->val.p);
-  const int* brp = B ? B->rowptr.as<int>() : nullptr;
-  const int* bci = B ? B->colind.as<int>() : nullptr;
-  const T* bva = B ? ((sizeof(T) == 4) ? reinterpret_cast<const T*>(B->valf.p) : reinterpret_cast<const T*>(B->val.p))
-                   : nullptr;
+  SpmmOperands o;
+  o.n = (int)n;
+  o.ns = ns;
+  o.m0 = m0;
+  o.rp = A->rowptr.as<int>();
+  o.ci = A->colind.as<int>();
+  o.va = (sizeof(T) == 4) ? A->valf.p : A->val.p;
+  o.brp = B ? B->rowptr.as<int>() : nullptr;
+  o.bci = B ? B->colind.as<int>() : nullptr;
+  o.bva = B ? ((sizeof(T) == 4) ? B->valf.p : B->val.p) : nullptr;
+  o.zs = zs;
+  o.active = active;
+  o.V = V;
+  o.W = W;
   auto run = [&](int idx) {
     if (B == nullptr)
-      launch_sched<T, false>(idx, st, grid, (int)n, per, A->rowptr.as<int>(), A->colind.as<int>(), va, nullptr,
-                             nullptr, nullptr, ns, m0, zs, active, V, W);
+      launch_sched<T, false>(idx, st, o);
     else
-      launch_sched<T, true>(idx, st, grid, (int)n, per, A->rowptr.as<int>(), A->colind.as<int>(), va, brp, bci,
-                            bva, ns, m0, zs, active, V, W);
+      launch_sched<T, true>(idx, st, o);
     IF_HIP(hipGetLastError());
   };
   // Autotuner: the first product of a given (matrix, B, width, precision) times every schedule on the

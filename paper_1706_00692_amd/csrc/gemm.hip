@@ -190,10 +190,19 @@ inline int gram_tb(int W) {
   return (nb + nt - 1) / nt;
 }
 
-inline int gram_nsplit(int64_t n, int items, int tiles) {
-  int64_t want = (1024 + (int64_t)items * tiles - 1) / ((int64_t)items * tiles);
-  int64_t maxs = std::max<int64_t>(1, n / 1024);
-  return (int)std::max<int64_t>(1, std::min(want, maxs));
+// Workgroups of k_gram<T, tb> resident on the whole device at once.
+template <class T>
+int gram_capacity(int tb);
+
+// Row splits per (item, tile): enough workgroups to fill the device twice, and a total that
+// does not exceed two full waves of resident workgroups (a third, nearly empty wave would
+// cost as much as a full one).  At least 1024 rows per split.
+inline int gram_nsplit(int64_t n, int items, int tiles, int cap) {
+  const int64_t per = (int64_t)items * tiles;
+  const int64_t target = 2 * (int64_t)std::max(cap, 1);
+  const int64_t want = std::max<int64_t>(1, target / per);
+  const int64_t maxs = std::max<int64_t>(1, n / 1024);
+  return (int)std::min(want, maxs);
 }
 
 // ------------------------------------------------------------------ apply
@@ -203,12 +212,12 @@ inline int gram_nsplit(int64_t n, int items, int tiles) {
 template <class T> struct ApplyCfg { static constexpr int KC = 32; };
 template <> struct ApplyCfg<double> { static constexpr int KC = 16; };
 
-template <class T, class TO, int TBQ>
+template <class T, class TO, int TBQ, int RB = 2, int KCX = ApplyCfg<T>::KC>
 __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
   using V = typename V16T<T>::t;
   constexpr int VN = V16T<T>::N;
-  constexpr int KC = ApplyCfg<T>::KC;
-  constexpr int RT = 128;
+  constexpr int KC = KCX;
+  constexpr int RT = 64 * RB;  // 4 waves x RB row blocks of 16
   constexpr int TQ = TBQ * 16;
   constexpr int LDA_S = KC + 4;
   constexpr int LDB_S = lds_ld<T>(TQ);
@@ -228,9 +237,9 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  typename Mfma<T>::acc acc[2][TBQ];
+  typename Mfma<T>::acc acc[RB][TBQ];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int t = 0; t < TBQ; ++t) acc[r][t] = Mfma<T>::zero();
 
@@ -295,15 +304,17 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
     if (nb_ < a.nb) fetch(nb_, nk * KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      T af[2];
+      T af[RB];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) af[r] = sA[(wave * 32 + r * 16 + li) * LDA_S + kk + lk];
+      for (int r = 0; r < RB; ++r) af[r] = sA[(wave * 16 * RB + r * 16 + li) * LDA_S + kk + lk];
 #pragma unroll
       for (int t = 0; t < TBQ; ++t) {
         if (t * 16 < vq) {
           const T bv = sB[(kk + lk) * LDB_S + t * 16 + li];
+          // transposed product: the MFMA computes (A Bm)^T blocks, so a lane ends up holding
+          // consecutive output columns of one row
 #pragma unroll
-          for (int r = 0; r < 2; ++r) acc[r][t] = Mfma<T>::mma(af[r], bv, acc[r][t]);
+          for (int r = 0; r < RB; ++r) acc[r][t] = Mfma<T>::mma(bv, af[r], acc[r][t]);
         }
       }
     }
@@ -313,43 +324,116 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
   }
 
   TO* __restrict__ O = static_cast<TO*>(a.O) + item * a.o_item;
+  // lane (li, lk) holds output row li of each 16-row block and its columns Mfma<T>::row(lk, v)
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < RB; ++r) {
+    const int64_t row = r0 + wave * 16 * RB + r * 16 + li;
+    if (row >= a.n) continue;
+    TO* __restrict__ orow = O + row * a.ldo + q0;
 #pragma unroll
     for (int t = 0; t < TBQ; ++t) {
-      if (t * 16 < vq) {
+      if (t * 16 >= vq) continue;
+      if constexpr (sizeof(T) == 4) {
+        // four consecutive columns 16 t + 4 lk .. + 3
+        TO* o = orow + t * 16 + 4 * lk;
+        TO val[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) val[v] = (TO)(a.alpha * (double)acc[r][t][v]);
+        if constexpr (sizeof(TO) == 4) {
+          float4* o4 = reinterpret_cast<float4*>(o);
+          float4 w = make_float4(val[0], val[1], val[2], val[3]);
+          if (a.beta != 0.0) {
+            const float4 old = *o4;
+            const float bt = (float)a.beta;
+            w = make_float4(bt * old.x + w.x, bt * old.y + w.y, bt * old.z + w.z, bt * old.w + w.w);
+          }
+          *o4 = w;
+        } else {
+          double2* o2 = reinterpret_cast<double2*>(o);
+          double2 w0 = make_double2(val[0], val[1]), w1 = make_double2(val[2], val[3]);
+          if (a.beta != 0.0) {
+            const double2 p0 = o2[0], p1 = o2[1];
+            w0 = make_double2(a.beta * p0.x + w0.x, a.beta * p0.y + w0.y);
+            w1 = make_double2(a.beta * p1.x + w1.x, a.beta * p1.y + w1.y);
+          }
+          o2[0] = w0;
+          o2[1] = w1;
+        }
+      } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t row = r0 + wave * 32 + r * 16 + Mfma<T>::row(lk, v);
-          const int col = q0 + t * 16 + li;
-          if (row < a.n) {
-            TO* o = O + row * a.ldo + col;
-            const TO val = (TO)(a.alpha * (double)acc[r][t][v]);
-            *o = (a.beta == 0.0) ? val : (TO)(a.beta * (double)(*o)) + val;
-          }
+          TO* o = orow + t * 16 + Mfma<T>::row(lk, v);
+          const TO val = (TO)(a.alpha * (double)acc[r][t][v]);
+          *o = (a.beta == 0.0) ? val : (TO)(a.beta * (double)(*o)) + val;
         }
       }
     }
+  }
 }
 
 }  // namespace
 
+namespace {
+template <class T, int TB>
+int gram_capacity_of() {
+  // without a device (host-only footprint queries) assume a large device: the row-split
+  // count, and with it the partial-sum buffer, only grows with the capacity
+  static int cap = -1;
+  if (cap < 0) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_gram<T, TB>), 256, 0) !=
+            hipSuccess ||
+        occ < 1 || cus < 1)
+      return 2048;
+    cap = occ * cus;
+  }
+  return cap;
+}
+
+template <class T>
+int gram_capacity(int tb) {
+  switch (tb) {
+    case 1: return gram_capacity_of<T, 1>();
+    case 2: return gram_capacity_of<T, 2>();
+    case 3: return gram_capacity_of<T, 3>();
+    case 4: return gram_capacity_of<T, 4>();
+    case 5: return gram_capacity_of<T, 5>();
+    case 6: return gram_capacity_of<T, 6>();
+    case 7: return gram_capacity_of<T, 7>();
+    case 8: return gram_capacity_of<T, 8>();
+    case 9: return gram_capacity_of<T, 9>();
+    default: return gram_capacity_of<T, 10>();
+  }
+}
+}  // namespace
+
+// Largest tile (in 16-column blocks) of the Gram kernel; 0 = as wide as the operands allow.
+int g_gram_variant = 0;
+
 template <class T>
 size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
-  const int tb = std::max(gram_tb(PW), gram_tb(QW));
-  const int tiles = ((PW / 16 + tb - 1) / tb) * ((QW / 16 + tb - 1) / tb);
-  const int ns = gram_nsplit(n, items, tiles);
-  return (size_t)items * ns * PW * QW * sizeof(T);
+  // the largest over the tilings launch_gram may choose
+  size_t best = 0;
+  const int tb0 = std::max(gram_tb(PW), gram_tb(QW));
+  for (int tb = 1; tb <= tb0; ++tb) {
+    const int tiles = ((PW / 16 + tb - 1) / tb) * ((QW / 16 + tb - 1) / tb);
+    const int ns = gram_nsplit(n, items, tiles, gram_capacity<T>(tb));
+    best = std::max(best, (size_t)items * ns * PW * QW * sizeof(T));
+  }
+  return best;
 }
 
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes) {
   IF_REQUIRE(g.PW % 16 == 0 && g.QW % 16 == 0, "gram: widths must be multiples of 16");
   // one square tile size for both dimensions
-  const int tb = std::max(gram_tb(g.PW), gram_tb(g.QW));
+  int tb = std::max(gram_tb(g.PW), gram_tb(g.QW));
+  if (g_gram_variant > 0 && tb > g_gram_variant) tb = g_gram_variant;
   const int ntp = (g.PW / 16 + tb - 1) / tb, ntq = (g.QW / 16 + tb - 1) / tb;
   const int items = g.ns * g.ni;
-  const int nsplit = gram_nsplit(g.n, items, ntp * ntq);
+  const int nsplit = gram_nsplit(g.n, items, ntp * ntq, gram_capacity<T>(tb));
   IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
   constexpr int KC = GramCfg<T>::KC;
   int64_t rps = (g.n + nsplit - 1) / nsplit;
@@ -387,29 +471,50 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   IF_HIP(hipGetLastError());
 }
 
+// Row blocks per wave and K chunk of the update kernel for 160-wide complex-FP32 blocks;
+// other shapes use 2 x (32 or 16).  -1 selects the built-in choice.
+int g_apply_variant = -1;
+
+template <class T, class TO, int RB, int KC>
+void launch_apply_rt(hipStream_t st, const ApplyArgs& a, int tbq, int ntq, KernelTimer* kt, int& tok) {
+  constexpr int RT = 64 * RB;
+  const int64_t nrt = (a.n + RT - 1) / RT;
+  const int per = (int)((nrt + kXcds - 1) / kXcds);
+  const dim3 grid(per * kXcds, ntq, a.items), block(256);
+  tok = kt ? kt->begin(st) : -1;
+  switch (tbq) {
+    case 1: hipLaunchKernelGGL((k_apply<T, TO, 1, RB, KC>), grid, block, 0, st, a, per); break;
+    case 2: hipLaunchKernelGGL((k_apply<T, TO, 2, RB, KC>), grid, block, 0, st, a, per); break;
+    case 3: hipLaunchKernelGGL((k_apply<T, TO, 3, RB, KC>), grid, block, 0, st, a, per); break;
+    case 4: hipLaunchKernelGGL((k_apply<T, TO, 4, RB, KC>), grid, block, 0, st, a, per); break;
+    case 5: hipLaunchKernelGGL((k_apply<T, TO, 5, RB, KC>), grid, block, 0, st, a, per); break;
+    case 6: hipLaunchKernelGGL((k_apply<T, TO, 6, RB, KC>), grid, block, 0, st, a, per); break;
+    case 7: hipLaunchKernelGGL((k_apply<T, TO, 7, RB, KC>), grid, block, 0, st, a, per); break;
+    case 8: hipLaunchKernelGGL((k_apply<T, TO, 8, RB, KC>), grid, block, 0, st, a, per); break;
+    case 9: hipLaunchKernelGGL((k_apply<T, TO, 9, RB, KC>), grid, block, 0, st, a, per); break;
+    case 10: hipLaunchKernelGGL((k_apply<T, TO, 10, RB, KC>), grid, block, 0, st, a, per); break;
+    default: throw Error{IFEAST_ERR_INVALID_ARG, "apply: unsupported tile"};
+  }
+}
+
 template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a) {
   IF_REQUIRE(a.OW % 16 == 0, "apply: output width must be a multiple of 16");
   const int nbq = a.OW / 16;
   const int ntq = (nbq + 9) / 10;
   const int tbq = (nbq + ntq - 1) / ntq;
-  const int64_t nrt = (a.n + 127) / 128;
-  const int per = (int)((nrt + kXcds - 1) / kXcds);
-  const dim3 grid(per * kXcds, ntq, a.items), block(256);
   KernelTimer* kt = current_timer();
-  const int tok = kt ? kt->begin(st) : -1;
-  switch (tbq) {
-    case 1: hipLaunchKernelGGL((k_apply<T, TO, 1>), grid, block, 0, st, a, per); break;
-    case 2: hipLaunchKernelGGL((k_apply<T, TO, 2>), grid, block, 0, st, a, per); break;
-    case 3: hipLaunchKernelGGL((k_apply<T, TO, 3>), grid, block, 0, st, a, per); break;
-    case 4: hipLaunchKernelGGL((k_apply<T, TO, 4>), grid, block, 0, st, a, per); break;
-    case 5: hipLaunchKernelGGL((k_apply<T, TO, 5>), grid, block, 0, st, a, per); break;
-    case 6: hipLaunchKernelGGL((k_apply<T, TO, 6>), grid, block, 0, st, a, per); break;
-    case 7: hipLaunchKernelGGL((k_apply<T, TO, 7>), grid, block, 0, st, a, per); break;
-    case 8: hipLaunchKernelGGL((k_apply<T, TO, 8>), grid, block, 0, st, a, per); break;
-    case 9: hipLaunchKernelGGL((k_apply<T, TO, 9>), grid, block, 0, st, a, per); break;
-    case 10: hipLaunchKernelGGL((k_apply<T, TO, 10>), grid, block, 0, st, a, per); break;
-    default: throw Error{IFEAST_ERR_INVALID_ARG, "apply: unsupported tile"};
+  int tok = -1;
+  constexpr int KC0 = ApplyCfg<T>::KC;
+  if (sizeof(T) == 4 && sizeof(TO) == 4 && tbq == 10) {
+    switch (g_apply_variant) {
+      case 0: launch_apply_rt<T, TO, 2, 32>(st, a, tbq, ntq, kt, tok); break;
+      case 1: launch_apply_rt<T, TO, 1, 64>(st, a, tbq, ntq, kt, tok); break;
+      case 2: launch_apply_rt<T, TO, 1, 16>(st, a, tbq, ntq, kt, tok); break;
+      default: launch_apply_rt<T, TO, 1, 32>(st, a, tbq, ntq, kt, tok); break;
+    }
+  } else {
+    launch_apply_rt<T, TO, 2, KC0>(st, a, tbq, ntq, kt, tok);
   }
   IF_HIP(hipGetLastError());
   if (kt) {

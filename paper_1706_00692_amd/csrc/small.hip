@@ -189,10 +189,10 @@ __global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __r
 __device__ inline int pk(int r, int c) { return r * (r + 1) / 2 + c; }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cholqr_lds(int m0, const double* __restrict__ G, double shift_rel,
+__global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __restrict__ G, double shift_rel,
                                                     double dead_thr, double tau_dep, const int* __restrict__ active,
                                                     T* __restrict__ Tinv, c2* __restrict__ Racc, int accumulate,
-                                                    c2* __restrict__ work) {
+                                                    c2* __restrict__ work, int ra_in_lds) {
   const int s = blockIdx.x;
   if (active != nullptr && active[s] == 0) return;
   extern __shared__ c2 lds_c2[];
@@ -205,16 +205,15 @@ __global__ __launch_bounds__(256) void k_cholqr_lds(int m0, const double* __rest
   c2* tmp = work + (int64_t)s * 3 * m0 * m0;
   __shared__ double dsc[128];
   __shared__ int dead[128];
-  __shared__ double piv;
 
-  for (int a = tid; a < m0; a += 256) {
+  for (int a = tid; a < m0; a += blockDim.x) {
     const double g = Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1];
     const bool dd = !(g > dead_thr);
     dead[a] = dd ? 1 : 0;
     dsc[a] = dd ? 1.0 : sqrt(g);
   }
   __syncthreads();
-  for (int idx = tid; idx < m0 * m0; idx += 256) {
+  for (int idx = tid; idx < m0 * m0; idx += blockDim.x) {
     const int a = idx / m0, b = idx % m0;
     if (b > a) continue;
     c2 g;
@@ -228,6 +227,7 @@ __global__ __launch_bounds__(256) void k_cholqr_lds(int m0, const double* __rest
   }
   __syncthreads();
   // right-looking Cholesky with deflation of small pivots
+  __shared__ double piv;
   for (int c = 0; c < m0; ++c) {
     if (tid == 0) {
       const double p = L[pk(c, c)].x;
@@ -238,46 +238,74 @@ __global__ __launch_bounds__(256) void k_cholqr_lds(int m0, const double* __rest
     __syncthreads();
     const bool dc = dead[c] != 0;
     const double inv = 1.0 / piv;
-    for (int r = c + 1 + tid; r < m0; r += 256) L[pk(r, c)] = dc ? cmk(0.0, 0.0) : cscale(inv, L[pk(r, c)]);
+    for (int r = c + 1 + tid; r < m0; r += blockDim.x) L[pk(r, c)] = dc ? cmk(0.0, 0.0) : cscale(inv, L[pk(r, c)]);
     __syncthreads();
     if (dc) continue;
     const int nt = m0 - c - 1;
-    for (int idx = tid; idx < nt * nt; idx += 256) {
+    for (int idx = tid; idx < nt * nt; idx += blockDim.x) {
       const int r = c + 1 + idx / nt, q = c + 1 + idx % nt;
       if (q <= r) L[pk(r, q)] = csub(L[pk(r, q)], cmul(L[pk(r, c)], cconj(L[pk(q, c)])));
     }
     __syncthreads();
   }
-  // R = L^H D with zero rows for dead columns; Racc <- R Racc (upper triangular)
-  for (int idx = tid; idx < m0 * m0; idx += 256) {
-    const int a = idx / m0, b = idx % m0;
-    c2 v = cmk(0.0, 0.0);
-    if (b >= a && !dead[a]) {
-      if (accumulate) {
-        for (int e = a; e <= b; ++e) v = cadd(v, cmul(cscale(dsc[e], cconj(L[pk(e, a)])), Ra[e * m0 + b]));
-      } else {
-        v = cscale(dsc[b], cconj(L[pk(b, a)]));
-      }
+  // R = L^H D with zero rows for dead columns; Racc <- R Racc (upper triangular).  The
+  // previous Racc is staged in LDS when it fits beside L, else read from global memory
+  // eight entries at a time.
+  if (accumulate) {
+    c2* Rs = x + m0;
+    const bool staged = ra_in_lds != 0;
+    if (staged) {
+      for (int idx = tid; idx < m0 * m0; idx += blockDim.x) Rs[idx] = Ra[idx];
+      __syncthreads();
     }
-    tmp[idx] = v;
+    const c2* Rsrc = staged ? Rs : Ra;
+    for (int idx = tid; idx < m0 * m0; idx += blockDim.x) {
+      const int a = idx / m0, b = idx % m0;
+      c2 v = cmk(0.0, 0.0);
+      if (b >= a && !dead[a]) {
+        for (int e0 = a; e0 <= b; e0 += 8) {
+          c2 rv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) rv[u] = (e0 + u <= b) ? Rsrc[(e0 + u) * m0 + b] : cmk(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (e0 + u <= b) v = cadd(v, cmul(cscale(dsc[e0 + u], cconj(L[pk(e0 + u, a)])), rv[u]));
+        }
+      }
+      tmp[idx] = v;
+    }
+  } else {
+    for (int idx = tid; idx < m0 * m0; idx += blockDim.x) {
+      const int a = idx / m0, b = idx % m0;
+      tmp[idx] = (b >= a && !dead[a]) ? cscale(dsc[b], cconj(L[pk(b, a)])) : cmk(0.0, 0.0);
+    }
   }
   __syncthreads();
-  for (int idx = tid; idx < m0 * m0; idx += 256) Ra[idx] = tmp[idx];
-  // L <- L^{-1} in place, trailing block first
+  for (int idx = tid; idx < m0 * m0; idx += blockDim.x) Ra[idx] = tmp[idx];
+  // L <- L^{-1} in place, trailing block first; each row's dot product is split over 8
+  // consecutive lanes and summed with shuffles
   for (int j = m0 - 1; j >= 0; --j) {
-    for (int i = j + 1 + tid; i < m0; i += 256) x[i] = L[pk(i, j)];
-    if (tid == 0) L[pk(j, j)] = cmk(1.0 / L[pk(j, j)].x, 0.0);
+    for (int i = j + 1 + tid; i < m0; i += blockDim.x) x[i] = L[pk(i, j)];
+    const double ljj = 1.0 / L[pk(j, j)].x;
     __syncthreads();
-    const double ljj = L[pk(j, j)].x;
-    for (int i = j + 1 + tid; i < m0; i += 256) {
+    const int nrows = m0 - 1 - j;
+    for (int base = 0; base < nrows; base += (int)blockDim.x / 8) {
+      const int i = j + 1 + base + tid / 8, part = tid % 8;
       c2 v = cmk(0.0, 0.0);
-      for (int k = j + 1; k <= i; ++k) v = cadd(v, cmul(L[pk(i, k)], x[k]));
-      L[pk(i, j)] = cscale(-ljj, v);
+      if (i < m0)
+        for (int k = j + 1 + part; k <= i; k += 8) v = cadd(v, cmul(L[pk(i, k)], x[k]));
+      for (int o = 1; o < 8; o <<= 1) {
+        v.x += __shfl_xor(v.x, o);
+        v.y += __shfl_xor(v.y, o);
+      }
+      if (i < m0 && part == 0) L[pk(i, j)] = cscale(-ljj, v);
     }
     __syncthreads();
+    if (tid == 0) L[pk(j, j)] = cmk(ljj, 0.0);
   }
+  __syncthreads();
   // Tinv = D^{-1} Ri with Ri = (L^{-1})^H; dead columns and rows are zero
-  for (int idx = tid; idx < m0 * m0; idx += 256) {
+  for (int idx = tid; idx < m0 * m0; idx += blockDim.x) {
     const int a = idx / m0, b = idx % m0;
     const c2 v = (b < a || dead[a] || dead[b]) ? cmk(0.0, 0.0) : cscale(1.0 / dsc[a], cconj(L[pk(b, a)]));
     store_realified(Tv, m2, a, b, v);
@@ -1064,13 +1092,17 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
-  const size_t lds = ((size_t)m0 * (m0 + 1) / 2 + m0) * sizeof(c2);
+  size_t lds = ((size_t)m0 * (m0 + 1) / 2 + m0) * sizeof(c2);
   if ((int64_t)lds + 2048 <= (int64_t)max_lds && getenv("IFEAST_CHOLQR_GLOBAL") == nullptr) {
+    // the previous R factor beside L when there is room
+    const size_t with_ra = lds + (size_t)m0 * m0 * sizeof(c2);
+    const int ra_in_lds = (accumulate && (int64_t)with_ra + 2048 <= (int64_t)max_lds) ? 1 : 0;
+    if (ra_in_lds) lds = with_ra;
     if (lds > 64 * 1024)
       IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_cholqr_lds<T>), dim3(ns), dim3(256), lds, st, m0, G, shift_rel, dead_thr, tau_dep, active,
-                       Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
+    hipLaunchKernelGGL((k_cholqr_lds<T>), dim3(ns), dim3(512), lds, st, m0, G, shift_rel, dead_thr, tau_dep, active,
+                       Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work), ra_in_lds);
   } else {
     hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, dead_thr, tau_dep,
                        active, Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));

@@ -87,6 +87,12 @@ enum { IFEAST_PREC_FP64 = 0,   /* complex FP64 inner solves */
 enum { IFEAST_PROBLEM_SYMMETRIC = 0, IFEAST_PROBLEM_GENERAL = 1 };
 enum { IFEAST_GUESS_RITZ = 0,  /* inner initial guess X (z - Lambda)^{-1} */
        IFEAST_GUESS_ZERO = 1 };/* zero initial guess, right-hand side B X (Algorithm 2 as printed) */
+enum { IFEAST_BASIS_AUTO = 0,      /* shared for B = I, per shift otherwise */
+       IFEAST_BASIS_SHARED = 1,    /* one real block Arnoldi of A serves every shift (B = I only): the shifted
+                                      block Krylov spaces from R (z_s - Lambda)^{-1} coincide, so up to
+                                      max_inner * max_cycles block steps run without restarts and only the
+                                      small least-squares problems are per shift */
+       IFEAST_BASIS_PER_SHIFT = 2 };/* per shift complex block GMRES(max_inner), restarted up to max_cycles */
 enum { IFEAST_INNER_GLOBAL = 0,/* stop when every column residual <= alpha ||R_F|| (Algorithm 2, step 1) */
        IFEAST_INNER_COLUMN = 1 };/* column j stops when its residual fell by alpha (Eq. alpha with alpha_j = alpha) */
 
@@ -101,12 +107,14 @@ typedef struct {
   double reorth_eta;   /* block Gram-Schmidt in the Arnoldi step: a second classical pass runs for a shift
                           when some column kept less than this fraction of its norm in the first one,
                           and the block is normalised by one Cholesky-QR pass when its Gram is certified
-                          well conditioned (two passes otherwise); 0 selects 0.1; >= 1 always runs two
-                          Gram-Schmidt and two Cholesky-QR passes */
+                          well conditioned (two passes otherwise); >= 1 always runs two Gram-Schmidt and
+                          two Cholesky-QR passes; 0 selects 0.1 for per-shift bases and 2 (always two
+                          passes) for the shared basis, whose long recurrence needs them */
   int precision;       /* IFEAST_PREC_* */
   int problem;         /* IFEAST_PROBLEM_* */
   int inner_guess;     /* IFEAST_GUESS_* */
   int inner_rule;      /* IFEAST_INNER_* */
+  int basis;           /* IFEAST_BASIS_* */
   uint64_t seed;       /* seed of the initial block when X0 is NULL */
 } ifeast_params;
 

@@ -20,6 +20,9 @@ from ._binding import (
     exported_symbols,
     PREC_FP64,
     PREC_MIXED,
+    BASIS_AUTO,
+    BASIS_SHARED,
+    BASIS_PER_SHIFT,
     FLAG_INSIDE,
     FLAG_SPURIOUS,
     STATUS,
@@ -38,6 +41,9 @@ __all__ = [
     "exported_symbols",
     "PREC_FP64",
     "PREC_MIXED",
+    "BASIS_AUTO",
+    "BASIS_SHARED",
+    "BASIS_PER_SHIFT",
     "FLAG_INSIDE",
     "FLAG_SPURIOUS",
     "STATUS",

@@ -41,7 +41,8 @@ class ParamsStruct(C.Structure):
     _fields_ = [("m0", C.c_int), ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_cycles", C.c_int),
                 ("alpha", C.c_double), ("tol", C.c_double), ("spurious_tau", C.c_double),
                 ("reorth_eta", C.c_double), ("precision", C.c_int),
-                ("problem", C.c_int), ("inner_guess", C.c_int), ("inner_rule", C.c_int), ("seed", C.c_uint64)]
+                ("problem", C.c_int), ("inner_guess", C.c_int), ("inner_rule", C.c_int), ("basis", C.c_int),
+                ("seed", C.c_uint64)]
 
 
 class ResultStruct(C.Structure):
@@ -61,6 +62,7 @@ class KernelStatStruct(C.Structure):
     _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
 
+BASIS_AUTO, BASIS_SHARED, BASIS_PER_SHIFT = 0, 1, 2
 KERNEL_SPMM, KERNEL_GRAM, KERNEL_UPDATE, KERNEL_QACC, KERNEL_OUTER = 0, 1, 2, 3, 4
 KERNEL_NAMES = {KERNEL_SPMM: "spmm", KERNEL_GRAM: "gram", KERNEL_UPDATE: "update", KERNEL_QACC: "qacc",
                 KERNEL_OUTER: "outer"}
@@ -160,10 +162,10 @@ def contour_struct(c: dict):
 
 def params_struct(m0, max_outer=50, max_inner=8, max_cycles=20, alpha=1e-2, tol=1e-9, tau=0.5,
                   precision=PREC_FP64, problem=PROBLEM_SYMMETRIC, inner_guess=GUESS_RITZ, inner_rule=INNER_COLUMN,
-                  seed=0, reorth_eta=0.0):
+                  seed=0, reorth_eta=0.0, basis=0):
     return ParamsStruct(int(m0), int(max_outer), int(max_inner), int(max_cycles), float(alpha), float(tol),
                         float(tau), float(reorth_eta), int(precision), int(problem), int(inner_guess),
-                        int(inner_rule), int(seed))
+                        int(inner_rule), int(basis), int(seed))
 
 
 def _params_from(p, precision):

@@ -96,6 +96,10 @@ Shape make_shape(int64_t n, bool hasB, const ifeast_contour* C, const ifeast_par
   s.k = p->max_inner;
   s.hasB = hasB;
   s.precision = p->precision;
+  if (p->basis == IFEAST_BASIS_SHARED && hasB)
+    throw Error{IFEAST_ERR_UNSUPPORTED, "a shared Krylov basis needs B = I"};
+  s.shared = !hasB && p->basis != IFEAST_BASIS_PER_SHIFT;
+  s.kb = s.shared ? p->max_inner * p->max_cycles : p->max_inner;
   return s;
 }
 
@@ -112,7 +116,8 @@ static std::map<ifeast_ctx*, EngineCache> g_cache;
 
 namespace {
 bool same(const Shape& a, const Shape& b) {
-  return a.n == b.n && a.m0 == b.m0 && a.ns == b.ns && a.k == b.k && a.hasB == b.hasB && a.precision == b.precision;
+  return a.n == b.n && a.m0 == b.m0 && a.ns == b.ns && a.k == b.k && a.hasB == b.hasB && a.precision == b.precision &&
+         a.shared == b.shared && a.kb == b.kb;
 }
 Engine& engine_for(ifeast_ctx* ctx, const Shape& s) {
   std::lock_guard<std::mutex> lk(g_cache_mu);

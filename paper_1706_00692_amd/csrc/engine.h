@@ -22,6 +22,8 @@ struct Shape {
   int m0, ns, k;
   bool hasB;
   int precision;
+  bool shared = false;  // one real Krylov basis for all shifts (B = I)
+  int kb = 0;           // basis capacity in blocks: k (per shift) or k * max_cycles (shared)
 };
 uint64_t workspace_bytes(const Shape& s);
 

@@ -132,6 +132,8 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
   IF_REQUIRE(p.alpha >= 0.0 && p.alpha < 1.0, "alpha must be in [0, 1)");
   IF_REQUIRE(p.tol > 0.0, "tol must be positive");
   IF_REQUIRE(p.reorth_eta >= 0.0, "reorth_eta must be >= 0");
+  IF_REQUIRE(p.basis == IFEAST_BASIS_AUTO || p.basis == IFEAST_BASIS_SHARED || p.basis == IFEAST_BASIS_PER_SHIFT,
+             "unknown basis mode");
   IF_REQUIRE(p.precision == IFEAST_PREC_FP64 || p.precision == IFEAST_PREC_MIXED, "unknown precision");
   IF_REQUIRE(p.inner_rule == IFEAST_INNER_GLOBAL || p.inner_rule == IFEAST_INNER_COLUMN, "unknown inner rule");
   if (p.problem != IFEAST_PROBLEM_SYMMETRIC)
@@ -158,11 +160,13 @@ struct Layout {
   // byte sizes of every buffer of the workspace
   size_t X, Q, AQ, BQ, R, vec, mm, rrwork, colpart;
   size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gw, Hr, Tinv, Racc, chol, Yq, Uc, zs;
+  size_t Hm, Ss;  // shared basis: real block Hessenberg, per-shift start blocks
 };
 
 Layout layout(const Shape& s) {
   const size_t ts = s.precision == IFEAST_PREC_MIXED ? 4 : 8;
-  const size_t n = (size_t)s.n, m0 = s.m0, ns = s.ns, k = s.k, m2 = 2 * m0;
+  const size_t n = (size_t)s.n, m0 = s.m0, ns = s.ns, m2 = 2 * m0;
+  const size_t k = s.kb;  // basis capacity in blocks
   const size_t ldc = ns * m0, ldh = (k + 1) * m0;
   Layout L{};
   L.X = L.Q = L.R = n * m0 * 8;
@@ -172,15 +176,40 @@ Layout layout(const Shape& s) {
   L.mm = m0 * m0 * 8;
   L.rrwork = (4 * m0 * m0 + 4 * m0) * 8;
   L.colpart = (size_t)col_sumsq_blocks(s.n) * m0 * 8;
-  L.V = (k + 1) * n * ldc * 2 * ts;
-  L.T1 = n * ldc * 2 * ts;
+  // per-shift least squares (both modes)
   L.H = ns * ldh * k * m0 * 16;
   L.Vh = ns * k * m2 * m0 * 16;
   L.tauh = ns * k * m0 * 8;
-  L.g = L.u = ns * ldh * m0 * 16;
+  L.g = ns * ldh * m0 * 16;
   L.y = ns * k * m0 * m0 * 16;
   L.flags = 16 * 64 * 4;
   L.tol = ns * m0 * 8 * 2;
+  L.Racc = ns * m0 * m0 * 16;
+  L.chol = ns * 3 * m0 * m0 * 16;
+  L.zs = 4 * 64 * 8;
+  if (s.shared) {
+    // one real basis of k + 1 blocks (n x m0), real products of width m0
+    L.V = (k + 1) * n * m0 * ts;
+    L.T1 = n * m0 * ts;
+    L.u = 16;
+    size_t gp = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
+    for (size_t items = 1; items <= k; ++items)
+      gp = std::max(gp, ts == 4 ? gram_partial_bytes<float>(s.n, (int)m0, (int)m0, (int)items)
+                                : gram_partial_bytes<double>(s.n, (int)m0, (int)m0, (int)items));
+    L.gpart = gp;
+    L.gred = std::max(k * m0 * m0, 2 * m0 * m0) * 8;
+    L.gw = m0 * m0 * 8;
+    L.Hr = k * m0 * m0 * ts;
+    L.Tinv = m0 * m0 * ts;
+    L.Yq = k * m0 * m0 * ts;
+    L.Uc = 16;
+    L.Hm = ldh * k * m0 * 8;
+    L.Ss = ns * m0 * m0 * 16;
+    return L;
+  }
+  L.V = (k + 1) * n * ldc * 2 * ts;
+  L.T1 = n * ldc * 2 * ts;
+  L.u = L.g;
   // the split count depends on the item count: take the largest over every step's Gram
   size_t gp = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
   for (size_t items = ns; items <= ns * k; items += ns)
@@ -191,18 +220,17 @@ Layout layout(const Shape& s) {
   L.gw = ns * m2 * m2 * 8;
   L.Hr = ns * k * m2 * m2 * ts;
   L.Tinv = ns * m2 * m2 * ts;
-  L.Racc = ns * m0 * m0 * 16;
-  L.chol = ns * 3 * m0 * m0 * 16;
   L.Yq = ns * k * m2 * m0 * ts;
   L.Uc = ns * (k + 1) * m2 * m2 * ts;
-  L.zs = 4 * 64 * 8;
+  L.Hm = 0;
+  L.Ss = 0;
   return L;
 }
 
 size_t total(const Layout& L) {
   return 3 * L.X + L.AQ + L.BQ + L.R + 8 * L.vec + 3 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
-         L.tauh + 2 * L.g + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq + L.Uc +
-         3 * L.zs;
+         L.tauh + L.g + L.u + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq +
+         L.Uc + 3 * L.zs + L.Hm + L.Ss;
 }
 
 }  // namespace
@@ -267,6 +295,9 @@ struct Engine::Impl {
   DevBuf X, Q, Xn, AQ, BQ, R, lam, resid, eta, rho, C, GA, GB, rrwork, colpart, clsout;
   // inner
   DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gwb, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
+  DevBuf Hm, Ss;             // shared basis
+  int* d_one = nullptr;      // a single 1 (the shared block's activity flag)
+  int shared_steps = 0;      // Arnoldi steps of the last shared inner solve
   int* d_active = nullptr;  // ns
   int* d_run = nullptr;     // ns
   int* d_cont = nullptr;    // ns
@@ -323,6 +354,8 @@ struct Engine::Impl {
     zsT = DevBuf(L.zs);
     zsD = DevBuf(L.zs);
     wsD = DevBuf(L.zs);
+    if (L.Hm) Hm = DevBuf(L.Hm);
+    if (L.Ss) Ss = DevBuf(L.Ss);
     int* f = flags.as<int>();
     d_active = f;
     d_run = f + 64;
@@ -333,12 +366,16 @@ struct Engine::Impl {
     d_need = f + 448;
     d_single = f + 512;
     d_two = f + 576;
+    d_one = f + 640;
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
     // stale basis blocks of shifts that stopped early are multiplied by zero
     // coefficients later; zero them once so they are always finite
     launch_fill_zero(st, V.p, V.bytes);
     launch_fill_zero(st, H.p, H.bytes);
+    if (L.Hm) launch_fill_zero(st, Hm.p, Hm.bytes);
+    const int one = 1;
+    h2d(d_one, &one, sizeof(int));
   }
 
   // -------------------------------------------------------- Rayleigh-Ritz
@@ -409,8 +446,9 @@ struct Engine::Impl {
     LsqArgs a;
     a.ns = sh.ns;
     a.m0 = sh.m0;
-    a.k = sh.k;
-    a.ldh = (sh.k + 1) * sh.m0;
+    a.k = sh.kb;
+    a.ldh = (sh.kb + 1) * sh.m0;
+    a.need_u = sh.shared ? 0 : 1;
     a.H = H.as<cd>();
     a.Vh = Vh.as<cd>();
     a.tauh = tauh.as<double>();
@@ -439,6 +477,137 @@ struct Engine::Impl {
   }
   void h2d(void* d, const void* h, size_t bytes) {
     IF_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
+  }
+
+  // ------------------------------------------------- shared real basis
+  // Cholesky-QR of one real n x m0 block (two passes, the first shifted); G0: its Gram.
+  template <class T>
+  void cholqr2_real(const T* src, T* tmp, T* dst, const double* G0 = nullptr) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0;
+    const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
+    const T* in = src;
+    for (int pass = 0; pass < 2; ++pass) {
+      T* out = pass == 0 ? tmp : dst;
+      const double* G = gred.as<double>();
+      if (pass == 0 && G0 != nullptr) {
+        G = G0;
+      } else {
+        GramArgs gg{n, m0, m0, 1, 1, in, m0, 0, 0, in, m0, 0, 0, nullptr, gred.as<double>()};
+        launch_gram<T>(st, gg, gpart.p, gpart.bytes);
+      }
+      launch_cholqr_factor<T>(st, 1, m0, G, pass == 0 ? 4.0 * m0 * eps : 0.0, nullptr, Tinv.as<T>(), Racc.as<cd>(),
+                              pass, chol.as<cd>(), true);
+      ApplyArgs ap{n, m0, m0, 1, 1, 1, in, m0, 0, 0, 0, Tinv.p, 0, out, m0, 0, 1.0, 0.0, nullptr, nullptr};
+      launch_apply<T, T>(st, ap);
+      in = out;
+    }
+  }
+
+  // Inner solves of all shifts on one real block Arnoldi of M = -A (B = I):
+  //   M V_j = V_{j+1} Hm,  (z_s I - A) V_j = V_{j+1} (z_s I~ + Hm),
+  // each shift's least squares min || [S0 D_s; 0] - (z_s I~ + Hm) y_s || updated per step
+  // and stopped by its own rule; Q = X rho_hat(Lambda) + V Re(sum_s wf_s y_s).
+  // Up to kb = k * max_cycles steps, no restarts.  Returns per-shift block iterations.
+  template <class T>
+  std::vector<int> inner_shared(const ifeast_matrix* A, const Nodes& nd, const ifeast_params& p, const double* Xd,
+                                const double* lamd, const double* Rd, const double* rhod,
+                                const std::vector<double>& tolh, double* Qd) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0, ns = sh.ns, K = sh.kb, ldh = (K + 1) * m0;
+    const int64_t bs = n * m0;  // elements per basis block
+    T* Vb = V.as<T>();
+    T* t1 = T1.as<T>();
+    T* t2 = T2.as<T>();
+    std::vector<double> zdv(2 * ns), wf(2 * ns);
+    for (int s = 0; s < ns; ++s) {
+      zdv[2 * s] = nd.z[s].real();
+      zdv[2 * s + 1] = nd.z[s].imag();
+      const cd f = nd.half ? 2.0 * nd.w[s] : nd.w[s];
+      wf[2 * s] = f.real();
+      wf[2 * s + 1] = f.imag();
+    }
+    const std::vector<T> zero(4, (T)0);
+    h2d(zsT.p, zero.data(), zero.size() * sizeof(T));
+    h2d(zsD.p, zdv.data(), zdv.size() * sizeof(double));
+    h2d(wsD.p, wf.data(), wf.size() * sizeof(double));
+    h2d(tol.p, tolh.data(), tolh.size() * sizeof(double));
+    // the long recurrence keeps its basis orthonormal only with two passes of both
+    // Gram-Schmidt and Cholesky-QR at every step (one pass loses orthogonality over the
+    // steps and the inner solves stall, in FP32 first), so that is the default here
+    reorth_eta = p.reorth_eta > 0.0 ? p.reorth_eta : 2.0;
+    single_gersh = sizeof(T) == 4 ? 0.8 : 0.5;
+    dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
+    const bool always = reorth_eta >= 1.0;
+    // Q = X rho_hat(Lambda); V_0 S0 = R
+    launch_scale_cols(st, n, m0, Xd, rhod, Qd);
+    launch_to_T<T>(st, bs, Rd, t1);
+    cholqr2_real<T>(t1, t2, Vb);
+    launch_start_rhs(st, ns, m0, Racc.as<cd>(), lamd, zsD.as<double>(), Ss.as<cd>());
+    std::vector<int> all(ns, 1);
+    h2d(d_active, all.data(), ns * sizeof(int));
+    h2d(d_run, all.data(), ns * sizeof(int));
+    note(d_active, all);
+    LsqArgs la = lsq_args();
+    // A is symmetric: Hm is block tridiagonal up to rounding (block Lanczos), so the least
+    // squares problems keep one block above the diagonal
+    la.band = 1;
+    launch_lsq_init(st, la, Ss.as<cd>());
+    auto cgs_pass = [&](int j, int accumulate) {
+      GramArgs gg{n, m0, m0, 1, j + 1, Vb, m0, 0, bs, t1, m0, 0, 0, nullptr, gred.as<double>()};
+      launch_gram<T>(st, gg, gpart.p, gpart.bytes);
+      launch_combine_real<T>(st, j + 1, m0, j, ldh, gred.as<double>(), Hm.as<double>(), Hr.as<T>(), accumulate);
+      ApplyArgs ap{n, m0, m0, 1, j + 1, j + 1, Vb, m0, 0, 0, bs, Hr.p, 0, t1, m0, 0, -1.0, 1.0, nullptr, nullptr};
+      launch_apply<T, T>(st, ap);
+    };
+    int jdone = 0;
+    for (int j = 0; j < K; ++j) {
+      // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
+      // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike)
+      launch_spmm_shifted<T>(st, A, nullptr, 1, m0 / 2, zsT.as<T>(), nullptr, Vb + (int64_t)j * bs, t1);
+      cgs_pass(j, 0);
+      if (always) {
+        cgs_pass(j, 1);
+        ++reorth_steps;
+      }
+      GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
+      launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+      std::vector<int> fl{0, 0, 1};
+      if (!always) {
+        launch_orth_check_real(st, m0, j, ldh, reorth_eta, single_gersh, dead_thr, gwb.as<double>(), Hm.as<double>(),
+                               d_need);
+        fl = d2h_ints(d_need, 3);
+      }
+      if (fl[0]) {
+        cgs_pass(j, 1);
+        launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+        ++reorth_steps;
+      }
+      T* dst = Vb + (int64_t)(j + 1) * bs;
+      if (fl[1]) {
+        launch_cholqr_factor<T>(st, 1, m0, gwb.as<double>(), 0.0, nullptr, Tinv.as<T>(), Racc.as<cd>(), 0,
+                                chol.as<cd>(), true);
+        ApplyArgs ap{n, m0, m0, 1, 1, 1, t1, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
+        launch_apply<T, T>(st, ap);
+        ++single_steps;
+      } else {
+        cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
+      }
+      launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
+      launch_shift_column(st, ns, m0, j, ldh, K, zsD.as<double>(), d_active, Hm.as<double>(), H.as<cd>(), la.band);
+      launch_lsq_step(st, la, j);
+      jdone = j + 1;
+      const std::vector<int> act = d2h_ints(d_active, ns);
+      note(d_active, act);
+      if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) break;
+    }
+    shared_steps = jdone;
+    launch_lsq_finish(st, la);
+    launch_sum_y<T>(st, ns, m0, K, jdone, y.as<cd>(), wsD.as<double>(), Yq.as<T>());
+    ApplyArgs aq{n, m0, m0, 1, jdone, jdone, Vb, m0, 0, 0, bs, Yq.p, 0, Qd, m0, 0, 1.0, 1.0, nullptr, nullptr,
+                 KC_QACC};
+    launch_apply<T, double>(st, aq);
+    return d2h_ints(d_iters, ns);
   }
 
   // --------------------------------------------------------- inner solve
@@ -680,9 +849,15 @@ void Engine::filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast
   IF_HIP(hipMemcpyAsync(residh.data(), I.resid.p, m0 * 8, hipMemcpyDeviceToHost, st_));
   IF_HIP(hipStreamSynchronize(st_));
   const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, rf, m0);
-  std::vector<int> it = shape_.precision == IFEAST_PREC_MIXED
-                            ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
-                            : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+  std::vector<int> it;
+  if (shape_.shared)
+    it = shape_.precision == IFEAST_PREC_MIXED
+             ? I.inner_shared<float>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+             : I.inner_shared<double>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+  else
+    it = shape_.precision == IFEAST_PREC_MIXED
+             ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+             : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
   IF_HIP(hipStreamSynchronize(st_));
   if (iters) *iters = it;
 }
@@ -757,18 +932,30 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   int status = IFEAST_WARN_NOT_CONVERGED;
   for (int it = 0; it < p.max_outer; ++it) {
     const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, stats.rf, m0);
-    std::vector<int> iters = shape_.precision == IFEAST_PREC_MIXED
-                                 ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
-                                 : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+    std::vector<int> iters;
+    if (shape_.shared)
+      iters = shape_.precision == IFEAST_PREC_MIXED
+                  ? I.inner_shared<float>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+                  : I.inner_shared<double>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+    else
+      iters = shape_.precision == IFEAST_PREC_MIXED
+                  ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+                  : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
     I.rr(A, B, Q, X, lam, R, resid, eta);
     classify(p.spurious_tau);
     stats.outer = it + 1;
     stats.rf_hist.push_back(stats.rf);
+    // matrix-vector products: one real block of m0 columns per shared Arnoldi step, or one
+    // complex block per shift and step
     int mx = 0;
     for (int s = 0; s < ns; ++s) {
       stats.inner_hist.push_back(iters[s]);
-      stats.total_matvec += (int64_t)iters[s] * m0;
+      if (!shape_.shared) stats.total_matvec += (int64_t)iters[s] * m0;
       mx = std::max(mx, iters[s]);
+    }
+    if (shape_.shared) {
+      stats.total_matvec += (int64_t)I.shared_steps * m0;
+      mx = I.shared_steps;
     }
     stats.seq_matvec += mx;
     if (verbose) {

@@ -194,10 +194,11 @@ void launch_apply(hipStream_t st, const ApplyArgs& a);
 // CholQR factor from the Gram of the block: per shift s,
 //   G (2m0 x 2m0 real view of W^H W) -> column scaling, optional shift,
 //   Cholesky -> Tinv (real-ified, type T, 2m0 x 2m0) and Rf (complex m0 x m0,
-//   W = W_new Rf); if `accumulate`, Racc = Rf * Racc_prev.
+//   W = W_new Rf); if `accumulate`, Racc = Rf * Racc_prev.  real: G is the m0 x m0
+//   Gram of a real block and Tinv real m0 x m0 (Rf then has zero imaginary parts).
 template <class T>
 void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, double shift_rel, const int* active,
-                          T* Tinv, cd* Racc, int accumulate, cd* work /*ns x 3 m0^2*/);
+                          T* Tinv, cd* Racc, int accumulate, cd* work /*ns x 3 m0^2*/, bool real = false);
 
 // CGS combine: for items (s, i), i < ni: C = complex(G) -> H[s](i-block rows, j-block col) = C
 // (+= C when accumulate), Hr[s, i] = real-ified C (type T) for the update W -= V Hr.
@@ -230,7 +231,31 @@ struct LsqArgs {
   int* active;        // ns: shift still iterating in this cycle
   int* iters;         // ns: block iterations in this cycle
   int* cycle_done;    // ns: 1 if the shift met its tolerance
+  int need_u = 1;     // lsq_finish also forms u (restart residual coefficients)
+  int band = 0;       // > 0: block column j of Hbar is zero above block row j - band (and R above
+                      // block row j - band - 1), so only the reflectors of steps >= j - band - 1 act on it
 };
+// ---- shared-basis inner solve (shared.hip): Arnoldi of M = -A on real blocks
+template <class T>
+void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
+// Gram-Schmidt coefficients G (ni items m0 x m0) -> block column j of Hm (FP64, column-major
+// ldh) and update factors Hr (type T)
+template <class T>
+void launch_combine_real(hipStream_t st, int ni, int m0, int j, int ldh, const double* G, double* Hm, T* Hr,
+                         int accumulate);
+// flags[0..2] = need second pass, one Cholesky-QR pass enough, two passes
+void launch_orth_check_real(hipStream_t st, int m0, int j, int ldh, double eta, double gersh, double dead_thr,
+                            const double* G, const double* Hm, int* flags);
+void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
+// block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
+void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,
+                         const double* Hm, cd* H, int band);
+// S_s = S0 diag(1 / (z_s - lambda)) (ns x m0 x m0 row-major)
+void launch_start_rhs(hipStream_t st, int ns, int m0, const cd* S0, const double* lam, const double* z, cd* S);
+// Yr[b] = Re sum_s wf_s y_s block b (b < jmax), m0 x m0 each, type T
+template <class T>
+void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* y, const double* wf, T* Yr);
+
 void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S /*ns x m0 x m0 row-major*/);
 void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j);
 void launch_lsq_finish(hipStream_t st, const LsqArgs& a);

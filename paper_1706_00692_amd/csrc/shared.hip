@@ -1,0 +1,191 @@
+// Kernels of the shared-basis inner solve (standard problems, B = I).
+//
+// For B = I the block Krylov space of z_s I - A from the right-hand side
+// R (z_s - Lambda)^{-1} is that of A from R for every shift z_s: a diagonal
+// scaling of the block's columns and a shift of the operator leave the block
+// Krylov space unchanged (Sec. 3.2 solves each shifted system from B X or its
+// residual form; the spaces coincide).  One real block Arnoldi
+//     M V_j = V_{j+1} Hm,   M = -A
+// therefore serves all shifts: (z_s I - A) V_j = V_{j+1} (z_s I~ + Hm), and only
+// the small least-squares problems, with right-hand sides [S0 D_s; 0], differ
+// per shift.  The helpers below move data between the shared real block
+// Hessenberg Hm and the per-shift complex ones the least-squares kernels use.
+#include "internal.h"
+
+namespace ifeast {
+
+namespace {
+
+typedef double2 c2;
+__device__ inline c2 cmk(double r, double i) { return make_double2(r, i); }
+__device__ inline c2 cmul(c2 a, c2 b) { return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline c2 cdiv(c2 a, c2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return cmk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+inline unsigned nblk(int64_t total) { return (unsigned)((total + 255) / 256); }
+
+template <class T>
+__global__ void k_to_T(int64_t count, const double* __restrict__ X, T* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) Y[i] = (T)X[i];
+}
+
+// Coefficients of one Gram-Schmidt pass: G = [V_0..V_j]^T W (ni = j+1 items of m0 x m0,
+// item-major, row a = basis column) -> block column j of Hm (+= when accumulating)
+// and the update factors Hr (same layout as G, type T) for W -= sum_i V_i Hr_i.
+template <class T>
+__global__ void k_combine_real(int ni, int m0, int j, int ldh, const double* __restrict__ G,
+                               double* __restrict__ Hm, T* __restrict__ Hr, int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)m0 * m0;
+  if (idx >= ni * per) return;
+  const int i = (int)(idx / per);
+  const int a = (int)((idx % per) / m0), b = (int)(idx % m0);
+  const double c = G[idx];
+  double* h = Hm + (int64_t)(j * m0 + b) * ldh + i * m0 + a;
+  *h = accumulate ? *h + c : c;
+  Hr[idx] = (T)c;
+}
+
+// need / single / twopass flags of the shared block (see k_orth_check): G = W1^T W1 real
+// (m0 x m0), H = block column j of Hm (rows 0..(j+1) m0).
+__global__ void k_orth_check_real(int m0, int j, int ldh, double eta2, double gersh, double dead_thr,
+                                  const double* __restrict__ G, const double* __restrict__ Hm,
+                                  int* __restrict__ flags /* need, single, twopass */) {
+  __shared__ int any_need, any_bad;
+  __shared__ double dsc[128];
+  if (threadIdx.x == 0) any_need = any_bad = 0;
+  __syncthreads();
+  const double* Hc = Hm + (int64_t)j * m0 * ldh;
+  for (int c = threadIdx.x; c < m0; c += blockDim.x) {
+    const double w1 = G[c * m0 + c];
+    double h = 0.0;
+    for (int r = 0; r < (j + 1) * m0; ++r) h += Hc[r + (int64_t)c * ldh] * Hc[r + (int64_t)c * ldh];
+    if (w1 > 1e-30 && w1 < eta2 * (w1 + h)) atomicOr(&any_need, 1);
+    if (!(w1 > dead_thr)) atomicOr(&any_bad, 1);
+    dsc[c] = sqrt(fmax(w1, 1e-300));
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < m0; r += blockDim.x) {
+    double off = 0.0;
+    for (int c = 0; c < m0; ++c)
+      if (c != r) off += fabs(G[r * m0 + c]) / (dsc[r] * dsc[c]);
+    if (!(off <= gersh)) atomicOr(&any_bad, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    flags[0] = any_need;
+    flags[1] = (any_need == 0 && any_bad == 0) ? 1 : 0;
+    flags[2] = flags[1] ? 0 : 1;
+  }
+}
+
+// Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
+__global__ void k_subdiag_real(int m0, int j, int ldh, const c2* __restrict__ Racc, double* __restrict__ Hm) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m0 * m0) return;
+  const int a = idx / m0, b = idx % m0;
+  Hm[(int64_t)(j * m0 + b) * ldh + (j + 1) * m0 + a] = Racc[idx].x;
+}
+
+// Block column j of every active shift's Hbar_s = z_s I~ + Hm (rows 0..(j+2) m0).
+// grid (ns, m0); one workgroup per (shift, column).
+// band > 0: rows above block row j - band are taken as zero (for symmetric A the
+// orthogonalisation coefficients there vanish in exact arithmetic: block Lanczos).
+__global__ void k_shift_column(int m0, int j, int ldh, int kcap, const double* __restrict__ z,
+                               const int* __restrict__ active, const double* __restrict__ Hm, c2* __restrict__ H,
+                               int band) {
+  const int s = blockIdx.x, c = blockIdx.y;
+  if (active[s] == 0) return;
+  const int col = j * m0 + c;
+  const double* src = Hm + (int64_t)col * ldh;
+  c2* dst = H + (int64_t)s * ldh * kcap * m0 + (int64_t)col * ldh;
+  const double zr = z[2 * s], zi = z[2 * s + 1];
+  const int r0 = band > 0 ? max(0, j - band) * m0 : 0;
+  for (int r = threadIdx.x; r < (j + 2) * m0; r += blockDim.x)
+    dst[r] = r < r0 ? cmk(0.0, 0.0) : (r == col) ? cmk(src[r] + zr, zi) : cmk(src[r], 0.0);
+}
+
+// Right-hand side of shift s in the basis: S_s = S0 diag(1 / (z_s - lambda_c)), row-major.
+__global__ void k_start_rhs(int ns, int m0, const c2* __restrict__ S0, const double* __restrict__ lam,
+                            const double* __restrict__ z, c2* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ns * m0 * m0) return;
+  const int s = (int)(idx / ((int64_t)m0 * m0));
+  const int rc = (int)(idx % ((int64_t)m0 * m0));
+  const int c = rc % m0;
+  S[idx] = cdiv(cmk(S0[rc].x, 0.0), cmk(z[2 * s] - lam[c], z[2 * s + 1]));
+}
+
+// Yr[b] (m0 x m0, type T, row k = basis column, column o) = Re sum_s wf_s y_s[b m0 + k][o]
+// for b < jmax: Q += V_b Yr[b] is the quadrature sum's correction.
+template <class T>
+__global__ void k_sum_y(int ns, int m0, int kcap, int jmax, const c2* __restrict__ y, const double* __restrict__ wf,
+                        T* __restrict__ Yr) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)jmax * m0 * m0) return;
+  const int b = (int)(idx / ((int64_t)m0 * m0));
+  const int k = (int)((idx / m0) % m0), o = (int)(idx % m0);
+  const int64_t ldy = (int64_t)kcap * m0;
+  double acc = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const c2 v = y[(int64_t)s * kcap * m0 * m0 + o * ldy + b * m0 + k];
+    acc += wf[2 * s] * v.x - wf[2 * s + 1] * v.y;
+  }
+  Yr[idx] = (T)acc;
+}
+
+}  // namespace
+
+template <class T>
+void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y) {
+  hipLaunchKernelGGL((k_to_T<T>), dim3(nblk(count)), dim3(256), 0, st, count, X, Y);
+  IF_HIP(hipGetLastError());
+}
+template <class T>
+void launch_combine_real(hipStream_t st, int ni, int m0, int j, int ldh, const double* G, double* Hm, T* Hr,
+                         int accumulate) {
+  hipLaunchKernelGGL((k_combine_real<T>), dim3(nblk((int64_t)ni * m0 * m0)), dim3(256), 0, st, ni, m0, j, ldh, G, Hm,
+                     Hr, accumulate);
+  IF_HIP(hipGetLastError());
+}
+void launch_orth_check_real(hipStream_t st, int m0, int j, int ldh, double eta, double gersh, double dead_thr,
+                            const double* G, const double* Hm, int* flags) {
+  IF_REQUIRE(m0 <= 128, "orth check: m0 > 128");
+  hipLaunchKernelGGL(k_orth_check_real, dim3(1), dim3(128), 0, st, m0, j, ldh, eta * eta, gersh, dead_thr, G, Hm,
+                     flags);
+  IF_HIP(hipGetLastError());
+}
+void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {
+  hipLaunchKernelGGL(k_subdiag_real, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh,
+                     reinterpret_cast<const c2*>(Racc), Hm);
+  IF_HIP(hipGetLastError());
+}
+void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,
+                         const double* Hm, cd* H, int band) {
+  hipLaunchKernelGGL(k_shift_column, dim3(ns, m0), dim3(256), 0, st, m0, j, ldh, kcap, z, active, Hm,
+                     reinterpret_cast<c2*>(H), band);
+  IF_HIP(hipGetLastError());
+}
+void launch_start_rhs(hipStream_t st, int ns, int m0, const cd* S0, const double* lam, const double* z, cd* S) {
+  hipLaunchKernelGGL(k_start_rhs, dim3(nblk((int64_t)ns * m0 * m0)), dim3(256), 0, st, ns, m0,
+                     reinterpret_cast<const c2*>(S0), lam, z, reinterpret_cast<c2*>(S));
+  IF_HIP(hipGetLastError());
+}
+template <class T>
+void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* y, const double* wf, T* Yr) {
+  hipLaunchKernelGGL((k_sum_y<T>), dim3(nblk((int64_t)jmax * m0 * m0)), dim3(256), 0, st, ns, m0, kcap, jmax,
+                     reinterpret_cast<const c2*>(y), wf, Yr);
+  IF_HIP(hipGetLastError());
+}
+
+template void launch_to_T<float>(hipStream_t, int64_t, const double*, float*);
+template void launch_to_T<double>(hipStream_t, int64_t, const double*, double*);
+template void launch_combine_real<float>(hipStream_t, int, int, int, int, const double*, double*, float*, int);
+template void launch_combine_real<double>(hipStream_t, int, int, int, int, const double*, double*, double*, int);
+template void launch_sum_y<float>(hipStream_t, int, int, int, int, const cd*, const double*, float*);
+template void launch_sum_y<double>(hipStream_t, int, int, int, int, const cd*, const double*, double*);
+
+}  // namespace ifeast

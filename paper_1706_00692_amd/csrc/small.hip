@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_cholqr_factor(int m0, const double* __r
 // Tinv = D^{-1} (L^{-1})^H is written out.  One workgroup per shift.
 __device__ inline int pk(int r, int c) { return r * (r + 1) / 2 + c; }
 
-template <class T>
+template <class T, bool REAL>
 __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __restrict__ G, double shift_rel,
                                                     double dead_thr, double tau_dep, const int* __restrict__ active,
                                                     T* __restrict__ Tinv, c2* __restrict__ Racc, int accumulate,
@@ -198,16 +198,19 @@ __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __rest
   extern __shared__ c2 lds_c2[];
   c2* L = lds_c2;                       // m0 (m0 + 1) / 2
   c2* x = L + m0 * (m0 + 1) / 2;        // m0
+  // REAL: G is the m0 x m0 Gram of a real block and Tinv the real m0 x m0 factor;
+  // otherwise G and Tinv are real views (2m0 x 2m0) of complex ones
   const int tid = threadIdx.x, m2 = 2 * m0;
-  const double* Gs = G + (int64_t)s * m2 * m2;
-  T* Tv = Tinv + (int64_t)s * m2 * m2;
+  const int gw = REAL ? m0 : m2;
+  const double* Gs = G + (int64_t)s * gw * gw;
+  T* Tv = Tinv + (int64_t)s * gw * gw;
   c2* Ra = Racc + (int64_t)s * m0 * m0;
   c2* tmp = work + (int64_t)s * 3 * m0 * m0;
   __shared__ double dsc[128];
   __shared__ int dead[128];
 
   for (int a = tid; a < m0; a += blockDim.x) {
-    const double g = Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1];
+    const double g = REAL ? Gs[a * m0 + a] : Gs[(2 * a) * m2 + 2 * a] + Gs[(2 * a + 1) * m2 + 2 * a + 1];
     const bool dd = !(g > dead_thr);
     dead[a] = dd ? 1 : 0;
     dsc[a] = dd ? 1.0 : sqrt(g);
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __rest
     if (dead[a] || dead[b]) {
       g = cmk(a == b ? 1.0 : 0.0, 0.0);
     } else {
-      g = cscale(1.0 / (dsc[a] * dsc[b]), gram_entry(Gs, m2, a, b));
+      g = cscale(1.0 / (dsc[a] * dsc[b]), REAL ? cmk(Gs[a * m0 + b], 0.0) : gram_entry(Gs, m2, a, b));
       if (a == b) g = cmk(g.x + shift_rel, 0.0);
     }
     L[pk(a, b)] = g;
@@ -308,7 +311,10 @@ __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __rest
   for (int idx = tid; idx < m0 * m0; idx += blockDim.x) {
     const int a = idx / m0, b = idx % m0;
     const c2 v = (b < a || dead[a] || dead[b]) ? cmk(0.0, 0.0) : cscale(1.0 / dsc[a], cconj(L[pk(b, a)]));
-    store_realified(Tv, m2, a, b, v);
+    if (REAL)
+      Tv[a * m0 + b] = (T)v.x;
+    else
+      store_realified(Tv, m2, a, b, v);
   }
 }
 
@@ -502,7 +508,9 @@ __global__ __launch_bounds__(256) void k_lsq_init(LsqArgs a, const c2* __restric
 }
 
 // Step j, part 1: the reflectors of steps 0..j-1 on the new block column j of Hbar.
-// grid (ns, ceil(m0/4)); wave w of block y owns column 4y + w, staged in LDS.
+// grid (ns, ceil(m0/4)); wave w of block y owns column 4y + w, staged in LDS (in place
+// in global memory when the column is too long for LDS).
+template <bool GLOBAL>
 __global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
   extern __shared__ c2 colbuf[];  // 4 x (j+2) m0
   const int s = blockIdx.x;
@@ -513,13 +521,16 @@ __global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
   const int col = blockIdx.y * 4 + wave;
   if (col >= m0) return;
   const int rows = (j + 2) * m0;
-  c2* x = colbuf + wave * rows;
   c2* h = v.H + (int64_t)(j * m0 + col) * ldh;
-  for (int r = lane; r < rows; r += 64) x[r] = h[r];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  for (int i = 0; i < j; ++i)
+  c2* x = GLOBAL ? h : colbuf + wave * rows;
+  if (!GLOBAL) {
+    for (int r = lane; r < rows; r += 64) x[r] = h[r];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  for (int i = a.band > 0 ? max(0, j - a.band - 1) : 0; i < j; ++i)
     wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + i * m0, lane, false);
-  for (int r = lane; r < rows; r += 64) h[r] = x[r];
+  if (!GLOBAL)
+    for (int r = lane; r < rows; r += 64) h[r] = x[r];
 }
 
 // Step j, part 2: Householder QR of the slab rows [j m0, (j+2) m0) of block column j
@@ -736,6 +747,7 @@ __global__ void k_lsq_stop(LsqArgs a, int j) {
 
 // y = R^{-1} g_top (column-oriented back substitution, one wave per right-hand side)
 // and u = Q_H [0; g_tail] (reflectors in reverse order).  grid (ns, ceil(m0/4)).
+template <bool GLOBAL>
 __global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
   extern __shared__ c2 colbuf[];  // 4 x ldh
   const int s = blockIdx.x;
@@ -747,7 +759,8 @@ __global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
   const int col = blockIdx.y * 4 + wave;
   if (col >= m0) return;
   const int n = J * m0;
-  c2* x = colbuf + wave * ldh;
+  // GLOBAL: solve in place in the column of y (and form u in place in u)
+  c2* x = GLOBAL ? v.y + (int64_t)col * ldy : colbuf + wave * ldh;
   const c2* gc = v.g + (int64_t)col * ldh;
   for (int r = lane; r < n; r += 64) x[r] = gc[r];
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -755,19 +768,26 @@ __global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
     const c2* Rc = v.H + (int64_t)c * ldh;  // column c of R
     const c2 d = Rc[c];
     const c2 yc = cabs2(d) > 1e-300 ? cdiv(x[c], d) : cmk(0.0, 0.0);
-    for (int r = lane; r < c; r += 64) x[r] = csub(x[r], cmul(Rc[r], yc));
+    const int rlo = a.band > 0 ? max(0, (c / m0 - a.band - 1) * m0) : 0;
+    for (int r = rlo + lane; r < c; r += 64) x[r] = csub(x[r], cmul(Rc[r], yc));
     if (lane == 0) x[c] = yc;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
   c2* yc = v.y + (int64_t)col * ldy;
-  for (int r = lane; r < ldy; r += 64) yc[r] = r < n ? x[r] : cmk(0.0, 0.0);
+  for (int r = lane; r < ldy; r += 64)
+    if (!GLOBAL || r >= n) yc[r] = r < n ? x[r] : cmk(0.0, 0.0);
+  if (!a.need_u) return;
   // u = Q_H [0; g_tail]
+  if (GLOBAL) x = v.u + (int64_t)col * ldh;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   for (int r = lane; r < ldh; r += 64) x[r] = (r >= n && r < n + m0) ? gc[r] : cmk(0.0, 0.0);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   for (int i = J - 1; i >= 0; --i)
     wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + i * m0, lane, true);
-  c2* uc = v.u + (int64_t)col * ldh;
-  for (int r = lane; r < ldh; r += 64) uc[r] = x[r];
+  if (!GLOBAL) {
+    c2* uc = v.u + (int64_t)col * ldh;
+    for (int r = lane; r < ldh; r += 64) uc[r] = x[r];
+  }
 }
 
 // Yq[s][b]: (2m0 x m0) real form for Q += Re(V_b (wf y_b)); Uc[s][b]: (2m0 x 2m0) real form of u_b.
@@ -1078,7 +1098,7 @@ inline unsigned nblocks(int64_t total, int bs = 256) { return (unsigned)((total 
 // ------------------------------------------------------------------ launchers
 template <class T>
 void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, double shift_rel, const int* active,
-                          T* Tinv, cd* Racc, int accumulate, cd* work) {
+                          T* Tinv, cd* Racc, int accumulate, cd* work, bool real) {
   IF_REQUIRE(m0 <= 128, "cholqr: m0 > 128");
   // squared norms below this are not resolved by products in T
   const double dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
@@ -1098,21 +1118,31 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
     const size_t with_ra = lds + (size_t)m0 * m0 * sizeof(c2);
     const int ra_in_lds = (accumulate && (int64_t)with_ra + 2048 <= (int64_t)max_lds) ? 1 : 0;
     if (ra_in_lds) lds = with_ra;
-    if (lds > 64 * 1024)
-      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_cholqr_lds<T>), dim3(ns), dim3(512), lds, st, m0, G, shift_rel, dead_thr, tau_dep, active,
-                       Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work), ra_in_lds);
+    if (real) {
+      if (lds > 64 * 1024)
+        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T, true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL((k_cholqr_lds<T, true>), dim3(ns), dim3(512), lds, st, m0, G, shift_rel, dead_thr, tau_dep,
+                         active, Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work), ra_in_lds);
+    } else {
+      if (lds > 64 * 1024)
+        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T, false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL((k_cholqr_lds<T, false>), dim3(ns), dim3(512), lds, st, m0, G, shift_rel, dead_thr, tau_dep,
+                         active, Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work),
+                         ra_in_lds);
+    }
   } else {
+    IF_REQUIRE(!real, "cholqr: the real-block factor needs the LDS kernel");
     hipLaunchKernelGGL((k_cholqr_factor<T>), dim3(ns), dim3(256), 0, st, m0, G, shift_rel, dead_thr, tau_dep,
                        active, Tinv, reinterpret_cast<c2*>(Racc), accumulate, reinterpret_cast<c2*>(work));
   }
   IF_HIP(hipGetLastError());
 }
 template void launch_cholqr_factor<float>(hipStream_t, int, int, const double*, double, const int*, float*, cd*, int,
-                                          cd*);
+                                          cd*, bool);
 template void launch_cholqr_factor<double>(hipStream_t, int, int, const double*, double, const int*, double*, cd*,
-                                           int, cd*);
+                                           int, cd*, bool);
 
 template <class T>
 void launch_cgs_combine(hipStream_t st, int ns, int ni, int m0, int j, int ldh, const double* G, const int* active,
@@ -1148,21 +1178,25 @@ void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S) {
   IF_HIP(hipGetLastError());
 }
 void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
-  if (j > 0) {
-    const size_t lds = (size_t)4 * (j + 2) * a.m0 * sizeof(c2);
-    if (lds > 64 * 1024)
-      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_prev), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
-    hipLaunchKernelGGL(k_lsq_prev, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a, j);
-    IF_HIP(hipGetLastError());
-  }
-  // packed slab in LDS when it fits the workgroup's LDS
   static int max_lds = -1;
   if (max_lds < 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
+  if (j > 0) {
+    const size_t lds = (size_t)4 * (j + 2) * a.m0 * sizeof(c2);
+    if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
+      if (lds > 64 * 1024)
+        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_prev<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(k_lsq_prev<false>, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a, j);
+    } else {
+      hipLaunchKernelGGL(k_lsq_prev<true>, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a, j);
+    }
+    IF_HIP(hipGetLastError());
+  }
+  // packed slab in LDS when it fits the workgroup's LDS
   const size_t P = (size_t)a.m0 * a.m0 + (size_t)a.m0 * (a.m0 + 1) / 2;
   const size_t lds = (P + 2 * (size_t)a.m0) * sizeof(c2);
   if ((int64_t)lds + 1024 <= (int64_t)max_lds && getenv("IFEAST_LSQ_GLOBAL") == nullptr) {
@@ -1180,11 +1214,21 @@ void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
   IF_HIP(hipGetLastError());
 }
 void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
   const size_t lds = (size_t)4 * a.ldh * sizeof(c2);
-  if (lds > 64 * 1024)
-    IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_finish), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-  hipLaunchKernelGGL(k_lsq_finish, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a);
+  if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
+    if (lds > 64 * 1024)
+      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_finish<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_lsq_finish<false>, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a);
+  } else {
+    hipLaunchKernelGGL(k_lsq_finish<true>, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a);
+  }
   IF_HIP(hipGetLastError());
 }
 

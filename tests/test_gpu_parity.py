@@ -166,15 +166,17 @@ def _first_iterate(prob):
     return lam, X, R, r
 
 
-def _oracle_filter(prob, lam, X, R, k, cycles):
+def _oracle_filter(prob, lam, X, R, k, cycles, restarted=True):
+    """restarted=False: one block GMRES cycle of k * cycles iterations per shift (what the shared
+    basis computes; in exact arithmetic the shifted block Krylov spaces coincide)."""
     A = prob.A.to_scipy()
     B = None if prob.B is None else prob.B.to_scipy()
     z, w, half = contour_nodes(prob.contour)
     D = []
     for zk in z:
         rhs = R / (zk - lam)[None, :]
-        if cycles == 1:
-            Dk, _ = O.block_gmres(O.shifted_operator(A, B, zk), rhs, k, 0.0)
+        if cycles == 1 or not restarted:
+            Dk, _ = O.block_gmres(O.shifted_operator(A, B, zk), rhs, k * cycles, 0.0)
         else:
             from oracle.krylov import block_gmres_restarted
 
@@ -183,13 +185,14 @@ def _oracle_filter(prob, lam, X, R, k, cycles):
     return O.quad_accumulate(X, lam, D, z, w, half)
 
 
-def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles, reorth_eta=0.0):
+def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles, reorth_eta=0.0, basis=None):
     import paper_1706_00692_amd as pk
 
     Am = ctx.matrix(prob.A)
     Bm = None if prob.B is None else ctx.matrix(prob.B)
     p = pk.params_struct(prob.m0, max_outer=1, max_inner=k, max_cycles=cycles, alpha=0.0, tol=1e-9,
-                         precision=prec, reorth_eta=reorth_eta)
+                         precision=prec, reorth_eta=reorth_eta,
+                         basis=pk.BASIS_AUTO if basis is None else basis)
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     ld = torch.from_numpy(np.ascontiguousarray(lam)).cuda()
     Rd = torch.from_numpy(np.ascontiguousarray(R)).cuda()
@@ -199,15 +202,20 @@ def _gpu_filter(ctx, torch, prob, lam, X, R, prec, k, cycles, reorth_eta=0.0):
     return Qd.cpu().numpy(), iters
 
 
+@pytest.mark.parametrize("basis", ["per_shift", "shared"])
 @pytest.mark.parametrize("cycles,reorth", [(1, 0.0), (3, 0.0), (1, 2.0), (3, 2.0)])
-def test_filter_parity_fp64(ctx, torch_cuda, cycles, reorth):
-    """reorth 0: the default selective second Gram-Schmidt pass; 2.0: always two passes."""
+def test_filter_parity_fp64(ctx, torch_cuda, cycles, reorth, basis):
+    """reorth 0: the default selective second Gram-Schmidt pass; 2.0: always two passes.
+    per_shift: restarted complex block GMRES(k) per shift; shared: one real Arnoldi of A for all
+    shifts, k * cycles steps without restarts (the oracle runs that many steps per shift)."""
     import paper_1706_00692_amd as pk
 
     prob = W.config1()
     lam, X, R, r = _first_iterate(prob)
-    want = _oracle_filter(prob, lam, X, R, prob.max_inner, cycles)
-    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, prob.max_inner, cycles, reorth)
+    shared = basis == "shared"
+    want = _oracle_filter(prob, lam, X, R, prob.max_inner, cycles, restarted=not shared)
+    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, prob.max_inner, cycles, reorth,
+                             pk.BASIS_SHARED if shared else pk.BASIS_PER_SHIFT)
     assert list(iters) == [prob.max_inner * cycles] * 8
     err = np.abs(got - want).max() / np.abs(want).max()
     assert err <= 1e-9, err

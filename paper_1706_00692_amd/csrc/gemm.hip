@@ -183,6 +183,93 @@ __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, con
   G[idx] = sum;
 }
 
+// Gram of several blocks of a shift against the same right operand:
+//   G[s, i] = A_{s,i}^T B_s,  i = 4 y .. 4 y + 3,  each (16 TB) x (16 TB).
+// Wave w owns block i = 4 y + w and all TB x TB of its MFMA tiles; the B tile is staged once
+// for the four waves, so B is read once per four blocks instead of once per block.
+// grid: x = row split, y = group of four blocks, z = shift.
+template <class T, int TB>
+__global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_t rows_per_split, T* __restrict__ partial) {
+  using V = typename V16T<T>::t;
+  constexpr int VN = V16T<T>::N;
+  constexpr int KC = 16;  // a short chunk keeps the five staged tiles' prefetch registers few
+  constexpr int TP = TB * 16;
+  constexpr int LD = lds_ld<T>(TP);
+  constexpr int NV = KC * TP / VN;             // 16-byte vectors per operand tile
+  constexpr int PER = (NV + 255) / 256;
+  __shared__ T sA[4][KC * LD];
+  __shared__ T sB[KC * LD];
+  const int s = blockIdx.z;
+  if (g.active != nullptr && g.active[s] == 0) return;
+  const int i0 = blockIdx.y * 4;
+  const int nil = min(4, g.ni - i0);  // blocks in this group
+  const int split = blockIdx.x;
+  const int64_t r0 = (int64_t)split * rows_per_split;
+  const int64_t r1 = min(g.n, r0 + rows_per_split);
+  const T* __restrict__ A0 = static_cast<const T*>(g.A) + s * g.a_s + i0 * g.a_i;
+  const T* __restrict__ B = static_cast<const T*>(g.B) + s * g.b_s;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  typename Mfma<T>::acc acc[TB][TB];
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[a][b] = Mfma<T>::zero();
+  V ra[4][PER], rb[PER];
+  auto fetch = [&](int64_t rc) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int v = tid + 256 * t;
+      const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
+      const int64_t row = rc + r;
+      const bool ok = v < NV && row < r1;
+      rb[t] = ok ? *reinterpret_cast<const V*>(B + row * g.ldb + c) : zero16<T>();
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        ra[q][t] = (ok && q < nil) ? *reinterpret_cast<const V*>(A0 + q * g.a_i + row * g.lda + c) : zero16<T>();
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t rc = r0; rc < r1; rc += KC) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int v = tid + 256 * t;
+      if (v < NV) {
+        const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
+        put16<T>(sB + r * LD + c, rb[t]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) put16<T>(sA[q] + r * LD + c, ra[q][t]);
+      }
+    }
+    __syncthreads();
+    if (rc + KC < r1) fetch(rc + KC);
+    if (wave < nil) {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        T af[TB], bf[TB];
+#pragma unroll
+        for (int a = 0; a < TB; ++a) af[a] = sA[wave][(kk + lk) * LD + a * 16 + li];
+#pragma unroll
+        for (int b = 0; b < TB; ++b) bf[b] = sB[(kk + lk) * LD + b * 16 + li];
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+          for (int b = 0; b < TB; ++b) acc[a][b] = Mfma<T>::mma(af[a], bf[b], acc[a][b]);
+      }
+    }
+    __syncthreads();
+  }
+  if (wave >= nil) return;
+  const int item = s * g.ni + i0 + wave;
+  T* out = partial + ((int64_t)item * nsplit + split) * TP * TP;
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(int64_t)(a * 16 + Mfma<T>::row(lk, v)) * TP + b * 16 + li] = acc[a][b][v];
+}
+
 inline int gram_tb(int W) {
   // tile blocks per dimension: at most 10 (160 reals), as few tiles as possible
   const int nb = W / 16;
@@ -392,6 +479,42 @@ int gram_capacity_of() {
   return cap;
 }
 
+template <class T, int TB>
+int gram4_capacity_of() {
+  static int cap = -1;
+  if (cap < 0) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_gram4<T, TB>), 256, 0) !=
+            hipSuccess ||
+        occ < 1 || cus < 1)
+      return 2048;
+    cap = occ * cus;
+  }
+  return cap;
+}
+
+template <class T>
+int gram4_capacity(int tb) {
+  switch (tb) {
+    case 1: return gram4_capacity_of<T, 1>();
+    case 2: return gram4_capacity_of<T, 2>();
+    case 3: return gram4_capacity_of<T, 3>();
+    case 4: return gram4_capacity_of<T, 4>();
+    default: return gram4_capacity_of<T, 5>();
+  }
+}
+
+// k_gram4 applies to square products of at most 80 columns whose right operand is shared by
+// the blocks of a shift
+// (FP64 at 80 columns would spill at two waves per SIMD: it keeps the one-block kernel)
+template <class T>
+bool gram4_fits(const GramArgs& g) {
+  const int maxw = sizeof(T) == 4 ? 80 : 64;
+  return g.PW == g.QW && g.PW % 16 == 0 && g.PW <= maxw && g.ni >= 2 && g.b_i == 0;
+}
+
 template <class T>
 int gram_capacity(int tb) {
   switch (tb) {
@@ -414,8 +537,14 @@ int g_gram_variant = 0;
 
 template <class T>
 size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
-  // the largest over the tilings launch_gram may choose
+  // the largest over the tilings launch_gram may choose (the four-block kernel when one shift
+  // has all the items: the fewest groups, the most row splits)
   size_t best = 0;
+  if (PW == QW && PW % 16 == 0 && PW <= (sizeof(T) == 4 ? 80 : 64) && items >= 2) {
+    const int groups = (items + 3) / 4;
+    const int ns = gram_nsplit(n, groups, 1, gram4_capacity<T>(PW / 16));
+    best = (size_t)items * ns * PW * QW * sizeof(T);
+  }
   const int tb0 = std::max(gram_tb(PW), gram_tb(QW));
   for (int tb = 1; tb <= tb0; ++tb) {
     const int tiles = ((PW / 16 + tb - 1) / tb) * ((QW / 16 + tb - 1) / tb);
@@ -428,6 +557,39 @@ size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes) {
   IF_REQUIRE(g.PW % 16 == 0 && g.QW % 16 == 0, "gram: widths must be multiples of 16");
+  if (gram4_fits<T>(g) && g_gram_variant >= 0) {
+    const int tb = g.PW / 16;
+    const int groups = (g.ni + 3) / 4;
+    const int items = g.ns * g.ni;
+    const int nsplit = gram_nsplit(g.n, g.ns * groups, 1, gram4_capacity<T>(tb));
+    IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
+    constexpr int KC = 16;
+    int64_t rps = (g.n + nsplit - 1) / nsplit;
+    rps = (rps + KC - 1) / KC * KC;
+    const dim3 grid(nsplit, groups, g.ns), block(256);
+    T* part = static_cast<T*>(partial);
+    KernelTimer* kt = current_timer();
+    const int tok = kt ? kt->begin(st) : -1;
+    switch (tb) {
+      case 1: hipLaunchKernelGGL((k_gram4<T, 1>), grid, block, 0, st, g, nsplit, rps, part); break;
+      case 2: hipLaunchKernelGGL((k_gram4<T, 2>), grid, block, 0, st, g, nsplit, rps, part); break;
+      case 3: hipLaunchKernelGGL((k_gram4<T, 3>), grid, block, 0, st, g, nsplit, rps, part); break;
+      case 4: hipLaunchKernelGGL((k_gram4<T, 4>), grid, block, 0, st, g, nsplit, rps, part); break;
+      default: hipLaunchKernelGGL((k_gram4<T, 5>), grid, block, 0, st, g, nsplit, rps, part); break;
+    }
+    IF_HIP(hipGetLastError());
+    if (kt) {
+      const int nact = kt->count(g.active, g.ns);
+      const double eff = (double)nact * g.ni;
+      kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff,
+              (double)g.n * g.PW * sizeof(T) * eff + (double)g.n * g.QW * sizeof(T) * nact);
+    }
+    const int64_t total = (int64_t)items * g.PW * g.QW;
+    hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
+                       g.PW, g.QW, g.ni, g.active, part, g.G);
+    IF_HIP(hipGetLastError());
+    return;
+  }
   // one square tile size for both dimensions
   int tb = std::max(gram_tb(g.PW), gram_tb(g.QW));
   if (g_gram_variant > 0 && tb > g_gram_variant) tb = g_gram_variant;
@@ -471,8 +633,9 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   IF_HIP(hipGetLastError());
 }
 
-// Row blocks per wave and K chunk of the update kernel for 160-wide complex-FP32 blocks;
-// other shapes use 2 x (32 or 16).  -1 selects the built-in choice.
+// Row blocks per wave and K chunk of the FP32 update kernel (FP64 uses 2 x 16); -1 selects the
+// built-in choice measured fastest: one row block per wave for 160-column outputs (the most
+// resident waves), two with a 16-row K chunk for 80-column outputs.
 int g_apply_variant = -1;
 
 template <class T, class TO, int RB, int KC>
@@ -506,12 +669,17 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   KernelTimer* kt = current_timer();
   int tok = -1;
   constexpr int KC0 = ApplyCfg<T>::KC;
-  if (sizeof(T) == 4 && sizeof(TO) == 4 && tbq == 10) {
-    switch (g_apply_variant) {
+  if (sizeof(T) == 4) {
+    int var = g_apply_variant;
+    if (var < 0) var = tbq >= 8 ? 3 : 6;
+    switch (var) {
       case 0: launch_apply_rt<T, TO, 2, 32>(st, a, tbq, ntq, kt, tok); break;
       case 1: launch_apply_rt<T, TO, 1, 64>(st, a, tbq, ntq, kt, tok); break;
       case 2: launch_apply_rt<T, TO, 1, 16>(st, a, tbq, ntq, kt, tok); break;
-      default: launch_apply_rt<T, TO, 1, 32>(st, a, tbq, ntq, kt, tok); break;
+      case 3: launch_apply_rt<T, TO, 1, 32>(st, a, tbq, ntq, kt, tok); break;
+      case 4: launch_apply_rt<T, TO, 4, 32>(st, a, tbq, ntq, kt, tok); break;
+      case 5: launch_apply_rt<T, TO, 4, 16>(st, a, tbq, ntq, kt, tok); break;
+      default: launch_apply_rt<T, TO, 2, 16>(st, a, tbq, ntq, kt, tok); break;
     }
   } else {
     launch_apply_rt<T, TO, 2, KC0>(st, a, tbq, ntq, kt, tok);

@@ -213,6 +213,67 @@ __global__ __launch_bounds__(256) void k_spmm_slab(int n, int rows_xcd, int rbx,
     nt_store(zs_minus(zs[2 * s], zs[2 * s + 1], self, acc), reinterpret_cast<V16*>(W) + (int64_t)row * nvec + vc);
 }
 
+// Whole rows for narrow blocks: a row of nvec <= 64 vectors is one group of nvec lanes and
+// a wavefront takes floor(64 / nvec) consecutive rows (3 rows of 20 vectors for a real
+// 80-column FP32 block), so every row is one contiguous run and few lanes idle.  Rows are
+// placed per XCD as in k_spmm_slab; CSR entries are fetched by the group's first KC lanes
+// and broadcast with lane shuffles.
+template <class T, bool HAS_B, int KC>
+__device__ inline void group_gather(int e0, int e1, int g0, int li, const int* __restrict__ ci,
+                                    const T* __restrict__ va, const typename Vec16<T>::type* __restrict__ Vv,
+                                    int nvec, int vc, typename Vec16<T>::type& acc) {
+  for (int e = e0; e < e1; e += KC) {
+    const int my = e + li;
+    const bool have = li < KC && my < e1;
+    const int cl = have ? ci[my] : 0;
+    const T al = have ? va[my] : T(0);
+    int c[KC];
+    T a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      c[k] = __shfl(cl, g0 + k);
+      a[k] = __shfl(al, g0 + k);
+    }
+    typename Vec16<T>::type x[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) x[k] = Vv[(int64_t)c[k] * nvec + vc];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) axpy(a[k], x[k], acc);
+  }
+}
+
+template <class T, bool HAS_B, int KC>
+__global__ __launch_bounds__(256) void k_spmm_rows(int n, int rows_xcd, int rbx, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const T* __restrict__ va,
+                                                   const int* __restrict__ brp, const int* __restrict__ bci,
+                                                   const T* __restrict__ bva, int ns, int m0,
+                                                   const T* __restrict__ zs, const int* __restrict__ active,
+                                                   const T* __restrict__ V, T* __restrict__ W) {
+  using V16 = typename Vec16<T>::type;
+  constexpr int C = Vec16<T>::C;
+  const int nvec = ns * m0 / C;
+  const int gpw = 64 / nvec;  // row groups per wavefront
+  const int xcd = blockIdx.x % kXcds, rb = blockIdx.x / kXcds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane / nvec, li = lane % nvec, g0 = grp * nvec;
+  const int rlo = xcd * rows_xcd;
+  const int rhi = min(n, rlo + rows_xcd);
+  const int row = rlo + (rb * 4 + wave) * gpw + grp;
+  // lanes past the last group, or groups past the XCD's rows, have nothing to do (each group
+  // shuffles only within itself)
+  if (grp >= gpw || row >= rhi) return;
+  const int s = (li * C) / m0;
+  const V16* __restrict__ Vv = reinterpret_cast<const V16*>(V);
+  V16 acc = vzero<V16>(), self = vzero<V16>();
+  group_gather<T, HAS_B, KC>(rp[row], rp[row + 1], g0, li, ci, va, Vv, nvec, li, acc);
+  if (HAS_B)
+    group_gather<T, HAS_B, KC>(brp[row], brp[row + 1], g0, li, bci, bva, Vv, nvec, li, self);
+  else
+    self = Vv[(int64_t)row * nvec + li];
+  if (active == nullptr || active[s] != 0)
+    nt_store(zs_minus(zs[2 * s], zs[2 * s + 1], self, acc), reinterpret_cast<V16*>(W) + (int64_t)row * nvec + li);
+}
+
 __global__ __launch_bounds__(256) void k_spmm_real(int n, int per, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const double* __restrict__ va, int m,
                                                    const double* __restrict__ X, double* __restrict__ Y) {
@@ -241,7 +302,7 @@ struct Sched {
 };
 constexpr Sched kSched[] = {{false, 1, 8, "row-U1-K8"}, {false, 2, 4, "row-U2-K4"}, {false, 3, 4, "row-U3-K4"},
                             {true, 8, 8, "slab8-K8"},   {true, 16, 8, "slab16-K8"}, {true, 32, 8, "slab32-K8"},
-                            {true, 16, 16, "slab16-K16"}, {true, 8, 4, "slab8-K4"}};
+                            {true, 16, 16, "slab16-K16"}, {true, 8, 4, "slab8-K4"},  {true, 0, 8, "rows-K8"}};
 constexpr int kNSched = sizeof(kSched) / sizeof(kSched[0]);
 
 struct SpmmOperands {
@@ -280,6 +341,22 @@ void launch_slab(hipStream_t st, const SpmmOperands& o) {
                      (const T*)o.zs, o.active, (const T*)o.V, (T*)o.W);
 }
 
+template <class T, bool HAS_B, int KC>
+void launch_rows(hipStream_t st, const SpmmOperands& o) {
+  constexpr int C = Vec16<T>::C;
+  const int nvec = o.ns * o.m0 / C;
+  IF_REQUIRE(nvec >= KC && nvec <= 64, "SpMM rows schedule needs a block of 8..64 vectors per row");
+  const int rpb = 4 * (64 / nvec);  // rows per workgroup
+  const int rows_xcd = (o.n + kXcds - 1) / kXcds;
+  const int rbx = (rows_xcd + rpb - 1) / rpb;
+  hipLaunchKernelGGL((k_spmm_rows<T, HAS_B, KC>), dim3((unsigned)((int64_t)kXcds * rbx)), dim3(256), 0, st, o.n,
+                     rows_xcd, rbx, o.rp, o.ci, (const T*)o.va, o.brp, o.bci, (const T*)o.bva, o.ns, o.m0,
+                     (const T*)o.zs, o.active, (const T*)o.V, (T*)o.W);
+}
+
+// whether schedule idx can run a block of nvec 16-byte vectors per row
+bool sched_fits(int idx, int nvec) { return idx != 8 || (nvec >= 8 && nvec <= 64); }
+
 template <class T, bool HAS_B>
 void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
   switch (idx) {
@@ -291,6 +368,7 @@ void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
     case 5: launch_slab<T, HAS_B, 32, 8>(st, o); break;
     case 6: launch_slab<T, HAS_B, 16, 16>(st, o); break;
     case 7: launch_slab<T, HAS_B, 8, 4>(st, o); break;
+    case 8: launch_rows<T, HAS_B, 8>(st, o); break;
     default: throw Error{IFEAST_ERR_INVALID_ARG, "unknown SpMM schedule"};
   }
 }
@@ -344,7 +422,12 @@ void launch_spmm_shifted(hipStream_t st, const ifeast_matrix* A, const ifeast_ma
       IF_HIP(hipEventCreate(&e1));
       float best = 1e30f;
       std::vector<float> times(kNSched, 0.f);
+      const int nvec = ns * m0 / (sizeof(T) == 4 ? 2 : 1);
       for (int c = 0; c < kNSched; ++c) {
+        if (!sched_fits(c, nvec)) {
+          times[c] = 0.f;
+          continue;
+        }
         run(c);  // warm
         IF_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < 3; ++r) run(c);

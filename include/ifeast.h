@@ -218,7 +218,10 @@ int ifeast_kernel_stats(ifeast_ctx *ctx, int kind, ifeast_kernel_stat *out);
  * s = 0..ns-1.  V and W are device n x (ns*m0) complex blocks, row-major;
  * precision MIXED means complex FP32 elements with the FP32 matrix copy,
  * FP64 means complex FP64.  z: host array of ns complex shifts.  B NULL =
- * identity. */
+ * identity.  Asynchronous: the product is queued on the context's stream
+ * (ifeast_set_stream) and W is complete when that stream reaches it; the
+ * first product of a new (matrix, width, precision) also times the SpMM
+ * schedules and keeps the fastest for that matrix. */
 int ifeast_spmm_shifted_dev(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matrix *B, int precision,
                             int ns, const double *z, int m0, const void *V, void *W);
 

@@ -322,21 +322,20 @@ int ifeast_spmm_shifted_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeas
     DeviceGuard g(ctx->device);
     TimingScope ts(ctx);
     hipStream_t st = ctx->stream;
+    // the shifts go to a buffer the context keeps, in stream order: consecutive calls queue
+    // without host synchronisation or allocation
+    if (ctx->zbuf.p == nullptr) ctx->zbuf = DevBuf(64 * 2 * sizeof(double));
     if (precision == IFEAST_PREC_MIXED) {
       std::vector<float> zf(2 * ns);
       for (int i = 0; i < 2 * ns; ++i) zf[i] = (float)z[i];
-      DevBuf zd(zf.size() * 4);
-      IF_HIP(hipMemcpyAsync(zd.p, zf.data(), zf.size() * 4, hipMemcpyHostToDevice, st));
-      launch_spmm_shifted<float>(st, A, B, ns, m0, zd.as<float>(), nullptr, static_cast<const float*>(V),
+      IF_HIP(hipMemcpyAsync(ctx->zbuf.p, zf.data(), zf.size() * 4, hipMemcpyHostToDevice, st));
+      launch_spmm_shifted<float>(st, A, B, ns, m0, ctx->zbuf.as<float>(), nullptr, static_cast<const float*>(V),
                                  static_cast<float*>(W));
-      IF_HIP(hipStreamSynchronize(st));
     } else {
       IF_REQUIRE(precision == IFEAST_PREC_FP64, "unknown precision");
-      DevBuf zd(2 * ns * 8);
-      IF_HIP(hipMemcpyAsync(zd.p, z, 2 * ns * 8, hipMemcpyHostToDevice, st));
-      launch_spmm_shifted<double>(st, A, B, ns, m0, zd.as<double>(), nullptr, static_cast<const double*>(V),
+      IF_HIP(hipMemcpyAsync(ctx->zbuf.p, z, 2 * ns * 8, hipMemcpyHostToDevice, st));
+      launch_spmm_shifted<double>(st, A, B, ns, m0, ctx->zbuf.as<double>(), nullptr, static_cast<const double*>(V),
                                   static_cast<double*>(W));
-      IF_HIP(hipStreamSynchronize(st));
     }
     return IFEAST_OK;
   });

@@ -171,16 +171,24 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
 template <class T>
 __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, const int* __restrict__ active,
                               const T* __restrict__ partial, double* __restrict__ G) {
+  // 8 consecutive lanes share one output element: each sums every 8th split, then the
+  // lanes' sums are added with shuffles (the order is fixed, so results are reproducible)
   const int64_t per_item = (int64_t)PW * QW;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= per_item * items) return;
-  const int item = (int)(idx / per_item);
-  const int64_t e = idx % per_item;
-  if (active != nullptr && active[item / ni] == 0) return;
-  const T* p = partial + (int64_t)item * nsplit * per_item + e;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = gid >> 3;
+  const int part = (int)(gid & 7);
+  const bool live = idx < per_item * items;
+  const int item = live ? (int)(idx / per_item) : 0;
+  const bool on = live && !(active != nullptr && active[item / ni] == 0);
   double sum = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) sum += (double)p[(int64_t)sp * per_item];
-  G[idx] = sum;
+  if (on) {
+    const T* p = partial + (int64_t)item * nsplit * per_item + idx % per_item;
+    for (int sp = part; sp < nsplit; sp += 8) sum += (double)p[(int64_t)sp * per_item];
+  }
+  sum += __shfl_xor(sum, 1);
+  sum += __shfl_xor(sum, 2);
+  sum += __shfl_xor(sum, 4);
+  if (on && part == 0) G[idx] = sum;
 }
 
 // Gram of several blocks of a shift against the same right operand:
@@ -584,7 +592,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
       kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff,
               (double)g.n * g.PW * sizeof(T) * eff + (double)g.n * g.QW * sizeof(T) * nact);
     }
-    const int64_t total = (int64_t)items * g.PW * g.QW;
+    const int64_t total = (int64_t)items * g.PW * g.QW * 8;
     hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
                        g.PW, g.QW, g.ni, g.active, part, g.G);
     IF_HIP(hipGetLastError());
@@ -627,7 +635,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     const double rb = (g.A == g.B && g.ni == 1) ? 0.0 : (double)g.n * g.QW * sizeof(T) * (g.b_i == 0 ? nact : eff);
     kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, ra + rb);
   }
-  const int64_t total = (int64_t)items * g.PW * g.QW;
+  const int64_t total = (int64_t)items * g.PW * g.QW * 8;
   hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
                      g.PW, g.QW, g.ni, g.active, part, g.G);
   IF_HIP(hipGetLastError());

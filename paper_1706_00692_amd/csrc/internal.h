@@ -130,6 +130,7 @@ struct ifeast_ctx {
   std::string last_error;
   std::mutex mu;  // serialises solves on this context
   std::unique_ptr<ifeast::Server> server;
+  ifeast::DevBuf zbuf;  // shifts of the step-level SpMM (64 complex FP64)
 };
 
 namespace ifeast {

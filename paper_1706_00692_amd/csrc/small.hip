@@ -318,6 +318,156 @@ __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __rest
   }
 }
 
+// Real-block factor (the shared basis), blocked by 16-column panels so that it needs a few
+// dozen block barriers instead of several per column.  L (m0 x m0, row-major) in LDS:
+//  1. unit-diagonal scaled Gram (+ shift), dead columns as identity;
+//  2. Cholesky: per panel, wave 0 factors the 16 x 16 diagonal block (with the deflation
+//     test), then the rows below solve against it, then the trailing matrix is updated;
+//  3. Racc <- R Racc (or R), R = L^T D with zero rows for dead columns;
+//  4. L^{-1}: one wave inverts each diagonal block, then block row i of the inverse is
+//     -L_ii^{-1} sum_{k=j..i-1} L_ik X_kj, for all j < i at once;
+//  5. Tinv = D^{-1} (L^{-1})^T with dead rows and columns zero.
+// LDS: L, a 16 x m0 block row, and the previous R (m0 <= 80).
+template <class T>
+__global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __restrict__ G, double shift_rel,
+                                                     double dead_thr, double tau_dep, T* __restrict__ Tinv,
+                                                     c2* __restrict__ Racc, int accumulate) {
+  constexpr int NB = 16;
+  extern __shared__ double lds_d[];
+  double* L = lds_d;           // m0 x m0
+  double* tmp = L + m0 * m0;   // 16 x m0
+  double* Rs = tmp + NB * m0;  // m0 x m0
+  __shared__ double dsc[128];
+  __shared__ int dead[128];
+  const int tid = threadIdx.x, nth = blockDim.x, wave = tid >> 6, lane = tid & 63;
+  const int P = m0 / NB;
+  // ---- 1.
+  for (int a = tid; a < m0; a += nth) {
+    const double g = G[a * m0 + a];
+    const bool dd = !(g > dead_thr);
+    dead[a] = dd ? 1 : 0;
+    dsc[a] = dd ? 1.0 : sqrt(g);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < m0 * m0; idx += nth) {
+    const int a = idx / m0, b = idx % m0;
+    double g;
+    if (dead[a] || dead[b]) g = a == b ? 1.0 : 0.0;
+    else g = G[idx] / (dsc[a] * dsc[b]) + (a == b ? shift_rel : 0.0);
+    L[idx] = g;
+    if (accumulate) Rs[idx] = Racc[idx].x;
+  }
+  __syncthreads();
+  // ---- 2. blocked Cholesky (lower triangle of L)
+  for (int p = 0; p < P; ++p) {
+    const int c0 = p * NB;
+    if (wave == 0) {
+      for (int c = c0; c < c0 + NB; ++c) {
+        const double pv0 = L[c * m0 + c];
+        const bool dc = dead[c] != 0 || !(pv0 > tau_dep);
+        const double pv = dc ? 1.0 : sqrt(pv0);
+        if (lane < c0 + NB - c - 1) {
+          const int r = c + 1 + lane;
+          L[r * m0 + c] = dc ? 0.0 : L[r * m0 + c] / pv;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane == 0) {
+          dead[c] = dc ? 1 : 0;
+          L[c * m0 + c] = pv;
+        }
+        if (!dc) {
+          const int nt = c0 + NB - c - 1;
+          for (int t = lane; t < nt * nt; t += 64) {
+            const int rr = c + 1 + t / nt, q = c + 1 + t % nt;
+            if (q <= rr) L[rr * m0 + q] -= L[rr * m0 + c] * L[q * m0 + c];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+    }
+    __syncthreads();
+    // rows below the diagonal block: x L11^T = a, forward along the panel's columns
+    for (int r = c0 + NB + tid; r < m0; r += nth) {
+      for (int c = c0; c < c0 + NB; ++c) {
+        double v = L[r * m0 + c];
+        for (int k = c0; k < c; ++k) v -= L[r * m0 + k] * L[c * m0 + k];
+        L[r * m0 + c] = dead[c] ? 0.0 : v / L[c * m0 + c];
+      }
+    }
+    __syncthreads();
+    // trailing matrix, lower triangle
+    const int t0 = c0 + NB, nt = m0 - t0;
+    for (int idx = tid; idx < nt * nt; idx += nth) {
+      const int r = t0 + idx / nt, q = t0 + idx % nt;
+      if (q > r) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) v += L[r * m0 + c0 + k] * L[q * m0 + c0 + k];
+      L[r * m0 + q] -= v;
+    }
+    __syncthreads();
+  }
+  // ---- 3. R factor (global writes; the previous R was staged in LDS)
+  for (int idx = tid; idx < m0 * m0; idx += nth) {
+    const int a = idx / m0, b = idx % m0;
+    double v = 0.0;
+    if (b >= a && !dead[a]) {
+      if (accumulate)
+        for (int e = a; e <= b; ++e) v += dsc[e] * L[e * m0 + a] * Rs[e * m0 + b];
+      else
+        v = dsc[b] * L[b * m0 + a];
+    }
+    Racc[idx] = make_double2(v, 0.0);
+  }
+  __syncthreads();
+  // ---- 4a. invert the diagonal blocks, one wave each (in place)
+  for (int p = wave; p < P; p += nth / 64) {
+    const int c0 = p * NB;
+    const int i = lane;  // row of the block (lanes 16..63 idle)
+    for (int j = NB - 1; j >= 0; --j) {
+      const double ljj = L[(c0 + j) * m0 + c0 + j];
+      const double xi = (i > j && i < NB) ? L[(c0 + i) * m0 + c0 + j] : 0.0;
+      double v = 0.0;
+      for (int k = j + 1; k < NB; ++k) {
+        const double xk = __shfl(xi, k);
+        if (i < NB && k <= i) v += L[(c0 + i) * m0 + c0 + k] * xk;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (i > j && i < NB) L[(c0 + i) * m0 + c0 + j] = -v / ljj;
+      if (i == j) L[(c0 + j) * m0 + c0 + j] = 1.0 / ljj;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  }
+  __syncthreads();
+  // ---- 4b. block rows of the inverse below the diagonal
+  for (int bi = 1; bi < P; ++bi) {
+    const int r0 = bi * NB, w = bi * NB;  // block row start; the blocks j < bi span columns [0, w)
+    // S_j = sum_{k=j..bi-1} L_{bi,k} X_{k,j}  (X: the inverse so far), into tmp[16][w]
+    for (int idx = tid; idx < NB * w; idx += nth) {
+      const int r = idx / w, c = idx % w;
+      // X is lower triangular (rows k >= c); L's storage above the diagonal is not part of it
+      double v = 0.0;
+      for (int k = c; k < r0; ++k) v += L[(r0 + r) * m0 + k] * L[k * m0 + c];
+      tmp[r * m0 + c] = v;
+    }
+    __syncthreads();
+    // X_{bi,j} = -L_{bi,bi}^{-1} S_j (the diagonal block is already inverted)
+    for (int idx = tid; idx < NB * w; idx += nth) {
+      const int r = idx / w, c = idx % w;
+      double v = 0.0;
+      for (int m = 0; m <= r; ++m) v += L[(r0 + r) * m0 + r0 + m] * tmp[m * m0 + c];
+      L[(r0 + r) * m0 + c] = -v;
+    }
+    __syncthreads();
+  }
+  // ---- 5.
+  for (int idx = tid; idx < m0 * m0; idx += nth) {
+    const int a = idx / m0, b = idx % m0;
+    const double v = (b < a || dead[a] || dead[b]) ? 0.0 : L[b * m0 + a] / dsc[a];
+    Tinv[idx] = (T)v;
+  }
+}
+
 template <class T>
 __global__ void k_cgs_combine(int ns, int ni, int m0, int j, int ldh, const double* __restrict__ G,
                               const int* __restrict__ active, c2* __restrict__ H, T* __restrict__ Hr, int accumulate) {
@@ -1118,7 +1268,15 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
     const size_t with_ra = lds + (size_t)m0 * m0 * sizeof(c2);
     const int ra_in_lds = (accumulate && (int64_t)with_ra + 2048 <= (int64_t)max_lds) ? 1 : 0;
     if (ra_in_lds) lds = with_ra;
-    if (real) {
+    const size_t lds_real = ((size_t)2 * m0 * m0 + 16 * (size_t)m0) * sizeof(double);
+    if (real && m0 <= 80 && ns == 1 && active == nullptr && (int64_t)lds_real + 2048 <= (int64_t)max_lds &&
+        getenv("IFEAST_CHOLQR_UNBLOCKED") == nullptr) {
+      if (lds_real > 64 * 1024)
+        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
+      hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep,
+                         Tinv, reinterpret_cast<c2*>(Racc), accumulate);
+    } else if (real) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T, true>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

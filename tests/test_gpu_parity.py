@@ -226,6 +226,23 @@ def test_filter_parity_fp64(ctx, torch_cuda, cycles, reorth, basis):
     assert err <= 1e-9, err
 
 
+@pytest.mark.parametrize("m0", [48, 80])
+def test_filter_parity_shared_wide(ctx, torch_cuda, m0):
+    """Shared basis with several 16-column panels in the block Cholesky-QR factor (m0 = 48, 80):
+    4 Arnoldi steps on a 10^3 Laplacian + potential, FP64, against per-shift block GMRES."""
+    import paper_1706_00692_amd as pk
+
+    N = 10
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    prob = W.config2_small(N=N, m0=m0, emin=0.5 * (lam_all[5] + lam_all[6]), emax=0.5 * (lam_all[20] + lam_all[21]))
+    lam, X, R, r = _first_iterate(prob)
+    want = _oracle_filter(prob, lam, X, R, 2, 2, restarted=False)
+    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_FP64, 2, 2, 0.0, pk.BASIS_SHARED)
+    assert list(iters) == [4] * 8
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err <= 1e-9, err
+
+
 def test_filter_parity_mixed(ctx, torch_cuda):
     import paper_1706_00692_amd as pk
 

@@ -196,11 +196,10 @@ __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, con
 // Wave w owns block i = 4 y + w and all TB x TB of its MFMA tiles; the B tile is staged once
 // for the four waves, so B is read once per four blocks instead of once per block.
 // grid: x = row split, y = group of four blocks, z = shift.
-template <class T, int TB>
+template <class T, int TB, int KC>
 __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_t rows_per_split, T* __restrict__ partial) {
   using V = typename V16T<T>::t;
   constexpr int VN = V16T<T>::N;
-  constexpr int KC = 16;  // a short chunk keeps the five staged tiles' prefetch registers few
   constexpr int TP = TB * 16;
   constexpr int LD = lds_ld<T>(TP);
   constexpr int NV = KC * TP / VN;             // 16-byte vectors per operand tile
@@ -494,7 +493,7 @@ int gram4_capacity_of() {
     int dev = 0, cus = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_gram4<T, TB>), 256, 0) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_gram4<T, TB, 16>), 256, 0) !=
             hipSuccess ||
         occ < 1 || cus < 1)
       return 2048;
@@ -542,6 +541,8 @@ int gram_capacity(int tb) {
 
 // Largest tile (in 16-column blocks) of the Gram kernel; 0 = as wide as the operands allow.
 int g_gram_variant = 0;
+// K chunk of the four-block Gram kernel (32, or 16).
+int g_gram4_kc = 32;
 
 template <class T>
 size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
@@ -571,20 +572,33 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     const int items = g.ns * g.ni;
     const int nsplit = gram_nsplit(g.n, g.ns * groups, 1, gram4_capacity<T>(tb));
     IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
-    constexpr int KC = 16;
+    // K chunk (rows per staged tile): 32 (measured fastest, two waves per SIMD still fit) or 16
+    const int kc = g_gram4_kc == 16 ? 16 : 32;
     int64_t rps = (g.n + nsplit - 1) / nsplit;
-    rps = (rps + KC - 1) / KC * KC;
+    rps = (rps + 31) / 32 * 32;
     const dim3 grid(nsplit, groups, g.ns), block(256);
     T* part = static_cast<T*>(partial);
     KernelTimer* kt = current_timer();
     const int tok = kt ? kt->begin(st) : -1;
-    switch (tb) {
-      case 1: hipLaunchKernelGGL((k_gram4<T, 1>), grid, block, 0, st, g, nsplit, rps, part); break;
-      case 2: hipLaunchKernelGGL((k_gram4<T, 2>), grid, block, 0, st, g, nsplit, rps, part); break;
-      case 3: hipLaunchKernelGGL((k_gram4<T, 3>), grid, block, 0, st, g, nsplit, rps, part); break;
-      case 4: hipLaunchKernelGGL((k_gram4<T, 4>), grid, block, 0, st, g, nsplit, rps, part); break;
-      default: hipLaunchKernelGGL((k_gram4<T, 5>), grid, block, 0, st, g, nsplit, rps, part); break;
+#define IF_G4(TB_, KC_) hipLaunchKernelGGL((k_gram4<T, TB_, KC_>), grid, block, 0, st, g, nsplit, rps, part)
+    if (kc == 32) {
+      switch (tb) {
+        case 1: IF_G4(1, 32); break;
+        case 2: IF_G4(2, 32); break;
+        case 3: IF_G4(3, 32); break;
+        case 4: IF_G4(4, 32); break;
+        default: IF_G4(5, 32); break;
+      }
+    } else {
+      switch (tb) {
+        case 1: IF_G4(1, 16); break;
+        case 2: IF_G4(2, 16); break;
+        case 3: IF_G4(3, 16); break;
+        case 4: IF_G4(4, 16); break;
+        default: IF_G4(5, 16); break;
+      }
     }
+#undef IF_G4
     IF_HIP(hipGetLastError());
     if (kt) {
       const int nact = kt->count(g.active, g.ns);

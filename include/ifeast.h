@@ -8,7 +8,8 @@
  *   A, B real sparse (CSR), B symmetric positive definite or the identity.
  * Method (Algorithm 2): starting from an n x m0 block X, each outer
  * iteration solves the nc shifted systems (z_k B - A) Y_k = B X inexactly
- * with restarted block GMRES, forms Q = sum_k w_k Y_k (Eq. contour_int_quad),
+ * with block GMRES (one real Krylov basis shared by all shifts when B = I,
+ * restarted per-shift bases otherwise), forms Q = sum_k w_k Y_k (Eq. contour_int_quad),
  * and runs Rayleigh-Ritz on span(Q) (Algorithm 2, step 3) until the
  * eigenvector residual ||R_F|| = max ||A x_j - lambda_j B x_j|| over the pairs
  * inside C falls below tol (Algorithm 2, step 4).
@@ -127,8 +128,10 @@ typedef struct {
   int m;                   /* counted eigenpairs inside C (they come first, ascending) */
   int outer_iters;
   int converged;
-  int64_t total_matvec;    /* sum over shifts of block iterations times m0 */
-  int64_t seq_matvec;      /* sum over outer iterations of the largest per-shift block-iteration count */
+  int64_t total_matvec;    /* columns multiplied by A: per-shift bases, sum over shifts of block iterations
+                              times m0 (complex columns); shared basis, Arnoldi steps times m0 (real) */
+  int64_t seq_matvec;      /* sum over outer iterations of the sequential block products: the largest
+                              per-shift block-iteration count, or the shared basis's Arnoldi steps */
   double max_resid;        /* ||R_F|| of the final iterate */
   double solve_seconds;    /* device time of the solve, CSR upload excluded */
   /* caller-allocated arrays (may be NULL to skip) */
@@ -146,8 +149,9 @@ typedef struct {
  * device memory of resident requests in the serving loop (0 = 90% of free). */
 int ifeast_create(ifeast_ctx **ctx, int device, uint64_t hbm_budget_bytes);
 int ifeast_destroy(ifeast_ctx *ctx);
-/* Order the context's work on a caller stream (a hipStream_t passed as
- * void*, NULL = the context's own stream).  The stream must outlive its use. */
+/* Order the context's later work on a caller stream (a hipStream_t passed as
+ * void*; NULL is the default (null) stream).  Until this is called a context
+ * uses a stream of its own.  The stream must outlive its use. */
 int ifeast_set_stream(ifeast_ctx *ctx, void *stream);
 const char *ifeast_status_str(int status);
 const char *ifeast_last_error(ifeast_ctx *ctx);

@@ -194,7 +194,7 @@ int ifeast_set_stream(ifeast_ctx* ctx, void* stream) {
   return guarded(ctx, [&]() -> int {
     IF_REQUIRE(ctx != nullptr, "null context");
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->stream = stream ? static_cast<hipStream_t>(stream) : ctx->own_stream;
+    ctx->stream = static_cast<hipStream_t>(stream);
     return IFEAST_OK;
   });
 }

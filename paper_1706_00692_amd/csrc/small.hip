@@ -974,15 +974,17 @@ __global__ void k_make_coefs(LsqArgs a, const double* __restrict__ wfac, int jma
 // ------------------------------------------------------------ Rayleigh-Ritz
 // Cyclic Jacobi with the round-robin pair order on a symmetric m x m matrix
 // held in LDS (row-major, stride m); eigenvectors accumulate in global Vg.
-__device__ void jacobi_eig(double* a, int m, double* Vg, double* red) {
+// Vs: rotations accumulate in LDS (copied to Vg at the end) when given, else in Vg directly.
+__device__ void jacobi_eig(double* a, int m, double* Vg, double* red, double* Vs) {
   __shared__ double cs[64], sn[64];
   __shared__ int pp[64], qq[64];
-  const int tid = threadIdx.x, half = m / 2;
-  for (int idx = tid; idx < m * m; idx += 256) Vg[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
+  const int tid = threadIdx.x, half = m / 2, nth = blockDim.x;
+  double* V = Vs != nullptr ? Vs : Vg;
+  for (int idx = tid; idx < m * m; idx += nth) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int idx = tid; idx < m * m; idx += 256) {
+    for (int idx = tid; idx < m * m; idx += nth) {
       const int r = idx / m, c = idx % m;
       if (r != c) off += a[idx] * a[idx];
       else dia += a[idx] * a[idx];
@@ -1010,20 +1012,20 @@ __device__ void jacobi_eig(double* a, int m, double* Vg, double* red) {
       }
       __syncthreads();
       // A <- A J and V <- V J (columns p, q)
-      for (int idx = tid; idx < half * m; idx += 256) {
+      for (int idx = tid; idx < half * m; idx += nth) {
         const int i = idx / m, r = idx % m;
         const int p = pp[i], q = qq[i];
         const double c = cs[i], sv = sn[i];
         const double ap = a[r * m + p], aq = a[r * m + q];
         a[r * m + p] = c * ap - sv * aq;
         a[r * m + q] = sv * ap + c * aq;
-        const double vp = Vg[r * m + p], vq = Vg[r * m + q];
-        Vg[r * m + p] = c * vp - sv * vq;
-        Vg[r * m + q] = sv * vp + c * vq;
+        const double vp = V[r * m + p], vq = V[r * m + q];
+        V[r * m + p] = c * vp - sv * vq;
+        V[r * m + q] = sv * vp + c * vq;
       }
       __syncthreads();
       // A <- J^T A (rows p, q)
-      for (int idx = tid; idx < half * m; idx += 256) {
+      for (int idx = tid; idx < half * m; idx += nth) {
         const int i = idx / m, col = idx % m;
         const int p = pp[i], q = qq[i];
         const double c = cs[i], sv = sn[i];
@@ -1034,13 +1036,18 @@ __device__ void jacobi_eig(double* a, int m, double* Vg, double* red) {
       __syncthreads();
     }
   }
+  if (Vs != nullptr) {
+    for (int idx = tid; idx < m * m; idx += nth) Vg[idx] = Vs[idx];
+    __syncthreads();
+  }
 }
 
-__global__ __launch_bounds__(256) void k_rr_small(int m0, const double* __restrict__ GA, const double* __restrict__ GB,
+__global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restrict__ GA, const double* __restrict__ GB,
                                                   double* __restrict__ lam, double* __restrict__ C,
-                                                  double* __restrict__ eta, double* __restrict__ work) {
-  extern __shared__ double sm[];  // m0 * m0
-  __shared__ double red[8];
+                                                  double* __restrict__ eta, double* __restrict__ work,
+                                                  int v_in_lds) {
+  extern __shared__ double sm[];  // m0 * m0, then (v_in_lds) the m0 * m0 rotation accumulator
+  __shared__ double red[16];
   __shared__ double dsc[128], th[128];
   __shared__ int order[128];
   const int tid = threadIdx.x, mm = m0 * m0;
@@ -1049,49 +1056,49 @@ __global__ __launch_bounds__(256) void k_rr_small(int m0, const double* __restri
   double* W = work + 2 * mm;
   double* Ar = work + 3 * mm;
   // 1. scaled, symmetrised B-Gram
-  for (int a = tid; a < m0; a += 256) {
+  for (int a = tid; a < m0; a += blockDim.x) {
     const double d = GB[a * m0 + a];
     dsc[a] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
   }
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     sm[idx] = 0.5 * (GB[r * m0 + c] + GB[c * m0 + r]) * dsc[r] * dsc[c];
   }
   __syncthreads();
-  jacobi_eig(sm, m0, U, red);
+  jacobi_eig(sm, m0, U, red, v_in_lds ? sm + mm : nullptr);
   // 2. floor tiny eigenvalues (SVQB), T = D U Theta^{-1/2}
   double tmax = 0.0;
-  for (int a = tid; a < m0; a += 256) tmax = fmax(tmax, sm[a * m0 + a]);
+  for (int a = tid; a < m0; a += blockDim.x) tmax = fmax(tmax, sm[a * m0 + a]);
   tmax = block_max(tmax, red);
-  for (int a = tid; a < m0; a += 256) th[a] = 1.0 / sqrt(fmax(sm[a * m0 + a], 2.220446049250313e-16 * m0 * tmax));
+  for (int a = tid; a < m0; a += blockDim.x) th[a] = 1.0 / sqrt(fmax(sm[a * m0 + a], 2.220446049250313e-16 * m0 * tmax));
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     Tm[idx] = dsc[r] * U[idx] * th[c];
   }
   __syncthreads();
   // 3. Ar = T^T GA T (symmetrised), via W = GA T
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     double sum = 0.0;
     for (int e = 0; e < m0; ++e) sum += 0.5 * (GA[r * m0 + e] + GA[e * m0 + r]) * Tm[e * m0 + c];
     W[idx] = sum;
   }
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     double sum = 0.0;
     for (int e = 0; e < m0; ++e) sum += Tm[e * m0 + r] * W[e * m0 + c];
     Ar[idx] = sum;
   }
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     sm[idx] = 0.5 * (Ar[r * m0 + c] + Ar[c * m0 + r]);
   }
   __syncthreads();
-  jacobi_eig(sm, m0, W, red);
+  jacobi_eig(sm, m0, W, red, v_in_lds ? sm + mm : nullptr);
   // 4. ascending order, C = T W(:, order), eta = 1/||c_l||
   if (tid == 0) {
     for (int i = 0; i < m0; ++i) order[i] = i;
@@ -1107,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_rr_small(int m0, const double* __restri
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < mm; idx += 256) {
+  for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     const int oc = order[c];
     double sum = 0.0;
@@ -1115,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_rr_small(int m0, const double* __restri
     C[idx] = sum;
   }
   __syncthreads();
-  for (int c = tid; c < m0; c += 256) {
+  for (int c = tid; c < m0; c += blockDim.x) {
     lam[c] = sm[order[c] * m0 + order[c]];
     double ss = 0.0;
     for (int r = 0; r < m0; ++r) ss += C[r * m0 + c] * C[r * m0 + c];
@@ -1402,11 +1409,20 @@ template void launch_make_coefs<double>(hipStream_t, const LsqArgs&, const doubl
 void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB, double* lam, double* C, double* eta,
                      double* work) {
   IF_REQUIRE(m0 <= 128 && m0 % 2 == 0, "rayleigh-ritz: m0 must be even and <= 128");
-  const size_t lds = (size_t)m0 * m0 * sizeof(double);
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
+  size_t lds = (size_t)m0 * m0 * sizeof(double);
+  // the Jacobi rotations accumulate in LDS too when both matrices fit
+  const int v_in_lds = (int64_t)(2 * lds) + 4096 <= (int64_t)max_lds ? 1 : 0;
+  if (v_in_lds) lds *= 2;
   if (lds > 64 * 1024)
     IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rr_small), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-  hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(256), lds, st, m0, GA, GB, lam, C, eta, work);
+  hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(1024), lds, st, m0, GA, GB, lam, C, eta, work, v_in_lds);
   IF_HIP(hipGetLastError());
 }
 

@@ -105,12 +105,15 @@ typedef struct {
   double alpha;        /* inner tolerance factor, 0 <= alpha < 1 */
   double tol;          /* eigen-residual tolerance on ||R_F|| */
   double spurious_tau; /* a Ritz pair inside C counts when its filter gain >= tau |rho_hat(lambda)| */
-  double reorth_eta;   /* block Gram-Schmidt in the Arnoldi step: a second classical pass runs for a shift
-                          when some column kept less than this fraction of its norm in the first one,
-                          and the block is normalised by one Cholesky-QR pass when its Gram is certified
-                          well conditioned (two passes otherwise); >= 1 always runs two Gram-Schmidt and
-                          two Cholesky-QR passes; 0 selects 0.1 for per-shift bases and 2 (always two
-                          passes) for the shared basis, whose long recurrence needs them */
+  double reorth_eta;   /* block Gram-Schmidt in the Arnoldi step.  Per-shift bases: a second classical
+                          pass runs for a shift when some column kept less than this fraction of its
+                          norm in the first one, and the block is normalised by one Cholesky-QR pass
+                          when its Gram is certified well conditioned (two passes otherwise); 0
+                          selects 0.1.  Shared basis: both passes project against the two newest
+                          blocks, and the second also against every older block when the measured
+                          loss of orthogonality to them, max |V_i^T w| / ||w|| over columns w,
+                          exceeds this value; 0 selects 1e-4 (FP32 basis) or 1e-12 (FP64).  >= 1:
+                          always two full passes and two Cholesky-QR passes */
   int precision;       /* IFEAST_PREC_* */
   int problem;         /* IFEAST_PROBLEM_* */
   int inner_guess;     /* IFEAST_GUESS_* */

@@ -307,11 +307,13 @@ struct Engine::Impl {
   int* d_need = nullptr;    // ns flags: second Gram-Schmidt pass needed
   int* d_single = nullptr;  // ns flags: one Cholesky-QR pass is enough
   int* d_two = nullptr;     // ns flags: two Cholesky-QR passes
+  double* d_loss = nullptr; // measured loss of orthogonality of the shared basis' newest block
   double single_gersh = 0.5;
   double dead_thr = 1e-280;
   int64_t single_steps = 0; // shift-steps normalised with one Cholesky-QR pass
   double reorth_eta = 0.1;  // keep-fraction below which a second pass runs (>= 1: always)
   int64_t reorth_steps = 0; // shift-steps that ran a second pass
+  double max_loss = 0.0;     // largest measured loss of orthogonality (shared basis, partial mode)
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
 
   Impl(hipStream_t s, const Shape& shape) : sh(shape), st(s), L(layout(shape)) {
@@ -367,6 +369,7 @@ struct Engine::Impl {
     d_single = f + 512;
     d_two = f + 576;
     d_one = f + 640;
+    d_loss = reinterpret_cast<double*>(f + 704);
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
     // stale basis blocks of shifts that stopped early are multiplied by zero
@@ -532,13 +535,15 @@ struct Engine::Impl {
     h2d(zsD.p, zdv.data(), zdv.size() * sizeof(double));
     h2d(wsD.p, wf.data(), wf.size() * sizeof(double));
     h2d(tol.p, tolh.data(), tolh.size() * sizeof(double));
-    // the long recurrence keeps its basis orthonormal only with two passes of both
-    // Gram-Schmidt and Cholesky-QR at every step (one pass loses orthogonality over the
-    // steps and the inner solves stall, in FP32 first), so that is the default here
-    reorth_eta = p.reorth_eta > 0.0 ? p.reorth_eta : 2.0;
-    single_gersh = sizeof(T) == 4 ? 0.8 : 0.5;
-    dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
-    const bool always = reorth_eta >= 1.0;
+    // A is symmetric, so in exact arithmetic A V_j has components along V_{j-1} and V_j only
+    // (block Lanczos).  Each step projects W against those two blocks twice; in the second
+    // pass the coefficients against every block are formed, and the older blocks are
+    // projected out as well only when W has lost more than reorth_eta of orthogonality to
+    // them (measured, relative to each column's norm).  reorth_eta >= 1 projects against
+    // every block in both passes.
+    const bool always = p.reorth_eta >= 1.0;
+    const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? 1e-4 : 1e-12);
+    reorth_eta = thr;
     // Q = X rho_hat(Lambda); V_0 S0 = R
     launch_scale_cols(st, n, m0, Xd, rhod, Qd);
     launch_to_T<T>(st, bs, Rd, t1);
@@ -549,50 +554,51 @@ struct Engine::Impl {
     h2d(d_run, all.data(), ns * sizeof(int));
     note(d_active, all);
     LsqArgs la = lsq_args();
-    // A is symmetric: Hm is block tridiagonal up to rounding (block Lanczos), so the least
-    // squares problems keep one block above the diagonal
+    // Hm is block tridiagonal up to rounding, so the least squares problems keep one block
+    // above the diagonal
     la.band = 1;
     launch_lsq_init(st, la, Ss.as<cd>());
-    auto cgs_pass = [&](int j, int accumulate) {
-      GramArgs gg{n, m0, m0, 1, j + 1, Vb, m0, 0, bs, t1, m0, 0, 0, nullptr, gred.as<double>()};
+    // G = [V_lo..V_{lo+nb-1}]^T W
+    auto gram = [&](int lo, int nb) {
+      GramArgs gg{n, m0, m0, 1, nb, Vb + (int64_t)lo * bs, m0, 0, bs, t1, m0, 0, 0, nullptr, gred.as<double>()};
       launch_gram<T>(st, gg, gpart.p, gpart.bytes);
-      launch_combine_real<T>(st, j + 1, m0, j, ldh, gred.as<double>(), Hm.as<double>(), Hr.as<T>(), accumulate);
-      ApplyArgs ap{n, m0, m0, 1, j + 1, j + 1, Vb, m0, 0, 0, bs, Hr.p, 0, t1, m0, 0, -1.0, 1.0, nullptr, nullptr};
+    };
+    // W -= [V_lo..V_{lo+nb-1}] G_lo.., coefficients into block column j of Hm
+    auto project = [&](int j, int lo, int nb, const double* G, int accumulate) {
+      launch_combine_real<T>(st, nb, lo, m0, j, ldh, G, Hm.as<double>(), Hr.as<T>(), accumulate);
+      ApplyArgs ap{n, m0, m0, 1, nb, nb, Vb + (int64_t)lo * bs, m0, 0, 0, bs, Hr.p, 0, t1, m0, 0, -1.0, 1.0, nullptr,
+                   nullptr};
       launch_apply<T, T>(st, ap);
     };
+    GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
     int jdone = 0;
     for (int j = 0; j < K; ++j) {
       // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
       // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike)
       launch_spmm_shifted<T>(st, A, nullptr, 1, m0 / 2, zsT.as<T>(), nullptr, Vb + (int64_t)j * bs, t1);
-      cgs_pass(j, 0);
-      if (always) {
-        cgs_pass(j, 1);
-        ++reorth_steps;
-      }
-      GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
-      launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-      std::vector<int> fl{0, 0, 1};
-      if (!always) {
-        launch_orth_check_real(st, m0, j, ldh, reorth_eta, single_gersh, dead_thr, gwb.as<double>(), Hm.as<double>(),
-                               d_need);
-        fl = d2h_ints(d_need, 3);
-      }
-      if (fl[0]) {
-        cgs_pass(j, 1);
+      const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
+      gram(lo, nl);
+      project(j, lo, nl, gred.as<double>(), 0);
+      gram(0, j + 1);
+      bool full = always || lo == 0;
+      if (!full) {
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-        ++reorth_steps;
+        launch_loss_check_real(st, lo, m0, gred.as<double>(), gwb.as<double>(), thr, d_need, d_loss);
+        double loss = 0.0;
+        IF_HIP(hipMemcpyAsync(&loss, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        IF_HIP(hipStreamSynchronize(st));
+        full = loss > thr;
+        max_loss = std::max(max_loss, loss);
       }
-      T* dst = Vb + (int64_t)(j + 1) * bs;
-      if (fl[1]) {
-        launch_cholqr_factor<T>(st, 1, m0, gwb.as<double>(), 0.0, nullptr, Tinv.as<T>(), Racc.as<cd>(), 0,
-                                chol.as<cd>(), true);
-        ApplyArgs ap{n, m0, m0, 1, 1, 1, t1, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
-        launch_apply<T, T>(st, ap);
-        ++single_steps;
+      if (full) {
+        project(j, 0, j + 1, gred.as<double>(), 1);
+        if (lo > 0) ++reorth_steps;
       } else {
-        cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
+        project(j, lo, nl, gred.as<double>() + (int64_t)lo * m0 * m0, 1);
       }
+      launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+      T* dst = Vb + (int64_t)(j + 1) * bs;
+      cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
       launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
       launch_shift_column(st, ns, m0, j, ldh, K, zsD.as<double>(), d_active, Hm.as<double>(), H.as<cd>(), la.band);
       launch_lsq_step(st, la, j);
@@ -967,8 +973,9 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         (void)hipEventElapsedTime(&ms_now, e0, en);
         (void)hipEventDestroy(en);
       }
-      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld t=%.2fs\n", it + 1,
-              stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps, ms_now * 1e-3);
+      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld loss=%.1e t=%.2fs\n",
+              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps, I.max_loss,
+              ms_now * 1e-3);
       if (verbose2) {
         std::vector<double> etah(m0), rhoh(m0);
         IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));

@@ -32,11 +32,11 @@ __global__ void k_to_T(int64_t count, const double* __restrict__ X, T* __restric
   if (i < count) Y[i] = (T)X[i];
 }
 
-// Coefficients of one Gram-Schmidt pass: G = [V_0..V_j]^T W (ni = j+1 items of m0 x m0,
-// item-major, row a = basis column) -> block column j of Hm (+= when accumulating)
-// and the update factors Hr (same layout as G, type T) for W -= sum_i V_i Hr_i.
+// Coefficients of one Gram-Schmidt pass: G = [V_i0..V_{i0+ni-1}]^T W (ni items of m0 x m0,
+// item-major, row a = basis column) -> block rows i0.. of block column j of Hm (+= when
+// accumulating) and the update factors Hr (same layout as G, type T) for W -= sum_i V_i Hr_i.
 template <class T>
-__global__ void k_combine_real(int ni, int m0, int j, int ldh, const double* __restrict__ G,
+__global__ void k_combine_real(int ni, int i0, int m0, int j, int ldh, const double* __restrict__ G,
                                double* __restrict__ Hm, T* __restrict__ Hr, int accumulate) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)m0 * m0;
@@ -44,41 +44,36 @@ __global__ void k_combine_real(int ni, int m0, int j, int ldh, const double* __r
   const int i = (int)(idx / per);
   const int a = (int)((idx % per) / m0), b = (int)(idx % m0);
   const double c = G[idx];
-  double* h = Hm + (int64_t)(j * m0 + b) * ldh + i * m0 + a;
+  double* h = Hm + (int64_t)(j * m0 + b) * ldh + (i0 + i) * m0 + a;
   *h = accumulate ? *h + c : c;
   Hr[idx] = (T)c;
 }
 
-// need / single / twopass flags of the shared block (see k_orth_check): G = W1^T W1 real
-// (m0 x m0), H = block column j of Hm (rows 0..(j+1) m0).
-__global__ void k_orth_check_real(int m0, int j, int ldh, double eta2, double gersh, double dead_thr,
-                                  const double* __restrict__ G, const double* __restrict__ Hm,
-                                  int* __restrict__ flags /* need, single, twopass */) {
-  __shared__ int any_need, any_bad;
-  __shared__ double dsc[128];
-  if (threadIdx.x == 0) any_need = any_bad = 0;
-  __syncthreads();
-  const double* Hc = Hm + (int64_t)j * m0 * ldh;
+// Loss of orthogonality of the projected block W against the older basis blocks: the
+// largest |V_i^T w_b| / ||w_b|| over the first nold items of G = [V_0..]^T W (layout as
+// above) with ||w_b||^2 the diagonal of gw = W^T W.  flags[0] = (loss > thr), out[0] = loss.
+// One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_loss_check_real(int nold, int m0, const double* __restrict__ G,
+                                                          const double* __restrict__ gw, double thr,
+                                                          int* __restrict__ flags, double* __restrict__ out) {
+  __shared__ double inv[128];
+  __shared__ double red[16];
   for (int c = threadIdx.x; c < m0; c += blockDim.x) {
-    const double w1 = G[c * m0 + c];
-    double h = 0.0;
-    for (int r = 0; r < (j + 1) * m0; ++r) h += Hc[r + (int64_t)c * ldh] * Hc[r + (int64_t)c * ldh];
-    if (w1 > 1e-30 && w1 < eta2 * (w1 + h)) atomicOr(&any_need, 1);
-    if (!(w1 > dead_thr)) atomicOr(&any_bad, 1);
-    dsc[c] = sqrt(fmax(w1, 1e-300));
+    const double d = gw[c * m0 + c];
+    inv[c] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < m0; r += blockDim.x) {
-    double off = 0.0;
-    for (int c = 0; c < m0; ++c)
-      if (c != r) off += fabs(G[r * m0 + c]) / (dsc[r] * dsc[c]);
-    if (!(off <= gersh)) atomicOr(&any_bad, 1);
-  }
+  double mx = 0.0;
+  const int64_t tot = (int64_t)nold * m0 * m0;
+  for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) mx = fmax(mx, fabs(G[i]) * inv[i % m0]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x == 0) {
-    flags[0] = any_need;
-    flags[1] = (any_need == 0 && any_bad == 0) ? 1 : 0;
-    flags[2] = flags[1] ? 0 : 1;
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    flags[0] = m > thr ? 1 : 0;
+    out[0] = m;
   }
 }
 
@@ -145,17 +140,16 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y) {
   IF_HIP(hipGetLastError());
 }
 template <class T>
-void launch_combine_real(hipStream_t st, int ni, int m0, int j, int ldh, const double* G, double* Hm, T* Hr,
-                         int accumulate) {
-  hipLaunchKernelGGL((k_combine_real<T>), dim3(nblk((int64_t)ni * m0 * m0)), dim3(256), 0, st, ni, m0, j, ldh, G, Hm,
-                     Hr, accumulate);
+void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh, const double* G, double* Hm,
+                         T* Hr, int accumulate) {
+  hipLaunchKernelGGL((k_combine_real<T>), dim3(nblk((int64_t)ni * m0 * m0)), dim3(256), 0, st, ni, i0, m0, j, ldh, G,
+                     Hm, Hr, accumulate);
   IF_HIP(hipGetLastError());
 }
-void launch_orth_check_real(hipStream_t st, int m0, int j, int ldh, double eta, double gersh, double dead_thr,
-                            const double* G, const double* Hm, int* flags) {
-  IF_REQUIRE(m0 <= 128, "orth check: m0 > 128");
-  hipLaunchKernelGGL(k_orth_check_real, dim3(1), dim3(128), 0, st, m0, j, ldh, eta * eta, gersh, dead_thr, G, Hm,
-                     flags);
+void launch_loss_check_real(hipStream_t st, int nold, int m0, const double* G, const double* gw, double thr,
+                            int* flags, double* out) {
+  IF_REQUIRE(m0 <= 128, "orthogonality check: m0 > 128");
+  hipLaunchKernelGGL(k_loss_check_real, dim3(1), dim3(1024), 0, st, nold, m0, G, gw, thr, flags, out);
   IF_HIP(hipGetLastError());
 }
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {
@@ -183,8 +177,9 @@ void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* 
 
 template void launch_to_T<float>(hipStream_t, int64_t, const double*, float*);
 template void launch_to_T<double>(hipStream_t, int64_t, const double*, double*);
-template void launch_combine_real<float>(hipStream_t, int, int, int, int, const double*, double*, float*, int);
-template void launch_combine_real<double>(hipStream_t, int, int, int, int, const double*, double*, double*, int);
+template void launch_combine_real<float>(hipStream_t, int, int, int, int, int, const double*, double*, float*, int);
+template void launch_combine_real<double>(hipStream_t, int, int, int, int, int, const double*, double*, double*,
+                                           int);
 template void launch_sum_y<float>(hipStream_t, int, int, int, int, const cd*, const double*, float*);
 template void launch_sum_y<double>(hipStream_t, int, int, int, int, const cd*, const double*, double*);
 

@@ -156,11 +156,15 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
 // ------------------------------------------------------------ workspace
 namespace {
 
+// Columns of the random sketch that estimates the shared basis' loss of orthogonality.
+constexpr int kSketch = 16;
+
 struct Layout {
   // byte sizes of every buffer of the workspace
   size_t X, Q, AQ, BQ, R, vec, mm, rrwork, colpart;
   size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gw, Hr, Tinv, Racc, chol, Yq, Uc, zs;
   size_t Hm, Ss;  // shared basis: real block Hessenberg, per-shift start blocks
+  size_t Us, Om;  // shared basis: sketch of the older blocks (n x kSketch), its random factors
 };
 
 Layout layout(const Shape& s) {
@@ -192,7 +196,9 @@ Layout layout(const Shape& s) {
     L.V = (k + 1) * n * m0 * ts;
     L.T1 = n * m0 * ts;
     L.u = 16;
-    size_t gp = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
+    size_t gp = std::max(gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1),
+                         ts == 4 ? gram_partial_bytes<float>(s.n, kSketch, (int)m0, 1)
+                                 : gram_partial_bytes<double>(s.n, kSketch, (int)m0, 1));
     for (size_t items = 1; items <= k; ++items)
       gp = std::max(gp, ts == 4 ? gram_partial_bytes<float>(s.n, (int)m0, (int)m0, (int)items)
                                 : gram_partial_bytes<double>(s.n, (int)m0, (int)m0, (int)items));
@@ -205,6 +211,8 @@ Layout layout(const Shape& s) {
     L.Uc = 16;
     L.Hm = ldh * k * m0 * 8;
     L.Ss = ns * m0 * m0 * 16;
+    L.Us = n * kSketch * ts;
+    L.Om = k * m0 * kSketch * ts;
     return L;
   }
   L.V = (k + 1) * n * ldc * 2 * ts;
@@ -224,13 +232,15 @@ Layout layout(const Shape& s) {
   L.Uc = ns * (k + 1) * m2 * m2 * ts;
   L.Hm = 0;
   L.Ss = 0;
+  L.Us = 0;
+  L.Om = 0;
   return L;
 }
 
 size_t total(const Layout& L) {
   return 3 * L.X + L.AQ + L.BQ + L.R + 8 * L.vec + 3 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
          L.tauh + L.g + L.u + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq +
-         L.Uc + 3 * L.zs + L.Hm + L.Ss;
+         L.Uc + 3 * L.zs + L.Hm + L.Ss + L.Us + L.Om;
 }
 
 }  // namespace
@@ -296,6 +306,7 @@ struct Engine::Impl {
   // inner
   DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gwb, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
   DevBuf Hm, Ss;             // shared basis
+  DevBuf Us, Om;             // shared basis: sketch of the older blocks, its random factors
   int* d_one = nullptr;      // a single 1 (the shared block's activity flag)
   int shared_steps = 0;      // Arnoldi steps of the last shared inner solve
   int* d_active = nullptr;  // ns
@@ -358,6 +369,24 @@ struct Engine::Impl {
     wsD = DevBuf(L.zs);
     if (L.Hm) Hm = DevBuf(L.Hm);
     if (L.Ss) Ss = DevBuf(L.Ss);
+    if (L.Us) Us = DevBuf(L.Us);
+    if (L.Om) {
+      // fixed Gaussian factors, variance 1 / kSketch: E ||Om^T x||^2 = ||x||^2
+      Om = DevBuf(L.Om);
+      std::mt19937_64 gen(0x5eed5ce7c4ULL);
+      std::normal_distribution<double> nd(0.0, 1.0 / std::sqrt((double)kSketch));
+      const bool f32 = sh.precision == IFEAST_PREC_MIXED;
+      const size_t cnt = L.Om / (f32 ? 4 : 8);
+      if (!f32) {
+        std::vector<double> h(cnt);
+        for (auto& x : h) x = nd(gen);
+        h2d(Om.p, h.data(), L.Om);
+      } else {
+        std::vector<float> h(cnt);
+        for (auto& x : h) x = (float)nd(gen);
+        h2d(Om.p, h.data(), L.Om);
+      }
+    }
     int* f = flags.as<int>();
     d_active = f;
     d_run = f + 64;
@@ -536,11 +565,12 @@ struct Engine::Impl {
     h2d(wsD.p, wf.data(), wf.size() * sizeof(double));
     h2d(tol.p, tolh.data(), tolh.size() * sizeof(double));
     // A is symmetric, so in exact arithmetic A V_j has components along V_{j-1} and V_j only
-    // (block Lanczos).  Each step projects W against those two blocks twice; in the second
-    // pass the coefficients against every block are formed, and the older blocks are
-    // projected out as well only when W has lost more than reorth_eta of orthogonality to
-    // them (measured, relative to each column's norm).  reorth_eta >= 1 projects against
-    // every block in both passes.
+    // (block Lanczos).  Each step projects W against those two blocks twice, and the second
+    // pass projects against every block when W has lost more than reorth_eta of
+    // orthogonality to the older ones: ||[V_0..V_{j-2}]^T w|| / ||w|| over the columns w,
+    // estimated from a Gaussian sketch U = sum_i V_i Om_i of those blocks (kSketch columns,
+    // E ||U^T w||^2 = ||[V_0..]^T w||^2), so that the estimate reads n x kSketch numbers
+    // instead of the whole basis.  reorth_eta >= 1 projects against every block in both passes.
     const bool always = p.reorth_eta >= 1.0;
     const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? 1e-4 : 1e-12);
     reorth_eta = thr;
@@ -571,6 +601,8 @@ struct Engine::Impl {
       launch_apply<T, T>(st, ap);
     };
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
+    T* U = Us.as<T>();
+    if (!always) launch_fill_zero(st, Us.p, Us.bytes);
     int jdone = 0;
     for (int j = 0; j < K; ++j) {
       // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
@@ -579,22 +611,29 @@ struct Engine::Impl {
       const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
       gram(lo, nl);
       project(j, lo, nl, gred.as<double>(), 0);
-      gram(0, j + 1);
       bool full = always || lo == 0;
       if (!full) {
+        // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
+        ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
+                     Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
+        launch_apply<T, T>(st, au);
+        GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gred.as<double>()};
+        launch_gram<T>(st, gs, gpart.p, gpart.bytes);
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-        launch_loss_check_real(st, lo, m0, gred.as<double>(), gwb.as<double>(), thr, d_need, d_loss);
+        launch_sketch_check_real(st, kSketch, m0, gred.as<double>(), gwb.as<double>(), d_loss);
         double loss = 0.0;
         IF_HIP(hipMemcpyAsync(&loss, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
         IF_HIP(hipStreamSynchronize(st));
-        full = loss > thr;
+        full = !(loss <= thr);
         max_loss = std::max(max_loss, loss);
       }
       if (full) {
+        gram(0, j + 1);
         project(j, 0, j + 1, gred.as<double>(), 1);
         if (lo > 0) ++reorth_steps;
       } else {
-        project(j, lo, nl, gred.as<double>() + (int64_t)lo * m0 * m0, 1);
+        gram(lo, nl);
+        project(j, lo, nl, gred.as<double>(), 1);
       }
       launch_gram<T>(st, gw, gpart.p, gpart.bytes);
       T* dst = Vb + (int64_t)(j + 1) * bs;

@@ -244,9 +244,8 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
 template <class T>
 void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh, const double* G, double* Hm,
                          T* Hr, int accumulate);
-// flags[0] = (max over the first nold items of |G| / ||w|| > thr), out[0] = that maximum
-void launch_loss_check_real(hipStream_t st, int nold, int m0, const double* G, const double* gw, double thr,
-                            int* flags, double* out);
+// out[0] = max over columns b of ||G[:, b]|| / ||w_b|| (G = U^T W, nk x m0; gw = W^T W)
+void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
 // block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
 void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,

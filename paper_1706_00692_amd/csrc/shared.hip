@@ -49,32 +49,28 @@ __global__ void k_combine_real(int ni, int i0, int m0, int j, int ldh, const dou
   Hr[idx] = (T)c;
 }
 
-// Loss of orthogonality of the projected block W against the older basis blocks: the
-// largest |V_i^T w_b| / ||w_b|| over the first nold items of G = [V_0..]^T W (layout as
-// above) with ||w_b||^2 the diagonal of gw = W^T W.  flags[0] = (loss > thr), out[0] = loss.
-// One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_loss_check_real(int nold, int m0, const double* __restrict__ G,
-                                                          const double* __restrict__ gw, double thr,
-                                                          int* __restrict__ flags, double* __restrict__ out) {
-  __shared__ double inv[128];
-  __shared__ double red[16];
-  for (int c = threadIdx.x; c < m0; c += blockDim.x) {
-    const double d = gw[c * m0 + c];
-    inv[c] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+// Estimated loss of orthogonality of the projected block W against the older basis blocks:
+// max over columns b of ||G[:, b]|| / ||w_b|| with G = U^T W (ns_k x m0, row-major) the
+// sketch product and ||w_b||^2 the diagonal of gw = W^T W.  out[0] = that maximum (NaN
+// when some column is not finite).  One workgroup of 128 threads.
+__global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const double* __restrict__ G,
+                                                           const double* __restrict__ gw, double* __restrict__ out) {
+  __shared__ double red[2];
+  double r = 0.0;
+  for (int b = threadIdx.x; b < m0; b += blockDim.x) {
+    double ss = 0.0;
+    for (int a = 0; a < nk; ++a) ss += G[a * m0 + b] * G[a * m0 + b];
+    const double d = gw[b * m0 + b];
+    const double v = d > 0.0 ? sqrt(ss / d) : (ss > 0.0 ? INFINITY : 0.0);
+    r = (v > r || v != v) ? v : r;
   }
-  __syncthreads();
-  double mx = 0.0;
-  const int64_t tot = (int64_t)nold * m0 * m0;
-  for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) mx = fmax(mx, fabs(G[i]) * inv[i % m0]);
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-    flags[0] = m > thr ? 1 : 0;
-    out[0] = m;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double t = __shfl_xor(r, o);
+    r = (t > r || t != t) ? t : r;
   }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (red[1] > red[0] || red[1] != red[1]) ? red[1] : red[0];
 }
 
 // Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
@@ -146,10 +142,8 @@ void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh,
                      Hm, Hr, accumulate);
   IF_HIP(hipGetLastError());
 }
-void launch_loss_check_real(hipStream_t st, int nold, int m0, const double* G, const double* gw, double thr,
-                            int* flags, double* out) {
-  IF_REQUIRE(m0 <= 128, "orthogonality check: m0 > 128");
-  hipLaunchKernelGGL(k_loss_check_real, dim3(1), dim3(1024), 0, st, nold, m0, G, gw, thr, flags, out);
+void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out) {
+  hipLaunchKernelGGL(k_sketch_check_real, dim3(1), dim3(128), 0, st, nk, m0, G, gw, out);
   IF_HIP(hipGetLastError());
 }
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {

@@ -327,6 +327,28 @@ struct Engine::Impl {
   double max_loss = 0.0;     // largest measured loss of orthogonality (shared basis, partial mode)
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
 
+  // side stream of the shared-basis least squares updates, its events and host flag slots
+  hipStream_t st_lsq = nullptr;
+  hipEvent_t ev_main = nullptr, ev_lsq[2] = {nullptr, nullptr};
+  int* h_flags = nullptr;  // pinned, 2 x 64
+  void side_stream() {
+    if (st_lsq) return;
+    IF_HIP(hipStreamCreateWithFlags(&st_lsq, hipStreamNonBlocking));
+    IF_HIP(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
+    IF_HIP(hipEventCreateWithFlags(&ev_lsq[0], hipEventDisableTiming));
+    IF_HIP(hipEventCreateWithFlags(&ev_lsq[1], hipEventDisableTiming));
+    IF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_flags), 2 * 64 * sizeof(int), hipHostMallocDefault));
+  }
+  ~Impl() {
+    if (st_lsq) (void)hipStreamSynchronize(st_lsq);
+    if (h_flags) (void)hipHostFree(h_flags);
+    for (hipEvent_t e : {ev_main, ev_lsq[0], ev_lsq[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (st_lsq) (void)hipStreamDestroy(st_lsq);
+  }
+  Impl(const Impl&) = delete;
+  Impl& operator=(const Impl&) = delete;
+
   Impl(hipStream_t s, const Shape& shape) : sh(shape), st(s), L(layout(shape)) {
     X = DevBuf(L.X);
     Q = DevBuf(L.Q);
@@ -603,6 +625,7 @@ struct Engine::Impl {
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
     T* U = Us.as<T>();
     if (!always) launch_fill_zero(st, Us.p, Us.bytes);
+    side_stream();
     int jdone = 0;
     for (int j = 0; j < K; ++j) {
       // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
@@ -612,6 +635,7 @@ struct Engine::Impl {
       gram(lo, nl);
       project(j, lo, nl, gred.as<double>(), 0);
       bool full = always || lo == 0;
+      const bool have_gw = !full;  // W^T W after the first pass is formed for the estimate
       if (!full) {
         // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
         ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
@@ -627,25 +651,44 @@ struct Engine::Impl {
         full = !(loss <= thr);
         max_loss = std::max(max_loss, loss);
       }
-      if (full) {
-        gram(0, j + 1);
-        project(j, 0, j + 1, gred.as<double>(), 1);
-        if (lo > 0) ++reorth_steps;
-      } else {
-        gram(lo, nl);
-        project(j, lo, nl, gred.as<double>(), 1);
-      }
-      launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+      const int plo = full ? 0 : lo, pnb = j + 1 - plo;
+      gram(plo, pnb);
+      project(j, plo, pnb, gred.as<double>(), 1);
+      if (full && lo > 0) ++reorth_steps;
+      // the Gram of the projected block: W^T W - C^T C (the second pass removes little, so
+      // this loses nothing to cancellation), else computed afresh
+      if (have_gw)
+        launch_gram_downdate(st, pnb * m0, m0, gred.as<double>(), gwb.as<double>());
+      else
+        launch_gram<T>(st, gw, gpart.p, gpart.bytes);
       T* dst = Vb + (int64_t)(j + 1) * bs;
       cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
       launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
-      launch_shift_column(st, ns, m0, j, ldh, K, zsD.as<double>(), d_active, Hm.as<double>(), H.as<cd>(), la.band);
-      launch_lsq_step(st, la, j);
+      // the shifts' least squares updates of step j run on the side stream, beside step
+      // j + 1's basis work; their stop flags are read one step later
+      IF_HIP(hipEventRecord(ev_main, st));
+      IF_HIP(hipStreamWaitEvent(st_lsq, ev_main, 0));
+      launch_shift_column(st_lsq, ns, m0, j, ldh, K, zsD.as<double>(), d_active, Hm.as<double>(), H.as<cd>(),
+                          la.band);
+      launch_lsq_step(st_lsq, la, j);
+      IF_HIP(hipMemcpyAsync(h_flags + (j & 1) * 64, d_active, ns * sizeof(int), hipMemcpyDeviceToHost, st_lsq));
+      IF_HIP(hipEventRecord(ev_lsq[j & 1], st_lsq));
       jdone = j + 1;
-      const std::vector<int> act = d2h_ints(d_active, ns);
-      note(d_active, act);
-      if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) break;
+      if (j >= 1) {
+        // every shift had stopped after step j - 1: step j's update left the least squares
+        // problems as they were (it skips stopped shifts), so the solution uses j blocks
+        IF_HIP(hipEventSynchronize(ev_lsq[(j - 1) & 1]));
+        const int* hf = h_flags + ((j - 1) & 1) * 64;
+        const std::vector<int> act(hf, hf + ns);
+        note(d_active, act);
+        if (std::none_of(act.begin(), act.end(), [](int a) { return a != 0; })) {
+          jdone = j;
+          break;
+        }
+      }
     }
+    IF_HIP(hipEventRecord(ev_lsq[0], st_lsq));
+    IF_HIP(hipStreamWaitEvent(st, ev_lsq[0], 0));
     shared_steps = jdone;
     launch_lsq_finish(st, la);
     launch_sum_y<T>(st, ns, m0, K, jdone, y.as<cd>(), wsD.as<double>(), Yq.as<T>());

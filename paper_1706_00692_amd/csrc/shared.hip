@@ -73,6 +73,17 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
   if (threadIdx.x == 0) out[0] = (red[1] > red[0] || red[1] != red[1]) ? red[1] : red[0];
 }
 
+// Gram of the block after a projection W2 = W1 - V C with orthonormal V: W2^T W2 =
+// W1^T W1 - C^T C.  gw (m0 x m0) holds W1^T W1 on entry; C has `rows` rows of m0.
+__global__ void k_gram_downdate(int rows, int m0, const double* __restrict__ C, double* __restrict__ gw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m0 * m0) return;
+  const int a = idx / m0, b = idx % m0;
+  double acc = 0.0;
+  for (int r = 0; r < rows; ++r) acc += C[(int64_t)r * m0 + a] * C[(int64_t)r * m0 + b];
+  gw[idx] -= acc;
+}
+
 // Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
 __global__ void k_subdiag_real(int m0, int j, int ldh, const c2* __restrict__ Racc, double* __restrict__ Hm) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,6 +155,10 @@ void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh,
 }
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out) {
   hipLaunchKernelGGL(k_sketch_check_real, dim3(1), dim3(128), 0, st, nk, m0, G, gw, out);
+  IF_HIP(hipGetLastError());
+}
+void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw) {
+  hipLaunchKernelGGL(k_gram_downdate, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, rows, m0, C, gw);
   IF_HIP(hipGetLastError());
 }
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {

@@ -940,6 +940,83 @@ __global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
   }
 }
 
+// y = R^{-1} g_top for a block-banded R (no u): block back substitution from the last block
+// row up.  Per block b: the diagonal block R_bb (packed upper triangle) is staged in LDS
+// once for the workgroup's four right-hand sides (one wave each) and solved column by
+// column, then the rows of blocks b - band - 1 .. b - 1 take the products with R's block
+// column b.  Each wave keeps its right-hand side's rows of the band + 2 blocks that the
+// current block row touches in an LDS window (row r in slot r mod (band + 2) m0); solved
+// blocks go to y, the next block above comes in from g.  grid (ns, ceil(m0/4)); LDS:
+// m0 (m0 + 1) / 2 + 4 (band + 2) m0 complex.
+__global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
+  extern __shared__ c2 fb_lds[];
+  const int s = blockIdx.x;
+  const int J = a.iters[s];
+  if (J == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, ldy = a.k * m0;
+  const int WB = a.band + 2, W = WB * m0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int col = blockIdx.y * 4 + wave;
+  const bool live = col < m0;  // dead waves still join the workgroup barriers
+  c2* Rd = fb_lds;                                  // packed R_bb, column cl at cl (cl + 1) / 2
+  c2* x = fb_lds + m0 * (m0 + 1) / 2 + wave * W;    // this wave's window
+  const int n = J * m0;
+  const c2* gc = v.g + (int64_t)(live ? col : 0) * ldh;
+  c2* yc = v.y + (int64_t)(live ? col : 0) * ldy;
+  if (live) {
+    for (int r = n + lane; r < ldy; r += 64) yc[r] = cmk(0.0, 0.0);
+    for (int r = max(0, n - W) + lane; r < n; r += 64) x[r % W] = gc[r];
+  }
+  for (int b = J - 1; b >= 0; --b) {
+    const int b0 = b * m0;
+    __syncthreads();
+    for (int idx = tid; idx < m0 * (m0 + 1) / 2; idx += blockDim.x) {
+      int cl = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (cl * (cl + 1) / 2 > idx) --cl;
+      while ((cl + 1) * (cl + 2) / 2 <= idx) ++cl;
+      const int r = idx - cl * (cl + 1) / 2;
+      Rd[idx] = v.H[(int64_t)(b0 + cl) * ldh + b0 + r];
+    }
+    __syncthreads();
+    if (live) {
+      // triangular solve with R_bb on the rows of block b
+      for (int cl = m0 - 1; cl >= 0; --cl) {
+        const c2* Rc = Rd + cl * (cl + 1) / 2;
+        const c2 d = Rc[cl];
+        const c2 yv = cabs2(d) > 1e-300 ? cdiv(x[(b0 + cl) % W], d) : cmk(0.0, 0.0);
+        for (int r = lane; r < cl; r += 64) {
+          c2& t = x[(b0 + r) % W];
+          t = csub(t, cmul(Rc[r], yv));
+        }
+        if (lane == 0) x[(b0 + cl) % W] = yv;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+      // rows of the blocks above within the band: x -= R(rows, block b) y_b
+      const int rlo = max(0, (b - a.band - 1) * m0);
+      for (int r0 = rlo; r0 < b0; r0 += 64) {
+        const int r = r0 + lane;
+        if (r < b0) {
+          c2 acc = cmk(0.0, 0.0);
+          const c2* Hr = v.H + (int64_t)b0 * ldh + r;
+          for (int cl = 0; cl < m0; ++cl) acc = cadd(acc, cmul(Hr[(int64_t)cl * ldh], x[(b0 + cl) % W]));
+          c2& t = x[r % W];
+          t = csub(t, acc);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      // block b is solved: out to y; its slots take the block that block row b - 1 reaches
+      const int nb = b - WB;
+      for (int r = lane; r < m0; r += 64) {
+        const int slot = (b0 + r) % W;
+        yc[b0 + r] = x[slot];
+        if (nb >= 0) x[slot] = gc[nb * m0 + r];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  }
+}
+
 // Yq[s][b]: (2m0 x m0) real form for Q += Re(V_b (wf y_b)); Uc[s][b]: (2m0 x 2m0) real form of u_b.
 template <class T>
 __global__ void k_make_coefs(LsqArgs a, const double* __restrict__ wfac, int jmax, T* __restrict__ Yq,
@@ -1384,6 +1461,17 @@ void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
+  if (a.band > 0 && !a.need_u && a.m0 <= 128) {
+    const size_t lds = ((size_t)a.m0 * (a.m0 + 1) / 2 + (size_t)4 * (a.band + 2) * a.m0) * sizeof(c2);
+    if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
+      if (lds > 64 * 1024)
+        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_finish_band),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(k_lsq_finish_band, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a);
+      IF_HIP(hipGetLastError());
+      return;
+    }
   }
   const size_t lds = (size_t)4 * a.ldh * sizeof(c2);
   if ((int64_t)lds + 1024 <= (int64_t)max_lds) {

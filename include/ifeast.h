@@ -110,10 +110,11 @@ typedef struct {
                           norm in the first one, and the block is normalised by one Cholesky-QR pass
                           when its Gram is certified well conditioned (two passes otherwise); 0
                           selects 0.1.  Shared basis: both passes project against the two newest
-                          blocks, and the second also against every older block when the measured
-                          loss of orthogonality to them, max |V_i^T w| / ||w|| over columns w,
-                          exceeds this value; 0 selects 1e-4 (FP32 basis) or 1e-12 (FP64).  >= 1:
-                          always two full passes and two Cholesky-QR passes */
+                          blocks, and the second also against every older block when the loss of
+                          orthogonality to them, max over columns w of ||[V_0..]^T w|| / ||w||
+                          estimated from a 16-column random sketch, exceeds this value; 0 selects
+                          max(1e-4, alpha / 4) for an FP32 basis and 1e-12 for an FP64 one.
+                          >= 1: always two full passes and two Cholesky-QR passes */
   int precision;       /* IFEAST_PREC_* */
   int problem;         /* IFEAST_PROBLEM_* */
   int inner_guess;     /* IFEAST_GUESS_* */
@@ -180,6 +181,16 @@ int ifeast_footprint(int64_t n, int64_t nnzA, int64_t nnzB, const ifeast_contour
 int ifeast_solve_resident(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matrix *B,
                           const ifeast_contour *C, const ifeast_params *p, const double *X0,
                           ifeast_result *res);
+
+/* As ifeast_solve_resident with the big arrays in HBM: X0 is a device n x m0
+ * row-major initial block (required), evec a device n x m0 row-major output
+ * for the eigenvectors in the order of res's arrays (NULL: not written).  The
+ * small host arrays of res are filled as in ifeast_solve_resident; res->evec,
+ * when non-NULL, is filled too.  Both device buffers belong to the caller and
+ * are used on the context's stream; the call returns when the solve is done. */
+int ifeast_solve_dev(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matrix *B,
+                     const ifeast_contour *C, const ifeast_params *p, const double *X0,
+                     double *evec, ifeast_result *res);
 
 /* Upload, solve, free: ifeast_matrix_create + ifeast_solve_resident. */
 int ifeast_solve(ifeast_ctx *ctx, const ifeast_csr *A, const ifeast_csr *B, const ifeast_contour *C,

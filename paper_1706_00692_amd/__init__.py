@@ -14,6 +14,7 @@ from ._binding import (
     Result,
     contour_struct,
     params_struct,
+    problem_params,
     footprint,
     library_path,
     load_library,
@@ -35,6 +36,7 @@ __all__ = [
     "Result",
     "contour_struct",
     "params_struct",
+    "problem_params",
     "footprint",
     "library_path",
     "load_library",

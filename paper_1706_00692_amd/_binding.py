@@ -99,6 +99,8 @@ def load_library():
                                    C.POINTER(u64)]),
         "ifeast_solve_resident": (i32, [vp, vp, vp, C.POINTER(ContourStruct), C.POINTER(ParamsStruct), vp,
                                         C.POINTER(ResultStruct)]),
+        "ifeast_solve_dev": (i32, [vp, vp, vp, C.POINTER(ContourStruct), C.POINTER(ParamsStruct), vp, vp,
+                                   C.POINTER(ResultStruct)]),
         "ifeast_solve": (i32, [vp, C.POINTER(CSRStruct), C.POINTER(CSRStruct), C.POINTER(ContourStruct),
                                C.POINTER(ParamsStruct), vp, C.POINTER(ResultStruct)]),
         "ifeast_submit": (i32, [vp, C.POINTER(CSRStruct), C.POINTER(CSRStruct), C.POINTER(ContourStruct),
@@ -175,6 +177,14 @@ def _params_from(p, precision):
                          INNER_COLUMN if p.inner_rule == "column" else INNER_GLOBAL)
 
 
+def problem_params(prob, precision=PREC_FP64, **overrides) -> ParamsStruct:
+    """The ifeast_params of a workloads.Problem, with field overrides."""
+    params = _params_from(prob, precision)
+    for k, v in overrides.items():
+        setattr(params, k, v)
+    return params
+
+
 def footprint(n, nnzA, nnzB, contour: dict, params: ParamsStruct) -> int:
     lib = load_library()
     cs, keep = contour_struct(contour)
@@ -214,17 +224,18 @@ class Result:
 
 
 class _ResultBuffers:
-    def __init__(self, n, m0, max_outer, nc):
+    def __init__(self, n, m0, max_outer, nc, host_evec=True):
         self.eval_re = np.zeros(m0)
         self.eval_im = np.zeros(m0)
-        self.evec = np.zeros((n, m0))
+        self.evec = np.zeros((n, m0)) if host_evec else None
         self.resid = np.zeros(m0)
         self.flags = np.zeros(m0, dtype=np.int32)
         self.rf_hist = np.zeros(max_outer)
         self.inner_hist = np.zeros(max_outer * nc, dtype=np.int32)
         self.s = ResultStruct()
         for name in ("eval_re", "eval_im", "evec", "resid", "flags", "rf_hist", "inner_hist"):
-            setattr(self.s, name, getattr(self, name).ctypes.data)
+            arr = getattr(self, name)
+            setattr(self.s, name, None if arr is None else arr.ctypes.data)
 
     def result(self, status, nc, latency=float("nan")):
         s = self.s
@@ -307,6 +318,18 @@ class Context:
                                                          C.byref(bufs.s)))
         return bufs.result(st, cs.nc)
 
+    def solve_dev(self, A: Matrix, B: Matrix | None, contour: dict, params: ParamsStruct, X0_ptr: int,
+                  evec_ptr: int | None = None) -> Result:
+        """ifeast_solve_dev: X0_ptr / evec_ptr are device addresses of n x m0 FP64 row-major
+        blocks (e.g. torch tensors' data_ptr()); the result's evec is None (it is in evec_ptr)."""
+        cs, keep = contour_struct(contour)
+        bufs = _ResultBuffers(A.n, params.m0, params.max_outer, cs.nc, host_evec=False)
+        st = self._check(self.lib.ifeast_solve_dev(self.h, A.h, None if B is None else B.h, C.byref(cs),
+                                                   C.byref(params), C.c_void_p(X0_ptr),
+                                                   None if evec_ptr is None else C.c_void_p(evec_ptr),
+                                                   C.byref(bufs.s)))
+        return bufs.result(st, cs.nc)
+
     def solve(self, A, B, contour: dict, params: ParamsStruct, X0=None) -> Result:
         a, ka = _csr_struct(A)
         b, kb = (None, None) if B is None else _csr_struct(B)
@@ -320,9 +343,7 @@ class Context:
 
     def solve_problem(self, prob, precision=PREC_FP64, resident=None, **overrides) -> Result:
         """Solve a workloads.Problem (matrices uploaded unless given as resident Matrix objects)."""
-        params = _params_from(prob, precision)
-        for k, v in overrides.items():
-            setattr(params, k, v)
+        params = problem_params(prob, precision, **overrides)
         if resident is not None:
             A, B = resident
             return self.solve_resident(A, B, prob.contour, params, prob.x0())

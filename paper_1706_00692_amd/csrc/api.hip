@@ -269,6 +269,21 @@ int ifeast_solve_resident(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_
   });
 }
 
+int ifeast_solve_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour* C,
+                     const ifeast_params* p, const double* X0, double* evec, ifeast_result* res) {
+  return guarded(ctx, [&]() -> int {
+    IF_REQUIRE(ctx != nullptr && A != nullptr && C != nullptr && p != nullptr && res != nullptr && X0 != nullptr,
+               "null argument");
+    IF_REQUIRE(B == nullptr || B->n == A->n, "A and B sizes differ");
+    validate_params(*p, *C, A->n);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, C, p));
+    TimingScope ts(ctx);
+    return eng.solve(A, B, *C, *p, X0, res, true, evec);
+  });
+}
+
 int ifeast_solve(ifeast_ctx* ctx, const ifeast_csr* A, const ifeast_csr* B, const ifeast_contour* C,
                  const ifeast_params* p, const double* X0, ifeast_result* res) {
   ifeast_matrix* Am = nullptr;

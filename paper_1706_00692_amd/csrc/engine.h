@@ -48,8 +48,11 @@ class Engine {
   hipStream_t stream() const { return st_; }
 
   // Full solve; X0 host n x m0 row-major (FP64).  Results written to res.
+  // X0: n x m0 initial block, host memory (NULL: seeded normal block) or, with x0_on_device,
+  // device memory.  evec_dev: device n x m0 output of the eigenvectors (NULL: none), in the
+  // order of the result arrays; res->evec (host) is filled when non-NULL.
   int solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour& C, const ifeast_params& p,
-            const double* X0_host, ifeast_result* res);
+            const double* X0, ifeast_result* res, bool x0_on_device = false, double* evec_dev = nullptr);
 
   // Step entry points on device data (for the step-level ABI).
   void filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour& C, const ifeast_params& p,

@@ -248,6 +248,16 @@ size_t total(const Layout& L) {
 uint64_t workspace_bytes(const Shape& s) { return (uint64_t)total(layout(s)); }
 
 namespace {
+// out[i][j] = X[i][order[j]] (n x m0 row-major): eigenvectors in the result order.
+__global__ void k_gather_cols(int64_t n, int m0, const double* __restrict__ X, const int* __restrict__ order,
+                              double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * m0) return;
+  const int64_t i = idx / m0;
+  const int j = (int)(idx % m0);
+  out[idx] = X[i * m0 + order[j]];
+}
+
 template <class T>
 __global__ void k_scan(const T* __restrict__ p, int64_t count, unsigned int* __restrict__ bad, double* __restrict__ mx) {
   __shared__ double sm[256];
@@ -594,7 +604,9 @@ struct Engine::Impl {
     // E ||U^T w||^2 = ||[V_0..]^T w||^2), so that the estimate reads n x kSketch numbers
     // instead of the whole basis.  reorth_eta >= 1 projects against every block in both passes.
     const bool always = p.reorth_eta >= 1.0;
-    const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? 1e-4 : 1e-12);
+    // default: a quarter of the inner tolerance factor for an FP32 basis (the loss then stays
+    // well below the accuracy the inner solves ask for), near FP64 rounding for an FP64 one
+    const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? std::max(1e-4, 0.25 * p.alpha) : 1e-12);
     reorth_eta = thr;
     // Q = X rho_hat(Lambda); V_0 S0 = R
     launch_scale_cols(st, n, m0, Xd, rhod, Qd);
@@ -655,9 +667,9 @@ struct Engine::Impl {
       gram(plo, pnb);
       project(j, plo, pnb, gred.as<double>(), 1);
       if (full && lo > 0) ++reorth_steps;
-      // the Gram of the projected block: W^T W - C^T C (the second pass removes little, so
-      // this loses nothing to cancellation), else computed afresh
-      if (have_gw)
+      // the Gram of the projected block: after a local second pass W^T W - C^T C (the pass
+      // removes little, so this loses nothing to cancellation), else computed afresh
+      if (have_gw && !full)
         launch_gram_downdate(st, pnb * m0, m0, gred.as<double>(), gwb.as<double>());
       else
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
@@ -951,7 +963,7 @@ void Engine::filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast
 }
 
 int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour& C, const ifeast_params& p,
-                  const double* X0_host, ifeast_result* res) {
+                  const double* X0_in, ifeast_result* res, bool x0_on_device, double* evec_dev) {
   Impl& I = *impl_;
   const int64_t n = shape_.n;
   const int m0 = shape_.m0, ns = shape_.ns;
@@ -967,15 +979,20 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   I.h2d(zb.p, zd.data(), zd.size() * 8);
   I.h2d(wb.p, wd.data(), wd.size() * 8);
   // initial block
-  std::vector<double> x0;
-  if (X0_host == nullptr) {
-    std::mt19937_64 gen(p.seed);
-    std::normal_distribution<double> nrm(0.0, 1.0);
-    x0.resize((size_t)n * m0);
-    for (auto& v : x0) v = nrm(gen);
-    X0_host = x0.data();
+  if (x0_on_device) {
+    IF_HIP(hipMemcpyAsync(I.Q.p, X0_in, (size_t)n * m0 * 8, hipMemcpyDeviceToDevice, st_));
+  } else {
+    std::vector<double> x0;
+    const double* X0_host = X0_in;
+    if (X0_host == nullptr) {
+      std::mt19937_64 gen(p.seed);
+      std::normal_distribution<double> nrm(0.0, 1.0);
+      x0.resize((size_t)n * m0);
+      for (auto& v : x0) v = nrm(gen);
+      X0_host = x0.data();
+    }
+    I.h2d(I.Q.p, X0_host, (size_t)n * m0 * 8);
   }
-  I.h2d(I.Q.p, X0_host, (size_t)n * m0 * 8);
 
   hipEvent_t e0, e1;
   IF_HIP(hipEventCreate(&e0));
@@ -1110,6 +1127,15 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     for (size_t i = 0; i < stats.rf_hist.size(); ++i) res->rf_hist[i] = stats.rf_hist[i];
   if (res->inner_hist)
     for (size_t i = 0; i < stats.inner_hist.size(); ++i) res->inner_hist[i] = stats.inner_hist[i];
+  if (evec_dev) {
+    DevBuf ob(m0 * sizeof(int));
+    I.h2d(ob.p, order.data(), m0 * sizeof(int));
+    const int64_t tot = n * m0;
+    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st_, n, m0, X, ob.as<int>(),
+                       evec_dev);
+    IF_HIP(hipGetLastError());
+    IF_HIP(hipStreamSynchronize(st_));
+  }
   if (res->evec) {
     std::vector<double> xh((size_t)n * m0);
     IF_HIP(hipMemcpyAsync(xh.data(), X, xh.size() * 8, hipMemcpyDeviceToHost, st_));

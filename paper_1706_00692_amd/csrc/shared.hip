@@ -75,13 +75,28 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
 
 // Gram of the block after a projection W2 = W1 - V C with orthonormal V: W2^T W2 =
 // W1^T W1 - C^T C.  gw (m0 x m0) holds W1^T W1 on entry; C has `rows` rows of m0.
-__global__ void k_gram_downdate(int rows, int m0, const double* __restrict__ C, double* __restrict__ gw) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m0 * m0) return;
-  const int a = idx / m0, b = idx % m0;
+// One workgroup per 16 x 16 tile of gw; rows staged through LDS 64 at a time.
+__global__ __launch_bounds__(256) void k_gram_downdate(int rows, int m0, const double* __restrict__ C,
+                                                       double* __restrict__ gw) {
+  __shared__ double ca[64][17], cb[64][17];
+  const int nt = (m0 + 15) / 16;
+  const int ta = blockIdx.x / nt, tb = blockIdx.x % nt;
+  const int a0 = ta * 16, b0 = tb * 16;
+  const int tid = threadIdx.x, ia = tid >> 4, ib = tid & 15;
   double acc = 0.0;
-  for (int r = 0; r < rows; ++r) acc += C[(int64_t)r * m0 + a] * C[(int64_t)r * m0 + b];
-  gw[idx] -= acc;
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    for (int idx = tid; idx < 64 * 16; idx += 256) {
+      const int r = idx >> 4, c = idx & 15;
+      const bool in = r0 + r < rows;
+      ca[r][c] = (in && a0 + c < m0) ? C[(int64_t)(r0 + r) * m0 + a0 + c] : 0.0;
+      cb[r][c] = (in && b0 + c < m0) ? C[(int64_t)(r0 + r) * m0 + b0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < 64; ++r) acc += ca[r][ia] * cb[r][ib];
+    __syncthreads();
+  }
+  if (a0 + ia < m0 && b0 + ib < m0) gw[(a0 + ia) * m0 + b0 + ib] -= acc;
 }
 
 // Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
@@ -158,7 +173,8 @@ void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, c
   IF_HIP(hipGetLastError());
 }
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw) {
-  hipLaunchKernelGGL(k_gram_downdate, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, rows, m0, C, gw);
+  const int nt = (m0 + 15) / 16;
+  hipLaunchKernelGGL(k_gram_downdate, dim3(nt * nt), dim3(256), 0, st, rows, m0, C, gw);
   IF_HIP(hipGetLastError());
 }
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {

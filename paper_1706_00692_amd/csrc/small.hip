@@ -999,7 +999,14 @@ __global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
         if (r < b0) {
           c2 acc = cmk(0.0, 0.0);
           const c2* Hr = v.H + (int64_t)b0 * ldh + r;
-          for (int cl = 0; cl < m0; ++cl) acc = cadd(acc, cmul(Hr[(int64_t)cl * ldh], x[(b0 + cl) % W]));
+          // 16 independent loads in flight per chunk (m0 is a multiple of 16)
+          for (int c0 = 0; c0 < m0; c0 += 16) {
+            c2 hv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) hv[u] = Hr[(int64_t)(c0 + u) * ldh];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = cadd(acc, cmul(hv[u], x[(b0 + c0 + u) % W]));
+          }
           c2& t = x[r % W];
           t = csub(t, acc);
         }
@@ -1088,27 +1095,31 @@ __device__ void jacobi_eig(double* a, int m, double* Vg, double* red, double* Vs
         qq[tid] = q;
       }
       __syncthreads();
-      // A <- A J and V <- V J (columns p, q)
+      // A <- J^T A J: the rotations of a round act on disjoint index pairs, so each 2 x 2
+      // block (rows of pair i1, columns of pair i2) changes with rotations i1 and i2 only
+      // and is updated in place by one thread
+      for (int idx = tid; idx < half * half; idx += nth) {
+        const int i1 = idx / half, i2 = idx % half;
+        const int p1 = pp[i1], q1 = qq[i1], p2 = pp[i2], q2 = qq[i2];
+        const double c1 = cs[i1], s1 = sn[i1], c2 = cs[i2], s2 = sn[i2];
+        const double b00 = a[p1 * m + p2], b01 = a[p1 * m + q2];
+        const double b10 = a[q1 * m + p2], b11 = a[q1 * m + q2];
+        const double x00 = c2 * b00 - s2 * b01, x01 = s2 * b00 + c2 * b01;
+        const double x10 = c2 * b10 - s2 * b11, x11 = s2 * b10 + c2 * b11;
+        a[p1 * m + p2] = c1 * x00 - s1 * x10;
+        a[q1 * m + q2] = s1 * x01 + c1 * x11;
+        // the pair's own entry is annihilated by its rotation
+        a[p1 * m + q2] = i1 == i2 ? 0.0 : c1 * x01 - s1 * x11;
+        a[q1 * m + p2] = i1 == i2 ? 0.0 : s1 * x00 + c1 * x10;
+      }
+      // V <- V J (columns p, q of each pair)
       for (int idx = tid; idx < half * m; idx += nth) {
         const int i = idx / m, r = idx % m;
         const int p = pp[i], q = qq[i];
         const double c = cs[i], sv = sn[i];
-        const double ap = a[r * m + p], aq = a[r * m + q];
-        a[r * m + p] = c * ap - sv * aq;
-        a[r * m + q] = sv * ap + c * aq;
         const double vp = V[r * m + p], vq = V[r * m + q];
         V[r * m + p] = c * vp - sv * vq;
         V[r * m + q] = sv * vp + c * vq;
-      }
-      __syncthreads();
-      // A <- J^T A (rows p, q)
-      for (int idx = tid; idx < half * m; idx += nth) {
-        const int i = idx / m, col = idx % m;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], sv = sn[i];
-        const double ap = a[p * m + col], aq = a[q * m + col];
-        a[p * m + col] = c * ap - sv * aq;
-        a[q * m + col] = sv * ap + c * aq;
       }
       __syncthreads();
     }

@@ -19,7 +19,8 @@ def _lib_or_skip():
 
 def test_header_declares_the_boundary():
     names = pk.exported_symbols()
-    for must in ("ifeast_create", "ifeast_destroy", "ifeast_solve", "ifeast_solve_resident", "ifeast_footprint",
+    for must in ("ifeast_create", "ifeast_destroy", "ifeast_solve", "ifeast_solve_resident", "ifeast_solve_dev",
+                 "ifeast_footprint",
                  "ifeast_submit", "ifeast_poll", "ifeast_wait", "ifeast_spmm_shifted_dev", "ifeast_filter_dev",
                  "ifeast_rayleigh_ritz_dev", "ifeast_matrix_create", "ifeast_status_str", "ifeast_last_error"):
         assert must in names

@@ -423,3 +423,30 @@ def test_serving_alone_vs_mix(ctx):
     with pytest.raises(pk.IFeastError) as e:
         ctx.poll(987654321)
     assert e.value.status == -6
+
+
+def test_solve_dev_matches_host_buffers(ctx, torch_cuda):
+    """ifeast_solve_dev (initial block and eigenvectors in HBM) computes what the host-buffer
+    entry point computes: same pairs, same histories, eigenvectors equal to the last bit."""
+    import paper_1706_00692_amd as pk
+
+    torch = torch_cuda
+    prob = W.config1()
+    Am = ctx.matrix(prob.A)
+    params = pk.problem_params(prob, pk.PREC_MIXED)
+    X0 = prob.x0()
+    ctx.solve_resident(Am, None, prob.contour, params, X0)  # first call of the shape: SpMM autotune
+    rh = ctx.solve_resident(Am, None, prob.contour, params, X0)
+    X0d = torch.from_numpy(X0).cuda()
+    Xd = torch.zeros_like(X0d)
+    rd = ctx.solve_dev(Am, None, prob.contour, params, X0d.data_ptr(), Xd.data_ptr())
+    torch.cuda.synchronize()
+    assert rd.converged and rh.converged
+    assert (rd.m, rd.outer_iters, rd.seq_matvec) == (rh.m, rh.outer_iters, rh.seq_matvec)
+    assert np.array_equal(rd.lam, rh.lam) and np.array_equal(rd.resid, rh.resid)
+    assert np.array_equal(rd.flags, rh.flags)
+    assert rd.X is None
+    assert np.array_equal(Xd.cpu().numpy(), rh.X)
+    # the input block is left as it was
+    assert np.array_equal(X0d.cpu().numpy(), X0)
+    Am.close()

@@ -329,6 +329,7 @@ struct Engine::Impl {
   int* d_single = nullptr;  // ns flags: one Cholesky-QR pass is enough
   int* d_two = nullptr;     // ns flags: two Cholesky-QR passes
   double* d_loss = nullptr; // measured loss of orthogonality of the shared basis' newest block
+  int* d_cnt = nullptr;     // blocks normalised with one Cholesky-QR pass (shared basis)
   double single_gersh = 0.5;
   double dead_thr = 1e-280;
   int64_t single_steps = 0; // shift-steps normalised with one Cholesky-QR pass
@@ -431,6 +432,7 @@ struct Engine::Impl {
     d_two = f + 576;
     d_one = f + 640;
     d_loss = reinterpret_cast<double*>(f + 704);
+    d_cnt = f + 720;
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
     // stale basis blocks of shifts that stopped early are multiplied by zero
@@ -568,6 +570,27 @@ struct Engine::Impl {
     }
   }
 
+  // Two Cholesky-QR passes, the second skipped on the device when the first Gram G0 is
+  // certified well conditioned (then the first pass runs unshifted and is accurate to
+  // about kappa^2 u with kappa <= (1 + g) / (1 - g), g = single_gersh).  The second pass's
+  // GEMMs are left out of the kernel timer (whether they run is known on the device only).
+  template <class T>
+  void cholqr_adaptive_real(const T* src, T* tmp, T* dst, const double* G0) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0;
+    const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
+    launch_gersh_flags(st, m0, G0, single_gersh, dead_thr, d_single, d_two, d_cnt);
+    launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single, 0);
+    ApplyArgs a1{n, m0, m0, 1, 1, 1, src, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
+    launch_apply<T, T>(st, a1);
+    GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two, gred.as<double>(), -1};
+    launch_gram<T>(st, g2, gpart.p, gpart.bytes);
+    launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single, 1);
+    ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two, nullptr, -1};
+    launch_apply<T, T>(st, a2);
+    launch_copy_if<T>(st, d_two, n * m0, tmp, dst);
+  }
+
   // Inner solves of all shifts on one real block Arnoldi of M = -A (B = I):
   //   M V_j = V_{j+1} Hm,  (z_s I - A) V_j = V_{j+1} (z_s I~ + Hm),
   // each shift's least squares min || [S0 D_s; 0] - (z_s I~ + Hm) y_s || updated per step
@@ -608,6 +631,9 @@ struct Engine::Impl {
     // well below the accuracy the inner solves ask for), near FP64 rounding for an FP64 one
     const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? std::max(1e-4, 0.25 * p.alpha) : 1e-12);
     reorth_eta = thr;
+    // one Cholesky-QR pass when the block's Gram certifies kappa <= 3 (orthonormal to ~9 u)
+    single_gersh = 0.5;
+    dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
     // Q = X rho_hat(Lambda); V_0 S0 = R
     launch_scale_cols(st, n, m0, Xd, rhod, Qd);
     launch_to_T<T>(st, bs, Rd, t1);
@@ -637,6 +663,8 @@ struct Engine::Impl {
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
     T* U = Us.as<T>();
     if (!always) launch_fill_zero(st, Us.p, Us.bytes);
+    const int zero_cnt = 0;
+    h2d(d_cnt, &zero_cnt, sizeof(int));
     side_stream();
     int jdone = 0;
     for (int j = 0; j < K; ++j) {
@@ -674,7 +702,10 @@ struct Engine::Impl {
       else
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
       T* dst = Vb + (int64_t)(j + 1) * bs;
-      cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
+      if (always)
+        cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
+      else
+        cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>());
       launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
       // the shifts' least squares updates of step j run on the side stream, beside step
       // j + 1's basis work; their stop flags are read one step later
@@ -702,6 +733,7 @@ struct Engine::Impl {
     IF_HIP(hipEventRecord(ev_lsq[0], st_lsq));
     IF_HIP(hipStreamWaitEvent(st, ev_lsq[0], 0));
     shared_steps = jdone;
+    single_steps += d2h_ints(d_cnt, 1)[0];
     launch_lsq_finish(st, la);
     launch_sum_y<T>(st, ns, m0, K, jdone, y.as<cd>(), wsD.as<double>(), Yq.as<T>());
     ApplyArgs aq{n, m0, m0, 1, jdone, jdone, Vb, m0, 0, 0, bs, Yq.p, 0, Qd, m0, 0, 1.0, 1.0, nullptr, nullptr,

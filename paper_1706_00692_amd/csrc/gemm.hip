@@ -578,7 +578,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     rps = (rps + 31) / 32 * 32;
     const dim3 grid(nsplit, groups, g.ns), block(256);
     T* part = static_cast<T*>(partial);
-    KernelTimer* kt = current_timer();
+    KernelTimer* kt = g.kclass >= 0 ? current_timer() : nullptr;
     const int tok = kt ? kt->begin(st) : -1;
 #define IF_G4(TB_, KC_) hipLaunchKernelGGL((k_gram4<T, TB_, KC_>), grid, block, 0, st, g, nsplit, rps, part)
     if (kc == 32) {
@@ -624,7 +624,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   rps = (rps + KC - 1) / KC * KC;
   const dim3 grid(nsplit, ntp * ntq, items), block(256);
   T* part = static_cast<T*>(partial);
-  KernelTimer* kt = current_timer();
+  KernelTimer* kt = g.kclass >= 0 ? current_timer() : nullptr;
   const int tok = kt ? kt->begin(st) : -1;
   switch (tb) {
     case 1: hipLaunchKernelGGL((k_gram<T, 1>), grid, block, 0, st, g, nsplit, rps, ntq, part); break;
@@ -688,7 +688,7 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   const int nbq = a.OW / 16;
   const int ntq = (nbq + 9) / 10;
   const int tbq = (nbq + ntq - 1) / ntq;
-  KernelTimer* kt = current_timer();
+  KernelTimer* kt = a.kclass >= 0 ? current_timer() : nullptr;
   int tok = -1;
   constexpr int KC0 = ApplyCfg<T>::KC;
   if (sizeof(T) == 4) {

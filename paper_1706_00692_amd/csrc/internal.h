@@ -161,7 +161,7 @@ struct GramArgs {
   int64_t ldb, b_s, b_i;
   const int* active;  // per s, may be null
   double* G;          // ns*ni*PW*QW
-  int kclass = KC_GRAM;  // timing class (KC_GRAM or KC_OUTER)
+  int kclass = KC_GRAM;  // timing class (KC_GRAM or KC_OUTER; < 0: not timed)
 };
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes);
@@ -186,7 +186,7 @@ struct ApplyArgs {
   double alpha, beta;
   const int* active_item;  // per item, may be null
   const int* active_sb;    // per sb, may be null
-  int kclass = KC_UPDATE;  // timing class (KC_UPDATE or KC_QACC)
+  int kclass = KC_UPDATE;  // timing class (KC_UPDATE or KC_QACC; < 0: not timed)
 };
 template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a);
@@ -197,6 +197,18 @@ void launch_apply(hipStream_t st, const ApplyArgs& a);
 //   Cholesky -> Tinv (real-ified, type T, 2m0 x 2m0) and Rf (complex m0 x m0,
 //   W = W_new Rf); if `accumulate`, Racc = Rf * Racc_prev.  real: G is the m0 x m0
 //   Gram of a real block and Tinv real m0 x m0 (Rf then has zero imaginary parts).
+// The blocked real factor (one block, m0 <= 80) steered by a device flag: single[0] != 0
+// makes the first pass (role 0) unshifted and the second (role 1) a no-op.
+template <class T>
+void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shift_rel, T* Tinv, cd* Racc,
+                            int accumulate, const int* single, int role);
+// single[0] / two[0]: one Cholesky-QR pass is enough for the block with Gram G (m0 x m0, real)
+// or not; count[0] (may be null) counts the certified blocks
+void launch_gersh_flags(hipStream_t st, int m0, const double* G, double gersh, double dead_thr, int* single, int* two,
+                        int* count);
+// dst = src (count elements) when flag[0] != 0
+template <class T>
+void launch_copy_if(hipStream_t st, const int* flag, int64_t count, const T* src, T* dst);
 template <class T>
 void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, double shift_rel, const int* active,
                           T* Tinv, cd* Racc, int accumulate, cd* work /*ns x 3 m0^2*/, bool real = false);

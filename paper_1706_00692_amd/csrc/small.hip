@@ -331,7 +331,15 @@ __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __rest
 template <class T>
 __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __restrict__ G, double shift_rel,
                                                      double dead_thr, double tau_dep, T* __restrict__ Tinv,
-                                                     c2* __restrict__ Racc, int accumulate) {
+                                                     c2* __restrict__ Racc, int accumulate,
+                                                     const int* __restrict__ single, int role) {
+  // single[0] != 0 (the Gram is certified well conditioned): the first pass (role 0) runs
+  // unshifted and the second (role 1) is not needed
+  if (single != nullptr && single[0] != 0) {
+    if (role == 1) return;
+    shift_rel = 0.0;
+    tau_dep = 0.25 * m0 * (sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+  }
   constexpr int NB = 16;
   extern __shared__ double lds_d[];
   double* L = lds_d;           // m0 x m0
@@ -1370,7 +1378,7 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
       hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep,
-                         Tinv, reinterpret_cast<c2*>(Racc), accumulate);
+                         Tinv, reinterpret_cast<c2*>(Racc), accumulate, nullptr, 0);
     } else if (real) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T, true>),
@@ -1392,6 +1400,80 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
   }
   IF_HIP(hipGetLastError());
 }
+// Certification of one Cholesky-QR pass for a real block: with the Gram scaled to a unit
+// diagonal, every row's off-diagonal absolute sum <= gersh bounds the condition number by
+// (1 + gersh) / (1 - gersh) (Gershgorin), and no column is below dead_thr.  single[0] /
+// two[0] = certified / not; count[0] += certified.  One workgroup of 128 threads.
+__global__ __launch_bounds__(128) void k_gersh_flags(int m0, const double* __restrict__ G, double gersh,
+                                                     double dead_thr, int* __restrict__ single,
+                                                     int* __restrict__ two, int* __restrict__ count) {
+  __shared__ double dsc[128];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < m0; c += blockDim.x) {
+    const double d = G[c * m0 + c];
+    if (!(d > dead_thr)) bad = 1;
+    dsc[c] = sqrt(fmax(d, 1e-300));
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < m0; r += blockDim.x) {
+    double off = 0.0;
+    for (int c = 0; c < m0; ++c)
+      if (c != r) off += fabs(G[r * m0 + c]) / (dsc[r] * dsc[c]);
+    if (!(off <= gersh)) bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    single[0] = bad ? 0 : 1;
+    two[0] = bad ? 1 : 0;
+    if (count != nullptr) count[0] += bad ? 0 : 1;
+  }
+}
+
+template <class T>
+__global__ void k_copy_if(const int* __restrict__ flag, int64_t count, const T* __restrict__ src,
+                          T* __restrict__ dst) {
+  if (flag[0] == 0) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+template <class T>
+void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shift_rel, T* Tinv, cd* Racc,
+                            int accumulate, const int* single, int role) {
+  IF_REQUIRE(m0 <= 80, "cholqr: m0 > 80 for the blocked real factor");
+  const double dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
+  const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+  const double tau_dep = shift_rel > 0.0 ? 0.5 * shift_rel : 0.25 * m0 * eps;
+  const size_t lds_real = ((size_t)2 * m0 * m0 + 16 * (size_t)m0) * sizeof(double);
+  if (lds_real > 64 * 1024)
+    IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
+  hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep, Tinv,
+                     reinterpret_cast<c2*>(Racc), accumulate, single, role);
+  IF_HIP(hipGetLastError());
+}
+template void launch_cholqr_real_ctl<float>(hipStream_t, int, const double*, double, float*, cd*, int, const int*,
+                                            int);
+template void launch_cholqr_real_ctl<double>(hipStream_t, int, const double*, double, double*, cd*, int,
+                                             const int*, int);
+
+void launch_gersh_flags(hipStream_t st, int m0, const double* G, double gersh, double dead_thr, int* single, int* two,
+                        int* count) {
+  IF_REQUIRE(m0 <= 128, "gershgorin check: m0 > 128");
+  hipLaunchKernelGGL(k_gersh_flags, dim3(1), dim3(128), 0, st, m0, G, gersh, dead_thr, single, two, count);
+  IF_HIP(hipGetLastError());
+}
+
+template <class T>
+void launch_copy_if(hipStream_t st, const int* flag, int64_t count, const T* src, T* dst) {
+  hipLaunchKernelGGL((k_copy_if<T>), dim3(2048), dim3(256), 0, st, flag, count, src, dst);
+  IF_HIP(hipGetLastError());
+}
+template void launch_copy_if<float>(hipStream_t, const int*, int64_t, const float*, float*);
+template void launch_copy_if<double>(hipStream_t, const int*, int64_t, const double*, double*);
+
 template void launch_cholqr_factor<float>(hipStream_t, int, int, const double*, double, const int*, float*, cd*, int,
                                           cd*, bool);
 template void launch_cholqr_factor<double>(hipStream_t, int, int, const double*, double, const int*, double*, cd*,

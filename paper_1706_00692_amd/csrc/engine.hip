@@ -158,6 +158,9 @@ namespace {
 
 // Columns of the random sketch that estimates the shared basis' loss of orthogonality.
 constexpr int kSketch = 16;
+// Kept fraction of a column's norm below which the local projection of a shared-basis step
+// runs twice.
+constexpr double kKeep = 0.5;
 
 struct Layout {
   // byte sizes of every buffer of the workspace
@@ -336,6 +339,7 @@ struct Engine::Impl {
   double reorth_eta = 0.1;  // keep-fraction below which a second pass runs (>= 1: always)
   int64_t reorth_steps = 0; // shift-steps that ran a second pass
   double max_loss = 0.0;     // largest measured loss of orthogonality (shared basis, partial mode)
+  int64_t one_pass_steps = 0;  // shared-basis steps with a single Gram-Schmidt pass
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
 
   // side stream of the shared-basis least squares updates, its events and host flag slots
@@ -675,30 +679,41 @@ struct Engine::Impl {
       gram(lo, nl);
       project(j, lo, nl, gred.as<double>(), 0);
       bool full = always || lo == 0;
+      bool second = true;          // the second Gram-Schmidt pass runs
       const bool have_gw = !full;  // W^T W after the first pass is formed for the estimate
       if (!full) {
         // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
         ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
                      Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
         launch_apply<T, T>(st, au);
-        GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gred.as<double>()};
+        // 16 x 16 tiles: the sketch is read once per tile column, the block once
+        GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gred.as<double>(), KC_GRAM, 1};
         launch_gram<T>(st, gs, gpart.p, gpart.bytes);
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-        launch_sketch_check_real(st, kSketch, m0, gred.as<double>(), gwb.as<double>(), d_loss);
-        double loss = 0.0;
-        IF_HIP(hipMemcpyAsync(&loss, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        launch_sketch_check_real(st, kSketch, m0, gred.as<double>(), gwb.as<double>(), Hm.as<double>(), ldh, j, lo,
+                                 kKeep, d_loss);
+        double chk[2] = {0.0, 0.0};
+        IF_HIP(hipMemcpyAsync(chk, d_loss, sizeof(chk), hipMemcpyDeviceToHost, st));
         IF_HIP(hipStreamSynchronize(st));
-        full = !(loss <= thr);
-        max_loss = std::max(max_loss, loss);
+        full = !(chk[0] <= thr);
+        max_loss = std::max(max_loss, chk[0]);
+        // one local pass leaves components of about u / kept along V_{j-1}, V_j: a second
+        // runs only when some column kept less than kKeep of its norm
+        second = full || chk[1] != 0.0;
       }
       const int plo = full ? 0 : lo, pnb = j + 1 - plo;
-      gram(plo, pnb);
-      project(j, plo, pnb, gred.as<double>(), 1);
+      if (second) {
+        gram(plo, pnb);
+        project(j, plo, pnb, gred.as<double>(), 1);
+      } else {
+        ++one_pass_steps;
+      }
       if (full && lo > 0) ++reorth_steps;
       // the Gram of the projected block: after a local second pass W^T W - C^T C (the pass
       // removes little, so this loses nothing to cancellation), else computed afresh
-      if (have_gw && !full)
-        launch_gram_downdate(st, pnb * m0, m0, gred.as<double>(), gwb.as<double>());
+      if (have_gw && !full) {
+        if (second) launch_gram_downdate(st, pnb * m0, m0, gred.as<double>(), gwb.as<double>());
+      }
       else
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
       T* dst = Vb + (int64_t)(j + 1) * bs;
@@ -1104,9 +1119,10 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         (void)hipEventElapsedTime(&ms_now, e0, en);
         (void)hipEventDestroy(en);
       }
-      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld loss=%.1e t=%.2fs\n",
-              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps, I.max_loss,
-              ms_now * 1e-3);
+      fprintf(stderr,
+              "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld onepass=%lld loss=%.1e t=%.2fs\n",
+              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps,
+              (long long)I.one_pass_steps, I.max_loss, ms_now * 1e-3);
       if (verbose2) {
         std::vector<double> etah(m0), rhoh(m0);
         IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));

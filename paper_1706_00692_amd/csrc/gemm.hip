@@ -615,6 +615,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   // one square tile size for both dimensions
   int tb = std::max(gram_tb(g.PW), gram_tb(g.QW));
   if (g_gram_variant > 0 && tb > g_gram_variant) tb = g_gram_variant;
+  if (g.tb_cap > 0 && tb > g.tb_cap) tb = g.tb_cap;
   const int ntp = (g.PW / 16 + tb - 1) / tb, ntq = (g.QW / 16 + tb - 1) / tb;
   const int items = g.ns * g.ni;
   const int nsplit = gram_nsplit(g.n, items, ntp * ntq, gram_capacity<T>(tb));

@@ -73,8 +73,13 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
     const double v = d > 0.0 ? sqrt(ss / d) : (ss > 0.0 ? INFINITY : 0.0);
     r = (v > r || v != v) ? v : r;
     const double* h = Hm + (int64_t)(j * m0 + b) * ldh;
-    double cc = 0.0;
-    for (int q = lo * m0; q < (j + 1) * m0; ++q) cc += h[q] * h[q];
+    double c8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int q0 = lo * m0, q1 = (j + 1) * m0;  // a multiple of 16 rows
+    for (int q = q0; q < q1; q += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c8[u] += h[q + u] * h[q + u];
+    }
+    const double cc = ((c8[0] + c8[1]) + (c8[2] + c8[3])) + ((c8[4] + c8[5]) + (c8[6] + c8[7]));
     if (!(d >= eta2 * (d + cc))) cancel = 1;
   }
   for (int o = 32; o > 0; o >>= 1) {

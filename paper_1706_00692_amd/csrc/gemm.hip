@@ -194,7 +194,8 @@ __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, con
 // Gram of several blocks of a shift against the same right operand:
 //   G[s, i] = A_{s,i}^T B_s,  i = 4 y .. 4 y + 3,  each (16 TB) x (16 TB).
 // Wave w owns block i = 4 y + w and all TB x TB of its MFMA tiles; the B tile is staged once
-// for the four waves, so B is read once per four blocks instead of once per block.
+// for the four waves, so B is read once per four blocks instead of once per block.  A group of
+// two blocks gives each block 2 waves, splitting its 16-row tile blocks.
 // grid: x = row split, y = group of four blocks, z = shift.
 template <class T, int TB, int KC>
 __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_t rows_per_split, T* __restrict__ partial) {
@@ -217,6 +218,11 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
   const T* __restrict__ B = static_cast<const T*>(g.B) + s * g.b_s;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
+  // waves per block: with fewer than four blocks in the group, several waves share a block,
+  // each taking a range [ra0, ra1) of its 16-row tile blocks
+  const int wpb = nil >= 3 ? 1 : 4 / nil;
+  const int q = wave / wpb, part = wave % wpb;
+  const int ra0 = part * TB / wpb, ra1 = (part + 1) * TB / wpb;
   typename Mfma<T>::acc acc[TB][TB];
 #pragma unroll
   for (int a = 0; a < TB; ++a)
@@ -250,31 +256,35 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
     }
     __syncthreads();
     if (rc + KC < r1) fetch(rc + KC);
-    if (wave < nil) {
+    if (q < nil) {
 #pragma unroll
       for (int kk = 0; kk < KC; kk += 4) {
         T af[TB], bf[TB];
 #pragma unroll
-        for (int a = 0; a < TB; ++a) af[a] = sA[wave][(kk + lk) * LD + a * 16 + li];
+        for (int a = 0; a < TB; ++a) af[a] = (a >= ra0 && a < ra1) ? sA[q][(kk + lk) * LD + a * 16 + li] : T(0);
 #pragma unroll
         for (int b = 0; b < TB; ++b) bf[b] = sB[(kk + lk) * LD + b * 16 + li];
 #pragma unroll
         for (int a = 0; a < TB; ++a)
+          if (a >= ra0 && a < ra1) {
 #pragma unroll
-          for (int b = 0; b < TB; ++b) acc[a][b] = Mfma<T>::mma(af[a], bf[b], acc[a][b]);
+            for (int b = 0; b < TB; ++b) acc[a][b] = Mfma<T>::mma(af[a], bf[b], acc[a][b]);
+          }
       }
     }
     __syncthreads();
   }
-  if (wave >= nil) return;
-  const int item = s * g.ni + i0 + wave;
+  if (q >= nil) return;
+  const int item = s * g.ni + i0 + q;
   T* out = partial + ((int64_t)item * nsplit + split) * TP * TP;
 #pragma unroll
   for (int a = 0; a < TB; ++a)
+    if (a >= ra0 && a < ra1) {
 #pragma unroll
-    for (int b = 0; b < TB; ++b)
+      for (int b = 0; b < TB; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(int64_t)(a * 16 + Mfma<T>::row(lk, v)) * TP + b * 16 + li] = acc[a][b][v];
+        for (int v = 0; v < 4; ++v) out[(int64_t)(a * 16 + Mfma<T>::row(lk, v)) * TP + b * 16 + li] = acc[a][b][v];
+    }
 }
 
 inline int gram_tb(int W) {
@@ -291,11 +301,13 @@ int gram_capacity(int tb);
 // Row splits per (item, tile): enough workgroups to fill the device twice, and a total that
 // does not exceed two full waves of resident workgroups (a third, nearly empty wave would
 // cost as much as a full one).  At least 1024 rows per split.
-inline int gram_nsplit(int64_t n, int items, int tiles, int cap) {
+// min_rows: smallest row range of one split (1024; 512 for the four-block kernel and for one
+// or two tiles, which otherwise leave too few workgroups in flight: measured on the device).
+inline int gram_nsplit(int64_t n, int items, int tiles, int cap, int64_t min_rows = 1024) {
   const int64_t per = (int64_t)items * tiles;
   const int64_t target = 2 * (int64_t)std::max(cap, 1);
   const int64_t want = std::max<int64_t>(1, target / per);
-  const int64_t maxs = std::max<int64_t>(1, n / 1024);
+  const int64_t maxs = std::max<int64_t>(1, n / min_rows);
   return (int)std::min(want, maxs);
 }
 
@@ -551,13 +563,13 @@ size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
   size_t best = 0;
   if (PW == QW && PW % 16 == 0 && PW <= (sizeof(T) == 4 ? 80 : 64) && items >= 2) {
     const int groups = (items + 3) / 4;
-    const int ns = gram_nsplit(n, groups, 1, gram4_capacity<T>(PW / 16));
+    const int ns = gram_nsplit(n, groups, 1, gram4_capacity<T>(PW / 16), 512);
     best = (size_t)items * ns * PW * QW * sizeof(T);
   }
   const int tb0 = std::max(gram_tb(PW), gram_tb(QW));
   for (int tb = 1; tb <= tb0; ++tb) {
     const int tiles = ((PW / 16 + tb - 1) / tb) * ((QW / 16 + tb - 1) / tb);
-    const int ns = gram_nsplit(n, items, tiles, gram_capacity<T>(tb));
+    const int ns = gram_nsplit(n, items, tiles, gram_capacity<T>(tb), items * tiles <= 2 ? 512 : 1024);
     best = std::max(best, (size_t)items * ns * PW * QW * sizeof(T));
   }
   return best;
@@ -570,7 +582,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     const int tb = g.PW / 16;
     const int groups = (g.ni + 3) / 4;
     const int items = g.ns * g.ni;
-    const int nsplit = gram_nsplit(g.n, g.ns * groups, 1, gram4_capacity<T>(tb));
+    const int nsplit = gram_nsplit(g.n, g.ns * groups, 1, gram4_capacity<T>(tb), 512);
     IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
     // K chunk (rows per staged tile): 32 (measured fastest, two waves per SIMD still fit) or 16
     const int kc = g_gram4_kc == 16 ? 16 : 32;
@@ -603,8 +615,9 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     if (kt) {
       const int nact = kt->count(g.active, g.ns);
       const double eff = (double)nact * g.ni;
-      kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff,
-              (double)g.n * g.PW * sizeof(T) * eff + (double)g.n * g.QW * sizeof(T) * nact);
+      // the self Gram (A == B, one block) reads one block
+      const double rb = (g.A == g.B && g.ni == 1) ? 0.0 : (double)g.n * g.QW * sizeof(T) * nact;
+      kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, (double)g.n * g.PW * sizeof(T) * eff + rb);
     }
     const int64_t total = (int64_t)items * g.PW * g.QW * 8;
     hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
@@ -618,7 +631,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   if (g.tb_cap > 0 && tb > g.tb_cap) tb = g.tb_cap;
   const int ntp = (g.PW / 16 + tb - 1) / tb, ntq = (g.QW / 16 + tb - 1) / tb;
   const int items = g.ns * g.ni;
-  const int nsplit = gram_nsplit(g.n, items, ntp * ntq, gram_capacity<T>(tb));
+  const int nsplit = gram_nsplit(g.n, items, ntp * ntq, gram_capacity<T>(tb), items * ntp * ntq <= 2 ? 512 : 1024);
   IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
   constexpr int KC = GramCfg<T>::KC;
   int64_t rps = (g.n + nsplit - 1) / nsplit;

@@ -1138,6 +1138,195 @@ __device__ void jacobi_eig(double* a, int m, double* Vg, double* red, double* Vs
   }
 }
 
+// Symmetric eigen-decomposition by Householder tridiagonalisation and the implicit QL
+// iteration with Wilkinson-type shifts (Bowdler, Martin, Reinsch & Wilkinson, 1968), in one
+// workgroup.  a (LDS, m x m, symmetric, m <= 128) is overwritten: on return its diagonal holds
+// the eigenvalues and the rest is zero; Vg (global, m x m row-major) holds the eigenvectors as
+// columns.  Hv: LDS scratch m x m.  save: global scratch m x m (a copy of the input, for the
+// cyclic Jacobi fallback when an eigenvalue needs more than 60 QL sweeps).
+// One thread runs each QL sweep's scalar recurrence and stores its rotations; every thread
+// then applies them, in order, to its rows of the eigenvector matrix (rotation buffers alternate
+// between sweeps, so one barrier per sweep).
+__device__ void sym_eig_ql(double* a, int m, double* Vg, double* red, double* Hv, double* save) {
+  __shared__ double dd[128], ee[128], bet[128], pv[128];
+  __shared__ double cr[2][128], sr[2][128];
+  __shared__ int sw_lo[2], sw_hi[2], sw_n[2];
+  __shared__ int ql_l, ql_iter, ql_fail;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int idx = tid; idx < m * m; idx += nth) save[idx] = a[idx];
+  // ---- 1. tridiagonalisation, H_k = I - bet_k v v^T with v in row k of Hv (entries k+1 ..)
+  for (int k = 0; k + 2 < m; ++k) {
+    const int n1 = k + 1;
+    double x = 0.0;
+    for (int r = n1 + tid; r < m; r += nth) x += a[r * m + k] * a[r * m + k];
+    const double sigma = block_sum(x, red);
+    const double x0 = a[n1 * m + k];
+    const double alpha = x0 >= 0.0 ? -sqrt(sigma) : sqrt(sigma);
+    const double v0 = x0 - alpha;
+    const double vn2 = sigma - x0 * x0 + v0 * v0;
+    const double b = (sigma > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+    for (int r = n1 + tid; r < m; r += nth) Hv[k * m + r] = (r == n1) ? v0 : a[r * m + k];
+    if (tid == 0) {
+      bet[k] = b;
+      dd[k] = a[k * m + k];
+      ee[k] = b != 0.0 ? alpha : x0;
+    }
+    __syncthreads();
+    if (b != 0.0) {
+      // pv = b A v on rows n1.., eight lanes per row
+      {
+        const int r = n1 + (tid >> 3), part = tid & 7;
+        double acc = 0.0;
+        if (r < m)
+          for (int c = n1 + part; c < m; c += 8) acc += a[r * m + c] * Hv[k * m + c];
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 4);
+        if (r < m && part == 0) pv[r] = b * acc;
+      }
+      __syncthreads();
+      double t = 0.0;
+      for (int r = n1 + tid; r < m; r += nth) t += Hv[k * m + r] * pv[r];
+      const double K = 0.5 * b * block_sum(t, red);
+      // A <- A - v w^T - w v^T with w = pv - K v, on rows and columns n1..
+      const int nk = m - n1;
+      for (int idx = tid; idx < nk * nk; idx += nth) {
+        const int r = n1 + idx / nk, c = n1 + idx % nk;
+        const double vr = Hv[k * m + r], vc = Hv[k * m + c];
+        const double wr = pv[r] - K * vr, wc = pv[c] - K * vc;
+        a[r * m + c] -= vr * wc + wr * vc;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    if (m >= 2) {
+      dd[m - 2] = a[(m - 2) * m + m - 2];
+      ee[m - 2] = a[(m - 1) * m + m - 2];
+      bet[m - 2] = 0.0;
+    }
+    dd[m - 1] = a[(m - 1) * m + m - 1];
+    ee[m - 1] = 0.0;
+    bet[m - 1] = 0.0;
+  }
+  __syncthreads();
+  // ---- 2. Q = H_0 H_1 ... (backward accumulation into a)
+  for (int idx = tid; idx < m * m; idx += nth) a[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = m - 3; k >= 0; --k) {
+    const double b = bet[k];
+    if (b == 0.0) continue;
+    const int n1 = k + 1, nk = m - n1;
+    {
+      const int c = n1 + (tid >> 3), part = tid & 7;
+      double acc = 0.0;
+      if (c < m)
+        for (int r = n1 + part; r < m; r += 8) acc += Hv[k * m + r] * a[r * m + c];
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      if (c < m && part == 0) pv[c] = b * acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nk * nk; idx += nth) {
+      const int r = n1 + idx / nk, c = n1 + idx % nk;
+      a[r * m + c] -= Hv[k * m + r] * pv[c];
+    }
+    __syncthreads();
+  }
+  // ---- 3. implicit QL on (dd, ee), rotations applied to the rows of a
+  if (tid == 0) {
+    ql_l = 0;
+    ql_iter = 0;
+    ql_fail = 0;
+  }
+  __syncthreads();
+  for (int buf = 0;; buf ^= 1) {
+    if (tid == 0) {
+      int l = ql_l, nrot = 0;
+      while (l < m) {
+        int mx = l;
+        for (; mx < m - 1; ++mx) {
+          const double ds = fabs(dd[mx]) + fabs(dd[mx + 1]);
+          if (fabs(ee[mx]) <= 2.220446049250313e-16 * ds) break;
+        }
+        if (mx == l) {
+          ++l;
+          ql_iter = 0;
+          continue;
+        }
+        if (++ql_iter > 60) {
+          ql_fail = 1;
+          l = m;
+          break;
+        }
+        double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
+        double r = hypot(g, 1.0);
+        g = dd[mx] - dd[l] + ee[l] / (g + (g >= 0.0 ? r : -r));
+        double sv = 1.0, c = 1.0, p = 0.0;
+        int i = mx - 1;
+        bool cut = false;
+        for (; i >= l; --i) {
+          const double f = sv * ee[i], bb = c * ee[i];
+          r = hypot(f, g);
+          ee[i + 1] = r;
+          if (r == 0.0) {
+            dd[i + 1] -= p;
+            ee[mx] = 0.0;
+            cut = true;
+            break;
+          }
+          sv = f / r;
+          c = g / r;
+          g = dd[i + 1] - p;
+          r = (dd[i] - g) * sv + 2.0 * c * bb;
+          p = sv * r;
+          dd[i + 1] = g + p;
+          g = c * r - bb;
+          cr[buf][i] = c;
+          sr[buf][i] = sv;
+        }
+        if (!cut) {
+          dd[l] -= p;
+          ee[l] = g;
+          ee[mx] = 0.0;
+        }
+        sw_hi[buf] = mx - 1;
+        sw_lo[buf] = cut ? i + 1 : l;
+        nrot = sw_hi[buf] - sw_lo[buf] + 1;
+        if (nrot > 0) break;  // a sweep cut at its first rotation changed no vector: go on
+      }
+      ql_l = l;
+      sw_n[buf] = l < m ? nrot : 0;
+      if (l >= m) sw_n[buf] = 0;
+    }
+    __syncthreads();
+    const int nrot = sw_n[buf];
+    if (nrot <= 0) break;
+    const int hi = sw_hi[buf], lo = sw_lo[buf];
+    for (int r = tid; r < m; r += nth) {
+      double* z = a + r * m;
+      for (int i = hi; i >= lo; --i) {
+        const double c = cr[buf][i], sv = sr[buf][i];
+        const double f = z[i + 1];
+        z[i + 1] = sv * z[i] + c * f;
+        z[i] = c * z[i] - sv * f;
+      }
+    }
+  }
+  __syncthreads();
+  if (ql_fail) {
+    for (int idx = tid; idx < m * m; idx += nth) a[idx] = save[idx];
+    __syncthreads();
+    jacobi_eig(a, m, Vg, red, Hv);
+    return;
+  }
+  for (int idx = tid; idx < m * m; idx += nth) Vg[idx] = a[idx];
+  __syncthreads();
+  for (int idx = tid; idx < m * m; idx += nth) a[idx] = (idx / m == idx % m) ? dd[idx / m] : 0.0;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restrict__ GA, const double* __restrict__ GB,
                                                   double* __restrict__ lam, double* __restrict__ C,
                                                   double* __restrict__ eta, double* __restrict__ work,
@@ -1162,7 +1351,10 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
     sm[idx] = 0.5 * (GB[r * m0 + c] + GB[c * m0 + r]) * dsc[r] * dsc[c];
   }
   __syncthreads();
-  jacobi_eig(sm, m0, U, red, v_in_lds ? sm + mm : nullptr);
+  if (v_in_lds)
+    sym_eig_ql(sm, m0, U, red, sm + mm, W);
+  else
+    jacobi_eig(sm, m0, U, red, nullptr);
   // 2. floor tiny eigenvalues (SVQB), T = D U Theta^{-1/2}
   double tmax = 0.0;
   for (int a = tid; a < m0; a += blockDim.x) tmax = fmax(tmax, sm[a * m0 + a]);
@@ -1194,7 +1386,10 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
     sm[idx] = 0.5 * (Ar[r * m0 + c] + Ar[c * m0 + r]);
   }
   __syncthreads();
-  jacobi_eig(sm, m0, W, red, v_in_lds ? sm + mm : nullptr);
+  if (v_in_lds)
+    sym_eig_ql(sm, m0, W, red, sm + mm, U);
+  else
+    jacobi_eig(sm, m0, W, red, nullptr);
   // 4. ascending order, C = T W(:, order), eta = 1/||c_l||
   if (tid == 0) {
     for (int i = 0; i < m0; ++i) order[i] = i;

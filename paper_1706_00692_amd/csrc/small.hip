@@ -1327,6 +1327,9 @@ __device__ void sym_eig_ql(double* a, int m, double* Vg, double* red, double* Hv
   __syncthreads();
 }
 
+// Outputs of an m0 x m0 product per thread of the 1024-thread Rayleigh-Ritz kernel (m0 <= 128).
+constexpr int kRrPer = 16;
+
 __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restrict__ GA, const double* __restrict__ GB,
                                                   double* __restrict__ lam, double* __restrict__ C,
                                                   double* __restrict__ eta, double* __restrict__ work,
@@ -1367,30 +1370,81 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
   }
   __syncthreads();
   // 3. Ar = T^T GA T (symmetrised), via W = GA T
-  for (int idx = tid; idx < mm; idx += blockDim.x) {
-    const int r = idx / m0, c = idx % m0;
-    double sum = 0.0;
-    for (int e = 0; e < m0; ++e) sum += 0.5 * (GA[r * m0 + e] + GA[e * m0 + r]) * Tm[e * m0 + c];
-    W[idx] = sum;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < mm; idx += blockDim.x) {
-    const int r = idx / m0, c = idx % m0;
-    double sum = 0.0;
-    for (int e = 0; e < m0; ++e) sum += Tm[e * m0 + r] * W[e * m0 + c];
-    Ar[idx] = sum;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < mm; idx += blockDim.x) {
-    const int r = idx / m0, c = idx % m0;
-    sm[idx] = 0.5 * (Ar[r * m0 + c] + Ar[c * m0 + r]);
-  }
-  __syncthreads();
-  if (v_in_lds)
+  if (v_in_lds) {
+    // products from LDS: sa = sym(GA), sb = T; then sa = W, sb = Ar
+    double* sa = sm;
+    double* sb = sm + mm;
+    for (int idx = tid; idx < mm; idx += blockDim.x) {
+      const int r = idx / m0, c = idx % m0;
+      sa[idx] = 0.5 * (GA[r * m0 + c] + GA[c * m0 + r]);
+      sb[idx] = Tm[idx];
+    }
+    __syncthreads();
+    double acc[kRrPer];
+#pragma unroll
+    for (int t = 0; t < kRrPer; ++t) {
+      const int idx = tid + t * (int)blockDim.x;
+      double sum = 0.0;
+      if (idx < mm) {
+        const int r = idx / m0, c = idx % m0;
+        for (int e = 0; e < m0; ++e) sum += sa[r * m0 + e] * sb[e * m0 + c];
+      }
+      acc[t] = sum;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kRrPer; ++t) {
+      const int idx = tid + t * (int)blockDim.x;
+      if (idx < mm) sa[idx] = acc[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kRrPer; ++t) {
+      const int idx = tid + t * (int)blockDim.x;
+      double sum = 0.0;
+      if (idx < mm) {
+        const int r = idx / m0, c = idx % m0;
+        for (int e = 0; e < m0; ++e) sum += sb[e * m0 + r] * sa[e * m0 + c];
+      }
+      acc[t] = sum;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kRrPer; ++t) {
+      const int idx = tid + t * (int)blockDim.x;
+      if (idx < mm) sb[idx] = acc[t];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < mm; idx += blockDim.x) {
+      const int r = idx / m0, c = idx % m0;
+      sa[idx] = 0.5 * (sb[r * m0 + c] + sb[c * m0 + r]);
+    }
+    __syncthreads();
     sym_eig_ql(sm, m0, W, red, sm + mm, U);
-  else
+  } else {
+    for (int idx = tid; idx < mm; idx += blockDim.x) {
+      const int r = idx / m0, c = idx % m0;
+      double sum = 0.0;
+      for (int e = 0; e < m0; ++e) sum += 0.5 * (GA[r * m0 + e] + GA[e * m0 + r]) * Tm[e * m0 + c];
+      W[idx] = sum;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < mm; idx += blockDim.x) {
+      const int r = idx / m0, c = idx % m0;
+      double sum = 0.0;
+      for (int e = 0; e < m0; ++e) sum += Tm[e * m0 + r] * W[e * m0 + c];
+      Ar[idx] = sum;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < mm; idx += blockDim.x) {
+      const int r = idx / m0, c = idx % m0;
+      sm[idx] = 0.5 * (Ar[r * m0 + c] + Ar[c * m0 + r]);
+    }
+    __syncthreads();
     jacobi_eig(sm, m0, W, red, nullptr);
+  }
   // 4. ascending order, C = T W(:, order), eta = 1/||c_l||
+  __shared__ double evs[128];
   if (tid == 0) {
     for (int i = 0; i < m0; ++i) order[i] = i;
     for (int i = 1; i < m0; ++i) {  // insertion sort on the diagonal
@@ -1403,8 +1457,44 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
       }
       order[k + 1] = oi;
     }
+    for (int i = 0; i < m0; ++i) evs[i] = sm[order[i] * m0 + order[i]];
   }
   __syncthreads();
+  if (v_in_lds) {
+    double* sa = sm;
+    double* sb = sm + mm;
+    for (int idx = tid; idx < mm; idx += blockDim.x) {
+      sa[idx] = Tm[idx];
+      sb[idx] = W[idx];
+    }
+    __syncthreads();
+    double acc[kRrPer];
+#pragma unroll
+    for (int t = 0; t < kRrPer; ++t) {
+      const int idx = tid + t * (int)blockDim.x;
+      double sum = 0.0;
+      if (idx < mm) {
+        const int r = idx / m0, oc = order[idx % m0];
+        for (int e = 0; e < m0; ++e) sum += sa[r * m0 + e] * sb[e * m0 + oc];
+        C[idx] = sum;
+      }
+      acc[t] = sum;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kRrPer; ++t) {
+      const int idx = tid + t * (int)blockDim.x;
+      if (idx < mm) sa[idx] = acc[t];
+    }
+    __syncthreads();
+    for (int c = tid; c < m0; c += blockDim.x) {
+      lam[c] = evs[c];
+      double ss = 0.0;
+      for (int r = 0; r < m0; ++r) ss += sa[r * m0 + c] * sa[r * m0 + c];
+      eta[c] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+    }
+    return;
+  }
   for (int idx = tid; idx < mm; idx += blockDim.x) {
     const int r = idx / m0, c = idx % m0;
     const int oc = order[c];
@@ -1414,7 +1504,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
   }
   __syncthreads();
   for (int c = tid; c < m0; c += blockDim.x) {
-    lam[c] = sm[order[c] * m0 + order[c]];
+    lam[c] = evs[c];
     double ss = 0.0;
     for (int r = 0; r < m0; ++r) ss += C[r * m0 + c] * C[r * m0 + c];
     eta[c] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
@@ -1793,7 +1883,7 @@ void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB,
   }
   size_t lds = (size_t)m0 * m0 * sizeof(double);
   // the Jacobi rotations accumulate in LDS too when both matrices fit
-  const int v_in_lds = (int64_t)(2 * lds) + 4096 <= (int64_t)max_lds ? 1 : 0;
+  const int v_in_lds = (int64_t)(2 * lds) + 16384 <= (int64_t)max_lds ? 1 : 0;
   if (v_in_lds) lds *= 2;
   if (lds > 64 * 1024)
     IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rr_small), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -17,6 +17,23 @@
 //  * classify: membership, filter-gain test and ||R_F|| (Algorithm 2, step 4).
 #include "internal.h"
 
+// Phase timestamps of the Rayleigh-Ritz kernel, compiled in only for profiling builds.
+#ifdef IFEAST_RR_PROFILE
+__device__ unsigned long long ifeast_rr_prof[16];
+extern "C" void ifeast_rr_prof_read(unsigned long long* out) {
+  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(ifeast_rr_prof), 16 * sizeof(unsigned long long));
+}
+#define RR_MARK(i)                                                \
+  do {                                                            \
+    __syncthreads();                                              \
+    if (threadIdx.x == 0) ::ifeast_rr_prof[i] = wall_clock64();   \
+  } while (0)
+#else
+#define RR_MARK(i) \
+  do {             \
+  } while (0)
+#endif
+
 #include <cstdlib>
 
 namespace ifeast {
@@ -1151,9 +1168,13 @@ __device__ void sym_eig_ql(double* a, int m, double* Vg, double* red, double* Hv
   __shared__ double dd[128], ee[128], bet[128], pv[128];
   __shared__ double cr[2][128], sr[2][128];
   __shared__ int sw_lo[2], sw_hi[2], sw_n[2];
-  __shared__ int ql_l, ql_iter, ql_fail;
+  __shared__ int ql_fail;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int idx = tid; idx < m * m; idx += nth) save[idx] = a[idx];
+  RR_MARK(6);
+#ifdef IFEAST_RR_PROFILE
+  if (tid == 0) ::ifeast_rr_prof[10] = ::ifeast_rr_prof[11] = 0;
+#endif
   // ---- 1. tridiagonalisation, H_k = I - bet_k v v^T with v in row k of Hv (entries k+1 ..)
   for (int k = 0; k + 2 < m; ++k) {
     const int n1 = k + 1;
@@ -1211,6 +1232,7 @@ __device__ void sym_eig_ql(double* a, int m, double* Vg, double* red, double* Hv
   }
   __syncthreads();
   // ---- 2. Q = H_0 H_1 ... (backward accumulation into a)
+  RR_MARK(7);
   for (int idx = tid; idx < m * m; idx += nth) a[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
   __syncthreads();
   for (int k = m - 3; k >= 0; --k) {
@@ -1234,29 +1256,43 @@ __device__ void sym_eig_ql(double* a, int m, double* Vg, double* red, double* Hv
     }
     __syncthreads();
   }
-  // ---- 3. implicit QL on (dd, ee), rotations applied to the rows of a
-  if (tid == 0) {
-    ql_l = 0;
-    ql_iter = 0;
-    ql_fail = 0;
-  }
+  // ---- 3. implicit QL on (dd, ee): wave 0 runs each sweep's recurrence (the same values in
+  // all its lanes; lane 0 stores), the other waves apply the sweep's rotations to their rows
+  // of a while wave 0 computes the next sweep
+  RR_MARK(8);
+#ifdef IFEAST_RR_PROFILE
+  if (tid == 0) ::ifeast_rr_prof[10] = ::ifeast_rr_prof[11] = 0;
+#endif
+  if (tid == 0) ql_fail = 0;
   __syncthreads();
-  for (int buf = 0;; buf ^= 1) {
-    if (tid == 0) {
-      int l = ql_l, nrot = 0;
+  const int wave = tid >> 6, lane = tid & 63;
+  if (wave == 0) {
+    int l = 0, iter = 0, buf = 0;
+    while (true) {
+      int nrot = 0, hi = 0, lo = 0;
       while (l < m) {
-        int mx = l;
-        for (; mx < m - 1; ++mx) {
-          const double ds = fabs(dd[mx]) + fabs(dd[mx + 1]);
-          if (fabs(ee[mx]) <= 2.220446049250313e-16 * ds) break;
+        // first mx >= l whose subdiagonal entry is negligible (mx = m - 1 if none)
+        int mx = m - 1;
+        for (int base = 0; base < m - 1; base += 64) {
+          const int idx = base + lane;
+          bool neg = false;
+          if (idx >= l && idx < m - 1) {
+            const double ds = fabs(dd[idx]) + fabs(dd[idx + 1]);
+            neg = fabs(ee[idx]) <= 2.220446049250313e-16 * ds;
+          }
+          const unsigned long long bal = __ballot(neg);
+          if (bal != 0ull) {
+            mx = base + __ffsll((long long)bal) - 1;
+            break;
+          }
         }
         if (mx == l) {
           ++l;
-          ql_iter = 0;
+          iter = 0;
           continue;
         }
-        if (++ql_iter > 60) {
-          ql_fail = 1;
+        if (++iter > 60) {
+          if (lane == 0) ql_fail = 1;
           l = m;
           break;
         }
@@ -1266,54 +1302,88 @@ __device__ void sym_eig_ql(double* a, int m, double* Vg, double* red, double* Hv
         double sv = 1.0, c = 1.0, p = 0.0;
         int i = mx - 1;
         bool cut = false;
+        // the sweep reads only entries it has not written yet: load them one step ahead.
+        // r and 1/r from the hardware reciprocal square root with two Newton steps
+        double e_i = ee[i], d_i = dd[i], d_i1 = dd[i + 1];
         for (; i >= l; --i) {
-          const double f = sv * ee[i], bb = c * ee[i];
-          r = hypot(f, g);
-          ee[i + 1] = r;
-          if (r == 0.0) {
-            dd[i + 1] -= p;
-            ee[mx] = 0.0;
+          const double e_n = i > l ? ee[i - 1] : 0.0, d_n = i > l ? dd[i - 1] : 0.0;
+          const double f = sv * e_i, bb = c * e_i;
+          const double r2 = f * f + g * g;
+          if (r2 == 0.0) {
+            if (lane == 0) {
+              ee[i + 1] = 0.0;
+              dd[i + 1] = d_i1 - p;
+              ee[mx] = 0.0;
+            }
             cut = true;
             break;
           }
-          sv = f / r;
-          c = g / r;
-          g = dd[i + 1] - p;
-          r = (dd[i] - g) * sv + 2.0 * c * bb;
-          p = sv * r;
-          dd[i + 1] = g + p;
-          g = c * r - bb;
-          cr[buf][i] = c;
-          sr[buf][i] = sv;
+          double rs = __builtin_amdgcn_rsq(r2);
+          rs = rs * (1.5 - 0.5 * r2 * rs * rs);
+          rs = rs * (1.5 - 0.5 * r2 * rs * rs);
+          sv = f * rs;
+          c = g * rs;
+          g = d_i1 - p;
+          const double t = (d_i - g) * sv + 2.0 * c * bb;
+          p = sv * t;
+          if (lane == 0) {
+            ee[i + 1] = r2 * rs;
+            dd[i + 1] = g + p;
+            cr[buf][i] = c;
+            sr[buf][i] = sv;
+          }
+          g = c * t - bb;
+          d_i1 = d_i;
+          e_i = e_n;
+          d_i = d_n;
         }
-        if (!cut) {
+        if (!cut && lane == 0) {
           dd[l] -= p;
           ee[l] = g;
           ee[mx] = 0.0;
         }
-        sw_hi[buf] = mx - 1;
-        sw_lo[buf] = cut ? i + 1 : l;
-        nrot = sw_hi[buf] - sw_lo[buf] + 1;
+        hi = mx - 1;
+        lo = cut ? i + 1 : l;
+        nrot = hi - lo + 1;
         if (nrot > 0) break;  // a sweep cut at its first rotation changed no vector: go on
       }
-      ql_l = l;
-      sw_n[buf] = l < m ? nrot : 0;
-      if (l >= m) sw_n[buf] = 0;
+      if (l >= m) nrot = 0;
+#ifdef IFEAST_RR_PROFILE
+      if (lane == 0) {
+        ::ifeast_rr_prof[10] += 1;
+        ::ifeast_rr_prof[11] += nrot;
+      }
+#endif
+      if (lane == 0) {
+        sw_hi[buf] = hi;
+        sw_lo[buf] = lo;
+        sw_n[buf] = nrot;
+      }
+      __syncthreads();
+      if (nrot <= 0) break;
+      buf ^= 1;
     }
-    __syncthreads();
-    const int nrot = sw_n[buf];
-    if (nrot <= 0) break;
-    const int hi = sw_hi[buf], lo = sw_lo[buf];
-    for (int r = tid; r < m; r += nth) {
-      double* z = a + r * m;
-      for (int i = hi; i >= lo; --i) {
-        const double c = cr[buf][i], sv = sr[buf][i];
-        const double f = z[i + 1];
-        z[i + 1] = sv * z[i] + c * f;
-        z[i] = c * z[i] - sv * f;
+  } else {
+    for (int buf = 0;; buf ^= 1) {
+      __syncthreads();
+      const int nrot = sw_n[buf];
+      if (nrot <= 0) break;
+      const int hi = sw_hi[buf], lo = sw_lo[buf];
+      for (int r = tid - 64; r < m; r += nth - 64) {
+        // rotation i changes z[i] and z[i + 1]; z[i] then feeds rotation i - 1: carried in a register
+        double* z = a + r * m;
+        double up = z[hi + 1];
+        for (int i = hi; i >= lo; --i) {
+          const double c = cr[buf][i], sv = sr[buf][i];
+          const double zi = z[i];
+          z[i + 1] = sv * zi + c * up;
+          up = c * zi - sv * up;
+        }
+        z[lo] = up;
       }
     }
   }
+  RR_MARK(9);
   __syncthreads();
   if (ql_fail) {
     for (int idx = tid; idx < m * m; idx += nth) a[idx] = save[idx];
@@ -1343,6 +1413,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
   double* Tm = work + mm;
   double* W = work + 2 * mm;
   double* Ar = work + 3 * mm;
+  RR_MARK(0);
   // 1. scaled, symmetrised B-Gram
   for (int a = tid; a < m0; a += blockDim.x) {
     const double d = GB[a * m0 + a];
@@ -1358,6 +1429,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
     sym_eig_ql(sm, m0, U, red, sm + mm, W);
   else
     jacobi_eig(sm, m0, U, red, nullptr);
+  RR_MARK(1);
   // 2. floor tiny eigenvalues (SVQB), T = D U Theta^{-1/2}
   double tmax = 0.0;
   for (int a = tid; a < m0; a += blockDim.x) tmax = fmax(tmax, sm[a * m0 + a]);
@@ -1370,6 +1442,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
   }
   __syncthreads();
   // 3. Ar = T^T GA T (symmetrised), via W = GA T
+  RR_MARK(2);
   if (v_in_lds) {
     // products from LDS: sa = sym(GA), sb = T; then sa = W, sb = Ar
     double* sa = sm;
@@ -1420,6 +1493,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
       sa[idx] = 0.5 * (sb[r * m0 + c] + sb[c * m0 + r]);
     }
     __syncthreads();
+    RR_MARK(3);
     sym_eig_ql(sm, m0, W, red, sm + mm, U);
   } else {
     for (int idx = tid; idx < mm; idx += blockDim.x) {
@@ -1444,20 +1518,18 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
     jacobi_eig(sm, m0, W, red, nullptr);
   }
   // 4. ascending order, C = T W(:, order), eta = 1/||c_l||
+  RR_MARK(4);
   __shared__ double evs[128];
-  if (tid == 0) {
-    for (int i = 0; i < m0; ++i) order[i] = i;
-    for (int i = 1; i < m0; ++i) {  // insertion sort on the diagonal
-      const int oi = order[i];
-      const double key = sm[oi * m0 + oi];
-      int k = i - 1;
-      while (k >= 0 && sm[order[k] * m0 + order[k]] > key) {
-        order[k + 1] = order[k];
-        --k;
-      }
-      order[k + 1] = oi;
+  // ascending ranks of the diagonal (ties by index), one thread per entry
+  for (int c = tid; c < m0; c += blockDim.x) {
+    const double key = sm[c * m0 + c];
+    int rank = 0;
+    for (int j = 0; j < m0; ++j) {
+      const double v = sm[j * m0 + j];
+      rank += (v < key || (v == key && j < c)) ? 1 : 0;
     }
-    for (int i = 0; i < m0; ++i) evs[i] = sm[order[i] * m0 + order[i]];
+    order[rank] = c;
+    evs[rank] = key;
   }
   __syncthreads();
   if (v_in_lds) {
@@ -1493,6 +1565,7 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
       for (int r = 0; r < m0; ++r) ss += sa[r * m0 + c] * sa[r * m0 + c];
       eta[c] = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
     }
+    RR_MARK(5);
     return;
   }
   for (int idx = tid; idx < mm; idx += blockDim.x) {

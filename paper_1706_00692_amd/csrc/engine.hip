@@ -158,9 +158,7 @@ namespace {
 
 // Columns of the random sketch that estimates the shared basis' loss of orthogonality.
 constexpr int kSketch = 16;
-// Kept fraction of a column's norm below which the local projection of a shared-basis step
-// runs twice.
-constexpr double kKeep = 0.5;
+
 
 struct Layout {
   // byte sizes of every buffer of the workspace
@@ -339,25 +337,26 @@ struct Engine::Impl {
   double reorth_eta = 0.1;  // keep-fraction below which a second pass runs (>= 1: always)
   int64_t reorth_steps = 0; // shift-steps that ran a second pass
   double max_loss = 0.0;     // largest measured loss of orthogonality (shared basis, partial mode)
-  int64_t one_pass_steps = 0;  // shared-basis steps with a single Gram-Schmidt pass
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
 
   // side stream of the shared-basis least squares updates, its events and host flag slots
   hipStream_t st_lsq = nullptr;
   hipEvent_t ev_main = nullptr, ev_lsq[2] = {nullptr, nullptr};
-  int* h_flags = nullptr;  // pinned, 2 x 64
+  int* h_flags = nullptr;  // pinned: 2 x 64 stop flags, then the step's check words
+  hipEvent_t ev_chk = nullptr;
   void side_stream() {
     if (st_lsq) return;
     IF_HIP(hipStreamCreateWithFlags(&st_lsq, hipStreamNonBlocking));
     IF_HIP(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[0], hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[1], hipEventDisableTiming));
-    IF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_flags), 2 * 64 * sizeof(int), hipHostMallocDefault));
+    IF_HIP(hipEventCreateWithFlags(&ev_chk, hipEventDisableTiming));
+    IF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_flags), 4 * 64 * sizeof(int), hipHostMallocDefault));
   }
   ~Impl() {
     if (st_lsq) (void)hipStreamSynchronize(st_lsq);
     if (h_flags) (void)hipHostFree(h_flags);
-    for (hipEvent_t e : {ev_main, ev_lsq[0], ev_lsq[1]})
+    for (hipEvent_t e : {ev_main, ev_lsq[0], ev_lsq[1], ev_chk})
       if (e) (void)hipEventDestroy(e);
     if (st_lsq) (void)hipStreamDestroy(st_lsq);
   }
@@ -579,14 +578,17 @@ struct Engine::Impl {
   // about kappa^2 u with kappa <= (1 + g) / (1 - g), g = single_gersh).  The second pass's
   // GEMMs are left out of the kernel timer (whether they run is known on the device only).
   template <class T>
-  void cholqr_adaptive_real(const T* src, T* tmp, T* dst, const double* G0) {
+  // certified: -1 unknown on the host (the flags are set here, on the device), 1 / 0: the
+  // flags d_single / d_two were set earlier and the host read them (one pass / two passes).
+  void cholqr_adaptive_real(const T* src, T* tmp, T* dst, const double* G0, int certified = -1) {
     const int64_t n = sh.n;
     const int m0 = sh.m0;
     const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
-    launch_gersh_flags(st, m0, G0, single_gersh, dead_thr, d_single, d_two, d_cnt);
+    if (certified < 0) launch_gersh_flags(st, m0, G0, single_gersh, dead_thr, d_single, d_two, d_cnt);
     launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single, 0);
     ApplyArgs a1{n, m0, m0, 1, 1, 1, src, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
     launch_apply<T, T>(st, a1);
+    if (certified == 1) return;
     GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two, gred.as<double>(), -1};
     launch_gram<T>(st, g2, gpart.p, gpart.bytes);
     launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single, 1);
@@ -679,48 +681,55 @@ struct Engine::Impl {
       gram(lo, nl);
       project(j, lo, nl, gred.as<double>(), 0);
       bool full = always || lo == 0;
-      bool second = true;          // the second Gram-Schmidt pass runs
-      const bool have_gw = !full;  // W^T W after the first pass is formed for the estimate
+      int certified = -1;
       if (!full) {
+        const int64_t mm0 = (int64_t)m0 * m0;
+        double* gsk = gred.as<double>() + 2 * mm0;  // beside the local pass's two items
         // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
         ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
                      Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
         launch_apply<T, T>(st, au);
         // 16 x 16 tiles: the sketch is read once per tile column, the block once
-        GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gred.as<double>(), KC_GRAM, 1};
+        GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gsk, KC_GRAM, 1};
         launch_gram<T>(st, gs, gpart.p, gpart.bytes);
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-        launch_sketch_check_real(st, kSketch, m0, gred.as<double>(), gwb.as<double>(), Hm.as<double>(), ldh, j, lo,
-                                 kKeep, d_loss);
-        double chk[2] = {0.0, 0.0};
-        IF_HIP(hipMemcpyAsync(chk, d_loss, sizeof(chk), hipMemcpyDeviceToHost, st));
-        IF_HIP(hipStreamSynchronize(st));
-        full = !(chk[0] <= thr);
-        max_loss = std::max(max_loss, chk[0]);
-        // one local pass leaves components of about u / kept along V_{j-1}, V_j: a second
-        // runs only when some column kept less than kKeep of its norm
-        second = full || chk[1] != 0.0;
-      }
-      const int plo = full ? 0 : lo, pnb = j + 1 - plo;
-      if (second) {
-        gram(plo, pnb);
-        project(j, plo, pnb, gred.as<double>(), 1);
+        launch_sketch_check_real(st, kSketch, m0, gsk, gwb.as<double>(), d_loss);
+        // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass
+        // changes the block by rounding only, or (a full pass) by at most reorth_eta per
+        // column, which the margin on the Gershgorin bound covers
+        launch_gersh_flags(st, m0, gwb.as<double>(), single_gersh - 4.0 * thr, dead_thr, d_single, d_two, d_cnt);
+        double* hchk = reinterpret_cast<double*>(h_flags + 128);
+        IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+        IF_HIP(hipMemcpyAsync(h_flags + 192, d_single, sizeof(int), hipMemcpyDeviceToHost, st));
+        IF_HIP(hipEventRecord(ev_chk, st));
+        // the local second pass is needed in either case: it runs while the host waits
+        gram(lo, nl);
+        project(j, lo, nl, gred.as<double>(), 1);
+        IF_HIP(hipEventSynchronize(ev_chk));
+        full = !(hchk[0] <= thr);
+        max_loss = std::max(max_loss, hchk[0]);
+        certified = h_flags[192] != 0 ? 1 : 0;
+        if (full) {
+          // a third pass against every block (the local blocks again: their coefficients are
+          // rounding-sized), and the block's Gram afresh
+          gram(0, j + 1);
+          project(j, 0, j + 1, gred.as<double>(), 1);
+          launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+          ++reorth_steps;
+        } else {
+          // W^T W - C^T C: the pass removed little, so this loses nothing to cancellation
+          launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwb.as<double>());
+        }
       } else {
-        ++one_pass_steps;
-      }
-      if (full && lo > 0) ++reorth_steps;
-      // the Gram of the projected block: after a local second pass W^T W - C^T C (the pass
-      // removes little, so this loses nothing to cancellation), else computed afresh
-      if (have_gw && !full) {
-        if (second) launch_gram_downdate(st, pnb * m0, m0, gred.as<double>(), gwb.as<double>());
-      }
-      else
+        gram(lo, nl);
+        project(j, lo, nl, gred.as<double>(), 1);
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+      }
       T* dst = Vb + (int64_t)(j + 1) * bs;
       if (always)
         cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
       else
-        cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>());
+        cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified);
       launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
       // the shifts' least squares updates of step j run on the side stream, beside step
       // j + 1's basis work; their stop flags are read one step later
@@ -1119,10 +1128,9 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         (void)hipEventElapsedTime(&ms_now, e0, en);
         (void)hipEventDestroy(en);
       }
-      fprintf(stderr,
-              "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld onepass=%lld loss=%.1e t=%.2fs\n",
-              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps,
-              (long long)I.one_pass_steps, I.max_loss, ms_now * 1e-3);
+      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld loss=%.1e t=%.2fs\n",
+              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps, I.max_loss,
+              ms_now * 1e-3);
       if (verbose2) {
         std::vector<double> etah(m0), rhoh(m0);
         IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));

@@ -257,11 +257,8 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
 template <class T>
 void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh, const double* G, double* Hm,
                          T* Hr, int accumulate);
-// out[0] = max over columns b of ||G[:, b]|| / ||w_b|| (G = U^T W, nk x m0; gw = W^T W);
-// out[1] = 1 when some column kept less than eta of its norm in the projection whose
-// coefficients are block column j of Hm from block row lo
-void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, const double* Hm,
-                              int ldh, int j, int lo, double eta, double* out);
+// out[0] = max over columns b of ||G[:, b]|| / ||w_b|| (G = U^T W, nk x m0; gw = W^T W)
+void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 // gw -= C^T C (C: rows x m0): the Gram of a block after projecting out orthonormal directions
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);

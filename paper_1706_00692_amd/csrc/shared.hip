@@ -52,19 +52,10 @@ __global__ void k_combine_real(int ni, int i0, int m0, int j, int ldh, const dou
 // Estimated loss of orthogonality of the projected block W against the older basis blocks:
 // max over columns b of ||G[:, b]|| / ||w_b|| with G = U^T W (nk x m0, row-major) the
 // sketch product and ||w_b||^2 the diagonal of gw = W^T W; out[0] = that maximum (NaN
-// when some column is not finite).  Also whether the first local projection cancelled
-// much of some column: out[1] = 1 when some w_b kept less than the fraction eta of its norm
-// before the projection, ||w_b||^2 < eta^2 (||w_b||^2 + ||c_b||^2), with c_b the
-// coefficients of that projection (block column j of Hm, rows lo m0 .. (j + 1) m0).
-// One workgroup of 128 threads.
+// when some column is not finite).  One workgroup of 128 threads.
 __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const double* __restrict__ G,
-                                                           const double* __restrict__ gw,
-                                                           const double* __restrict__ Hm, int ldh, int j, int lo,
-                                                           double eta2, double* __restrict__ out) {
+                                                           const double* __restrict__ gw, double* __restrict__ out) {
   __shared__ double red[2];
-  __shared__ int cancel;
-  if (threadIdx.x == 0) cancel = 0;
-  __syncthreads();
   double r = 0.0;
   for (int b = threadIdx.x; b < m0; b += blockDim.x) {
     double ss = 0.0;
@@ -72,15 +63,6 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
     const double d = gw[b * m0 + b];
     const double v = d > 0.0 ? sqrt(ss / d) : (ss > 0.0 ? INFINITY : 0.0);
     r = (v > r || v != v) ? v : r;
-    const double* h = Hm + (int64_t)(j * m0 + b) * ldh;
-    double c8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int q0 = lo * m0, q1 = (j + 1) * m0;  // a multiple of 16 rows
-    for (int q = q0; q < q1; q += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) c8[u] += h[q + u] * h[q + u];
-    }
-    const double cc = ((c8[0] + c8[1]) + (c8[2] + c8[3])) + ((c8[4] + c8[5]) + (c8[6] + c8[7]));
-    if (!(d >= eta2 * (d + cc))) cancel = 1;
   }
   for (int o = 32; o > 0; o >>= 1) {
     const double t = __shfl_xor(r, o);
@@ -88,10 +70,7 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
   }
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    out[0] = (red[1] > red[0] || red[1] != red[1]) ? red[1] : red[0];
-    out[1] = cancel ? 1.0 : 0.0;
-  }
+  if (threadIdx.x == 0) out[0] = (red[1] > red[0] || red[1] != red[1]) ? red[1] : red[0];
 }
 
 // Gram of the block after a projection W2 = W1 - V C with orthonormal V: W2^T W2 =
@@ -189,9 +168,8 @@ void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh,
                      Hm, Hr, accumulate);
   IF_HIP(hipGetLastError());
 }
-void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, const double* Hm,
-                              int ldh, int j, int lo, double eta, double* out) {
-  hipLaunchKernelGGL(k_sketch_check_real, dim3(1), dim3(128), 0, st, nk, m0, G, gw, Hm, ldh, j, lo, eta * eta, out);
+void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out) {
+  hipLaunchKernelGGL(k_sketch_check_real, dim3(1), dim3(128), 0, st, nk, m0, G, gw, out);
   IF_HIP(hipGetLastError());
 }
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw) {

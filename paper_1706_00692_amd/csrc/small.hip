@@ -19,9 +19,9 @@
 
 // Phase timestamps of the Rayleigh-Ritz kernel, compiled in only for profiling builds.
 #ifdef IFEAST_RR_PROFILE
-__device__ unsigned long long ifeast_rr_prof[16];
+__device__ unsigned long long ifeast_rr_prof[32];
 extern "C" void ifeast_rr_prof_read(unsigned long long* out) {
-  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(ifeast_rr_prof), 16 * sizeof(unsigned long long));
+  (void)hipMemcpyFromSymbol(out, HIP_SYMBOL(ifeast_rr_prof), 32 * sizeof(unsigned long long));
 }
 #define RR_MARK(i)                                                \
   do {                                                            \
@@ -359,13 +359,16 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
   }
   constexpr int NB = 16;
   extern __shared__ double lds_d[];
-  double* L = lds_d;           // m0 x m0
-  double* tmp = L + m0 * m0;   // 16 x m0
-  double* Rs = tmp + NB * m0;  // m0 x m0
-  __shared__ double dsc[128];
+  // rows of L padded to an odd number of doubles: column walks hit distinct LDS banks
+  const int ldl = m0 + 1;
+  double* L = lds_d;            // m0 x ldl
+  double* tmp = L + m0 * ldl;   // 16 x m0
+  double* Rs = tmp + NB * m0;   // m0 x m0
+  __shared__ double dsc[128], dinv[128];
   __shared__ int dead[128];
   const int tid = threadIdx.x, nth = blockDim.x, wave = tid >> 6, lane = tid & 63;
   const int P = m0 / NB;
+  RR_MARK(16);
   // ---- 1.
   for (int a = tid; a < m0; a += nth) {
     const double g = G[a * m0 + a];
@@ -379,32 +382,35 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     double g;
     if (dead[a] || dead[b]) g = a == b ? 1.0 : 0.0;
     else g = G[idx] / (dsc[a] * dsc[b]) + (a == b ? shift_rel : 0.0);
-    L[idx] = g;
+    L[a * ldl + b] = g;
     if (accumulate) Rs[idx] = Racc[idx].x;
   }
   __syncthreads();
   // ---- 2. blocked Cholesky (lower triangle of L)
+  RR_MARK(17);
   for (int p = 0; p < P; ++p) {
     const int c0 = p * NB;
     if (wave == 0) {
       for (int c = c0; c < c0 + NB; ++c) {
-        const double pv0 = L[c * m0 + c];
+        const double pv0 = L[c * ldl + c];
         const bool dc = dead[c] != 0 || !(pv0 > tau_dep);
         const double pv = dc ? 1.0 : sqrt(pv0);
+        const double rpv = 1.0 / pv;
         if (lane < c0 + NB - c - 1) {
           const int r = c + 1 + lane;
-          L[r * m0 + c] = dc ? 0.0 : L[r * m0 + c] / pv;
+          L[r * ldl + c] = dc ? 0.0 : L[r * ldl + c] * rpv;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (lane == 0) {
           dead[c] = dc ? 1 : 0;
-          L[c * m0 + c] = pv;
+          L[c * ldl + c] = pv;
+          dinv[c] = rpv;
         }
         if (!dc) {
           const int nt = c0 + NB - c - 1;
           for (int t = lane; t < nt * nt; t += 64) {
             const int rr = c + 1 + t / nt, q = c + 1 + t % nt;
-            if (q <= rr) L[rr * m0 + q] -= L[rr * m0 + c] * L[q * m0 + c];
+            if (q <= rr) L[rr * ldl + q] -= L[rr * ldl + c] * L[q * ldl + c];
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -414,9 +420,9 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     // rows below the diagonal block: x L11^T = a, forward along the panel's columns
     for (int r = c0 + NB + tid; r < m0; r += nth) {
       for (int c = c0; c < c0 + NB; ++c) {
-        double v = L[r * m0 + c];
-        for (int k = c0; k < c; ++k) v -= L[r * m0 + k] * L[c * m0 + k];
-        L[r * m0 + c] = dead[c] ? 0.0 : v / L[c * m0 + c];
+        double v = L[r * ldl + c];
+        for (int k = c0; k < c; ++k) v -= L[r * ldl + k] * L[c * ldl + k];
+        L[r * ldl + c] = dead[c] ? 0.0 : v * dinv[c];
       }
     }
     __syncthreads();
@@ -427,44 +433,47 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       if (q > r) continue;
       double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < NB; ++k) v += L[r * m0 + c0 + k] * L[q * m0 + c0 + k];
-      L[r * m0 + q] -= v;
+      for (int k = 0; k < NB; ++k) v += L[r * ldl + c0 + k] * L[q * ldl + c0 + k];
+      L[r * ldl + q] -= v;
     }
     __syncthreads();
   }
   // ---- 3. R factor (global writes; the previous R was staged in LDS)
+  RR_MARK(18);
   for (int idx = tid; idx < m0 * m0; idx += nth) {
     const int a = idx / m0, b = idx % m0;
     double v = 0.0;
     if (b >= a && !dead[a]) {
       if (accumulate)
-        for (int e = a; e <= b; ++e) v += dsc[e] * L[e * m0 + a] * Rs[e * m0 + b];
+        for (int e = a; e <= b; ++e) v += dsc[e] * L[e * ldl + a] * Rs[e * m0 + b];
       else
-        v = dsc[b] * L[b * m0 + a];
+        v = dsc[b] * L[b * ldl + a];
     }
     Racc[idx] = make_double2(v, 0.0);
   }
   __syncthreads();
   // ---- 4a. invert the diagonal blocks, one wave each (in place)
+  RR_MARK(19);
   for (int p = wave; p < P; p += nth / 64) {
     const int c0 = p * NB;
     const int i = lane;  // row of the block (lanes 16..63 idle)
     for (int j = NB - 1; j >= 0; --j) {
-      const double ljj = L[(c0 + j) * m0 + c0 + j];
-      const double xi = (i > j && i < NB) ? L[(c0 + i) * m0 + c0 + j] : 0.0;
+      const double ljj = L[(c0 + j) * ldl + c0 + j];
+      const double xi = (i > j && i < NB) ? L[(c0 + i) * ldl + c0 + j] : 0.0;
       double v = 0.0;
       for (int k = j + 1; k < NB; ++k) {
         const double xk = __shfl(xi, k);
-        if (i < NB && k <= i) v += L[(c0 + i) * m0 + c0 + k] * xk;
+        if (i < NB && k <= i) v += L[(c0 + i) * ldl + c0 + k] * xk;
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (i > j && i < NB) L[(c0 + i) * m0 + c0 + j] = -v / ljj;
-      if (i == j) L[(c0 + j) * m0 + c0 + j] = 1.0 / ljj;
+      if (i > j && i < NB) L[(c0 + i) * ldl + c0 + j] = -v / ljj;
+      if (i == j) L[(c0 + j) * ldl + c0 + j] = 1.0 / ljj;
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   }
   __syncthreads();
   // ---- 4b. block rows of the inverse below the diagonal
+  RR_MARK(20);
   for (int bi = 1; bi < P; ++bi) {
     const int r0 = bi * NB, w = bi * NB;  // block row start; the blocks j < bi span columns [0, w)
     // S_j = sum_{k=j..bi-1} L_{bi,k} X_{k,j}  (X: the inverse so far), into tmp[16][w]
@@ -472,7 +481,7 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       const int r = idx / w, c = idx % w;
       // X is lower triangular (rows k >= c); L's storage above the diagonal is not part of it
       double v = 0.0;
-      for (int k = c; k < r0; ++k) v += L[(r0 + r) * m0 + k] * L[k * m0 + c];
+      for (int k = c; k < r0; ++k) v += L[(r0 + r) * ldl + k] * L[k * ldl + c];
       tmp[r * m0 + c] = v;
     }
     __syncthreads();
@@ -480,17 +489,19 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     for (int idx = tid; idx < NB * w; idx += nth) {
       const int r = idx / w, c = idx % w;
       double v = 0.0;
-      for (int m = 0; m <= r; ++m) v += L[(r0 + r) * m0 + r0 + m] * tmp[m * m0 + c];
-      L[(r0 + r) * m0 + c] = -v;
+      for (int m = 0; m <= r; ++m) v += L[(r0 + r) * ldl + r0 + m] * tmp[m * m0 + c];
+      L[(r0 + r) * ldl + c] = -v;
     }
     __syncthreads();
   }
   // ---- 5.
+  RR_MARK(21);
   for (int idx = tid; idx < m0 * m0; idx += nth) {
     const int a = idx / m0, b = idx % m0;
-    const double v = (b < a || dead[a] || dead[b]) ? 0.0 : L[b * m0 + a] / dsc[a];
+    const double v = (b < a || dead[a] || dead[b]) ? 0.0 : L[b * ldl + a] / dsc[a];
     Tinv[idx] = (T)v;
   }
+  RR_MARK(22);
 }
 
 template <class T>
@@ -986,6 +997,7 @@ __global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
   const bool live = col < m0;  // dead waves still join the workgroup barriers
   c2* Rd = fb_lds;                                  // packed R_bb, column cl at cl (cl + 1) / 2
   c2* x = fb_lds + m0 * (m0 + 1) / 2 + wave * W;    // this wave's window
+  c2* Hc = fb_lds + m0 * (m0 + 1) / 2 + 4 * W;      // 16 columns of the band above R_bb
   const int n = J * m0;
   const c2* gc = v.g + (int64_t)(live ? col : 0) * ldh;
   c2* yc = v.y + (int64_t)(live ? col : 0) * ldy;
@@ -1017,26 +1029,48 @@ __global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
         if (lane == 0) x[(b0 + cl) % W] = yv;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
-      // rows of the blocks above within the band: x -= R(rows, block b) y_b
-      const int rlo = max(0, (b - a.band - 1) * m0);
-      for (int r0 = rlo; r0 < b0; r0 += 64) {
-        const int r = r0 + lane;
-        if (r < b0) {
-          c2 acc = cmk(0.0, 0.0);
-          const c2* Hr = v.H + (int64_t)b0 * ldh + r;
-          // 16 independent loads in flight per chunk (m0 is a multiple of 16)
-          for (int c0 = 0; c0 < m0; c0 += 16) {
-            c2 hv[16];
+    }
+    // rows of the blocks above within the band: x -= R(rows, block b) y_b, with R's block
+    // column staged 16 columns at a time (every wave of the workgroup reads the same R)
+    {
+      const int rlo = max(0, (b - a.band - 1) * m0), nr = b0 - rlo;  // nr <= 256
+      c2 acc[4];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) hv[u] = Hr[(int64_t)(c0 + u) * ldh];
+      for (int t = 0; t < 4; ++t) acc[t] = cmk(0.0, 0.0);
+      for (int c0 = 0; c0 < m0; c0 += 16) {
+        __syncthreads();
+        for (int idx = tid; idx < 16 * nr; idx += blockDim.x) {
+          const int u = idx / nr, rr = idx % nr;
+          Hc[idx] = v.H[(int64_t)(b0 + c0 + u) * ldh + rlo + rr];
+        }
+        __syncthreads();
+        if (live) {
+          c2 yv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc = cadd(acc, cmul(hv[u], x[(b0 + c0 + u) % W]));
+          for (int u = 0; u < 16; ++u) yv[u] = x[(b0 + c0 + u) % W];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int rr = lane + 64 * t;
+            if (rr < nr) {
+#pragma unroll
+              for (int u = 0; u < 16; ++u) acc[t] = cadd(acc[t], cmul(Hc[u * nr + rr], yv[u]));
+            }
           }
-          c2& t = x[r % W];
-          t = csub(t, acc);
+        }
+      }
+      if (live) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int rr = lane + 64 * t;
+          if (rr < nr) {
+            c2& tt = x[(rlo + rr) % W];
+            tt = csub(tt, acc[t]);
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    if (live) {
       // block b is solved: out to y; its slots take the block that block row b - 1 reaches
       const int nb = b - WB;
       for (int r = lane; r < m0; r += 64) {
@@ -1729,7 +1763,7 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
     const size_t with_ra = lds + (size_t)m0 * m0 * sizeof(c2);
     const int ra_in_lds = (accumulate && (int64_t)with_ra + 2048 <= (int64_t)max_lds) ? 1 : 0;
     if (ra_in_lds) lds = with_ra;
-    const size_t lds_real = ((size_t)2 * m0 * m0 + 16 * (size_t)m0) * sizeof(double);
+    const size_t lds_real = ((size_t)m0 * (m0 + 1) + (size_t)m0 * m0 + 16 * (size_t)m0) * sizeof(double);
     if (real && m0 <= 80 && ns == 1 && active == nullptr && (int64_t)lds_real + 2048 <= (int64_t)max_lds &&
         getenv("IFEAST_CHOLQR_UNBLOCKED") == nullptr) {
       if (lds_real > 64 * 1024)
@@ -1804,7 +1838,7 @@ void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shif
   const double dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
   const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   const double tau_dep = shift_rel > 0.0 ? 0.5 * shift_rel : 0.25 * m0 * eps;
-  const size_t lds_real = ((size_t)2 * m0 * m0 + 16 * (size_t)m0) * sizeof(double);
+  const size_t lds_real = ((size_t)m0 * (m0 + 1) + (size_t)m0 * m0 + 16 * (size_t)m0) * sizeof(double);
   if (lds_real > 64 * 1024)
     IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
@@ -1913,8 +1947,9 @@ void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
-  if (a.band > 0 && !a.need_u && a.m0 <= 128) {
-    const size_t lds = ((size_t)a.m0 * (a.m0 + 1) / 2 + (size_t)4 * (a.band + 2) * a.m0) * sizeof(c2);
+  if (a.band > 0 && !a.need_u && a.m0 <= 128 && (a.band + 1) * a.m0 <= 256) {
+    const size_t lds = ((size_t)a.m0 * (a.m0 + 1) / 2 + (size_t)4 * (a.band + 2) * a.m0 +
+                        (size_t)16 * (a.band + 1) * a.m0) * sizeof(c2);
     if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_finish_band),

@@ -113,7 +113,7 @@ typedef struct {
                           blocks, and the second also against every older block when the loss of
                           orthogonality to them, max over columns w of ||[V_0..]^T w|| / ||w||
                           estimated from a 16-column random sketch, exceeds this value; 0 selects
-                          max(1e-4, alpha / 4) for an FP32 basis and 1e-12 for an FP64 one.
+                          max(1e-4, alpha / 10) for an FP32 basis and 1e-12 for an FP64 one.
                           >= 1: always two full passes and two Cholesky-QR passes */
   int precision;       /* IFEAST_PREC_* */
   int problem;         /* IFEAST_PROBLEM_* */

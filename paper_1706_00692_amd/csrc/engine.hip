@@ -633,9 +633,10 @@ struct Engine::Impl {
     // E ||U^T w||^2 = ||[V_0..]^T w||^2), so that the estimate reads n x kSketch numbers
     // instead of the whole basis.  reorth_eta >= 1 projects against every block in both passes.
     const bool always = p.reorth_eta >= 1.0;
-    // default: a quarter of the inner tolerance factor for an FP32 basis (the loss then stays
-    // well below the accuracy the inner solves ask for), near FP64 rounding for an FP64 one
-    const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? std::max(1e-4, 0.25 * p.alpha) : 1e-12);
+    // default: a tenth of the inner tolerance factor for an FP32 basis (the loss then stays an
+    // order of magnitude below the accuracy the inner solves ask for), near FP64 rounding for
+    // an FP64 one
+    const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? std::max(1e-4, 0.1 * p.alpha) : 1e-12);
     reorth_eta = thr;
     // one Cholesky-QR pass when the block's Gram certifies kappa <= 3 (orthonormal to ~9 u)
     single_gersh = 0.5;

@@ -977,10 +977,10 @@ __global__ __launch_bounds__(256) void k_lsq_finish(LsqArgs a) {
 }
 
 // y = R^{-1} g_top for a block-banded R (no u): block back substitution from the last block
-// row up.  Per block b: the diagonal block R_bb (packed upper triangle) is staged in LDS
-// once for the workgroup's four right-hand sides (one wave each) and solved column by
-// column, then the rows of blocks b - band - 1 .. b - 1 take the products with R's block
-// column b.  Each wave keeps its right-hand side's rows of the band + 2 blocks that the
+// row up.  Per block b: the diagonal block R_bb (packed upper triangle, its diagonal as
+// reciprocals) is staged in LDS once for the workgroup's four right-hand sides (one wave
+// each) and solved column by column, then the rows of blocks b - band - 1 .. b - 1 take
+// the products with R's block column b.  Each wave keeps its right-hand side's rows of the band + 2 blocks that the
 // current block row touches in an LDS window (row r in slot r mod (band + 2) m0); solved
 // blocks go to y, the next block above comes in from g.  grid (ns, ceil(m0/4)); LDS:
 // m0 (m0 + 1) / 2 + 4 (band + 2) m0 complex.
@@ -997,7 +997,6 @@ __global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
   const bool live = col < m0;  // dead waves still join the workgroup barriers
   c2* Rd = fb_lds;                                  // packed R_bb, column cl at cl (cl + 1) / 2
   c2* x = fb_lds + m0 * (m0 + 1) / 2 + wave * W;    // this wave's window
-  c2* Hc = fb_lds + m0 * (m0 + 1) / 2 + 4 * W;      // 16 columns of the band above R_bb
   const int n = J * m0;
   const c2* gc = v.g + (int64_t)(live ? col : 0) * ldh;
   c2* yc = v.y + (int64_t)(live ? col : 0) * ldy;
@@ -1007,76 +1006,52 @@ __global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
   }
   for (int b = J - 1; b >= 0; --b) {
     const int b0 = b * m0;
+    c2* xb = x + (b % WB) * m0;  // window slots of block b
     __syncthreads();
     for (int idx = tid; idx < m0 * (m0 + 1) / 2; idx += blockDim.x) {
       int cl = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
       while (cl * (cl + 1) / 2 > idx) --cl;
       while ((cl + 1) * (cl + 2) / 2 <= idx) ++cl;
       const int r = idx - cl * (cl + 1) / 2;
-      Rd[idx] = v.H[(int64_t)(b0 + cl) * ldh + b0 + r];
+      const c2 h = v.H[(int64_t)(b0 + cl) * ldh + b0 + r];
+      // the diagonal is kept as its reciprocal (0 for a deflated column)
+      Rd[idx] = r == cl ? (cabs2(h) > 1e-300 ? cdiv(cmk(1.0, 0.0), h) : cmk(0.0, 0.0)) : h;
     }
     __syncthreads();
     if (live) {
       // triangular solve with R_bb on the rows of block b
       for (int cl = m0 - 1; cl >= 0; --cl) {
         const c2* Rc = Rd + cl * (cl + 1) / 2;
-        const c2 d = Rc[cl];
-        const c2 yv = cabs2(d) > 1e-300 ? cdiv(x[(b0 + cl) % W], d) : cmk(0.0, 0.0);
-        for (int r = lane; r < cl; r += 64) {
-          c2& t = x[(b0 + r) % W];
-          t = csub(t, cmul(Rc[r], yv));
-        }
-        if (lane == 0) x[(b0 + cl) % W] = yv;
+        const c2 yv = cmul(xb[cl], Rc[cl]);
+        for (int r = lane; r < cl; r += 64) xb[r] = csub(xb[r], cmul(Rc[r], yv));
+        if (lane == 0) xb[cl] = yv;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
-    }
-    // rows of the blocks above within the band: x -= R(rows, block b) y_b, with R's block
-    // column staged 16 columns at a time (every wave of the workgroup reads the same R)
-    {
-      const int rlo = max(0, (b - a.band - 1) * m0), nr = b0 - rlo;  // nr <= 256
-      c2 acc[4];
+      // rows of the blocks above within the band: x -= R(rows, block b) y_b
+      const int rlo = max(0, (b - a.band - 1) * m0);
+      for (int r0 = rlo; r0 < b0; r0 += 64) {
+        const int r = r0 + lane;
+        if (r < b0) {
+          c2 acc = cmk(0.0, 0.0);
+          const c2* Hr = v.H + (int64_t)b0 * ldh + r;
+          // 16 independent loads in flight per chunk (m0 is a multiple of 16)
+          for (int c0 = 0; c0 < m0; c0 += 16) {
+            c2 hv[16];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = cmk(0.0, 0.0);
-      for (int c0 = 0; c0 < m0; c0 += 16) {
-        __syncthreads();
-        for (int idx = tid; idx < 16 * nr; idx += blockDim.x) {
-          const int u = idx / nr, rr = idx % nr;
-          Hc[idx] = v.H[(int64_t)(b0 + c0 + u) * ldh + rlo + rr];
-        }
-        __syncthreads();
-        if (live) {
-          c2 yv[16];
+            for (int u = 0; u < 16; ++u) hv[u] = Hr[(int64_t)(c0 + u) * ldh];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) yv[u] = x[(b0 + c0 + u) % W];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int rr = lane + 64 * t;
-            if (rr < nr) {
-#pragma unroll
-              for (int u = 0; u < 16; ++u) acc[t] = cadd(acc[t], cmul(Hc[u * nr + rr], yv[u]));
-            }
+            for (int u = 0; u < 16; ++u) acc = cadd(acc, cmul(hv[u], xb[c0 + u]));
           }
-        }
-      }
-      if (live) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int rr = lane + 64 * t;
-          if (rr < nr) {
-            c2& tt = x[(rlo + rr) % W];
-            tt = csub(tt, acc[t]);
-          }
+          c2& t = x[((r / m0) % WB) * m0 + r % m0];
+          t = csub(t, acc);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    }
-    if (live) {
       // block b is solved: out to y; its slots take the block that block row b - 1 reaches
       const int nb = b - WB;
       for (int r = lane; r < m0; r += 64) {
-        const int slot = (b0 + r) % W;
-        yc[b0 + r] = x[slot];
-        if (nb >= 0) x[slot] = gc[nb * m0 + r];
+        yc[b0 + r] = xb[r];
+        if (nb >= 0) xb[r] = gc[nb * m0 + r];
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
@@ -1947,9 +1922,8 @@ void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
-  if (a.band > 0 && !a.need_u && a.m0 <= 128 && (a.band + 1) * a.m0 <= 256) {
-    const size_t lds = ((size_t)a.m0 * (a.m0 + 1) / 2 + (size_t)4 * (a.band + 2) * a.m0 +
-                        (size_t)16 * (a.band + 1) * a.m0) * sizeof(c2);
+  if (a.band > 0 && !a.need_u && a.m0 <= 128) {
+    const size_t lds = ((size_t)a.m0 * (a.m0 + 1) / 2 + (size_t)4 * (a.band + 2) * a.m0) * sizeof(c2);
     if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_finish_band),

@@ -670,6 +670,7 @@ struct Engine::Impl {
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
     T* U = Us.as<T>();
     if (!always) launch_fill_zero(st, Us.p, Us.bytes);
+    bool force_next = false;  // the step after a triggered third pass takes one too
     const int zero_cnt = 0;
     h2d(d_cnt, &zero_cnt, sizeof(int));
     side_stream();
@@ -707,13 +708,32 @@ struct Engine::Impl {
         gram(lo, nl);
         project(j, lo, nl, gred.as<double>(), 1);
         IF_HIP(hipEventSynchronize(ev_chk));
-        full = !(hchk[0] <= thr);
+        // a third pass cleans the new block, but the block before it still carries the loss
+        // into the next step's product: that step takes a third pass too, after which both
+        // parents of the recurrence are clean (Simon's partial reorthogonalisation does the same)
+        full = force_next || !(hchk[0] <= thr);
+        force_next = full && !force_next;
         max_loss = std::max(max_loss, hchk[0]);
         certified = h_flags[192] != 0 ? 1 : 0;
         if (full) {
           // a third pass against every block (the local blocks again: their coefficients are
           // rounding-sized), and the block's Gram afresh
           gram(0, j + 1);
+          if (getenv("IFEAST_DEBUG_REORTH") != nullptr) {
+            std::vector<double> gh((size_t)(j + 1) * m0 * m0), wh((size_t)m0 * m0);
+            IF_HIP(hipMemcpyAsync(gh.data(), gred.p, gh.size() * 8, hipMemcpyDeviceToHost, st));
+            IF_HIP(hipMemcpyAsync(wh.data(), gwb.p, wh.size() * 8, hipMemcpyDeviceToHost, st));
+            IF_HIP(hipStreamSynchronize(st));
+            fprintf(stderr, "[reorth] j=%d est=%.1e per-block max|c|/|w|:", j, hchk[0]);
+            for (int i = 0; i <= j; ++i) {
+              double mx = 0.0;
+              for (int a = 0; a < m0; ++a)
+                for (int b = 0; b < m0; ++b)
+                  mx = std::max(mx, std::fabs(gh[(size_t)i * m0 * m0 + a * m0 + b]) / std::sqrt(wh[b * m0 + b]));
+              fprintf(stderr, " %.0e", mx);
+            }
+            fprintf(stderr, "\n");
+          }
           project(j, 0, j + 1, gred.as<double>(), 1);
           launch_gram<T>(st, gw, gpart.p, gpart.bytes);
           ++reorth_steps;

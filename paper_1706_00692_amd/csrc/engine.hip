@@ -680,7 +680,16 @@ struct Engine::Impl {
       // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike)
       launch_spmm_shifted<T>(st, A, nullptr, 1, m0 / 2, zsT.as<T>(), nullptr, Vb + (int64_t)j * bs, t1);
       const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
-      gram(lo, nl);
+      if (!always && j >= 1) {
+        // first pass: the coefficients against V_{j-1} are those of the recurrence,
+        // V_{j-1}^T M V_j = (M V_{j-1})^T V_j = Hm(j, j-1)^T, so only V_j^T W is formed
+        GramArgs g1{n, m0, m0, 1, 1, Vb + (int64_t)j * bs, m0, 0, 0, t1, m0, 0, 0, nullptr,
+                    gred.as<double>() + (int64_t)m0 * m0};
+        launch_gram<T>(st, g1, gpart.p, gpart.bytes);
+        launch_lanczos_prev(st, m0, j, ldh, Hm.as<double>(), gred.as<double>());
+      } else {
+        gram(lo, nl);
+      }
       project(j, lo, nl, gred.as<double>(), 0);
       bool full = always || lo == 0;
       int certified = -1;

@@ -261,6 +261,8 @@ void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh,
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 // gw -= C^T C (C: rows x m0): the Gram of a block after projecting out orthonormal directions
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw);
+// G0 (m0 x m0, Gram layout) = Hm(j, j-1)^T: first-pass coefficients against V_{j-1}
+void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, const double* Hm, double* G0);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
 // block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
 void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,

@@ -99,6 +99,15 @@ __global__ __launch_bounds__(256) void k_gram_downdate(int rows, int m0, const d
   if (a0 + ia < m0 && b0 + ib < m0) gw[(a0 + ia) * m0 + b0 + ib] -= acc;
 }
 
+// G0[a][b] = Hm(j, j-1)[b][a]: the first-pass coefficients of W = M V_j against V_{j-1}
+// (the transpose of the previous step's subdiagonal block, M symmetric), in the Gram layout.
+__global__ void k_lanczos_prev(int m0, int j, int ldh, const double* __restrict__ Hm, double* __restrict__ G0) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m0 * m0) return;
+  const int a = idx / m0, b = idx % m0;
+  G0[idx] = Hm[(int64_t)((j - 1) * m0 + a) * ldh + j * m0 + b];
+}
+
 // Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
 __global__ void k_subdiag_real(int m0, int j, int ldh, const c2* __restrict__ Racc, double* __restrict__ Hm) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,6 +184,10 @@ void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, c
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw) {
   const int nt = (m0 + 15) / 16;
   hipLaunchKernelGGL(k_gram_downdate, dim3(nt * nt), dim3(256), 0, st, rows, m0, C, gw);
+  IF_HIP(hipGetLastError());
+}
+void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, const double* Hm, double* G0) {
+  hipLaunchKernelGGL(k_lanczos_prev, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh, Hm, G0);
   IF_HIP(hipGetLastError());
 }
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {

@@ -656,13 +656,16 @@ struct Engine::Impl {
     la.band = 1;
     launch_lsq_init(st, la, Ss.as<cd>());
     // G = [V_lo..V_{lo+nb-1}]^T W
-    auto gram = [&](int lo, int nb) {
-      GramArgs gg{n, m0, m0, 1, nb, Vb + (int64_t)lo * bs, m0, 0, bs, t1, m0, 0, 0, nullptr, gred.as<double>()};
+    // G = [V_lo..V_{lo+nb-1}]^T W into gred (from item 0 at gred + off items), its reduction
+    // also writing block column j of Hm (block rows lo..) and the update factors Hr
+    auto gram = [&](int j, int lo, int nb, int accumulate, int off = 0) {
+      GramArgs gg{n, m0, m0, 1, nb, Vb + (int64_t)lo * bs, m0, 0, bs, t1, m0, 0, 0, nullptr,
+                  gred.as<double>() + (int64_t)off * m0 * m0};
+      gg.cmb = GramCombine{Hm.as<double>(), ldh, j, lo, accumulate, Hr.as<T>() + (int64_t)off * m0 * m0};
       launch_gram<T>(st, gg, gpart.p, gpart.bytes);
     };
-    // W -= [V_lo..V_{lo+nb-1}] G_lo.., coefficients into block column j of Hm
-    auto project = [&](int j, int lo, int nb, const double* G, int accumulate) {
-      launch_combine_real<T>(st, nb, lo, m0, j, ldh, G, Hm.as<double>(), Hr.as<T>(), accumulate);
+    // W -= [V_lo..V_{lo+nb-1}] Hr
+    auto project = [&](int lo, int nb) {
       ApplyArgs ap{n, m0, m0, 1, nb, nb, Vb + (int64_t)lo * bs, m0, 0, 0, bs, Hr.p, 0, t1, m0, 0, -1.0, 1.0, nullptr,
                    nullptr};
       launch_apply<T, T>(st, ap);
@@ -683,14 +686,12 @@ struct Engine::Impl {
       if (!always && j >= 1) {
         // first pass: the coefficients against V_{j-1} are those of the recurrence,
         // V_{j-1}^T M V_j = (M V_{j-1})^T V_j = Hm(j, j-1)^T, so only V_j^T W is formed
-        GramArgs g1{n, m0, m0, 1, 1, Vb + (int64_t)j * bs, m0, 0, 0, t1, m0, 0, 0, nullptr,
-                    gred.as<double>() + (int64_t)m0 * m0};
-        launch_gram<T>(st, g1, gpart.p, gpart.bytes);
-        launch_lanczos_prev(st, m0, j, ldh, Hm.as<double>(), gred.as<double>());
+        launch_lanczos_prev<T>(st, m0, j, ldh, Hm.as<double>(), Hr.as<T>());
+        gram(j, j, 1, 0, 1);
       } else {
-        gram(lo, nl);
+        gram(j, lo, nl, 0);
       }
-      project(j, lo, nl, gred.as<double>(), 0);
+      project(lo, nl);
       bool full = always || lo == 0;
       int certified = -1;
       if (!full) {
@@ -714,8 +715,8 @@ struct Engine::Impl {
         IF_HIP(hipMemcpyAsync(h_flags + 192, d_single, sizeof(int), hipMemcpyDeviceToHost, st));
         IF_HIP(hipEventRecord(ev_chk, st));
         // the local second pass is needed in either case: it runs while the host waits
-        gram(lo, nl);
-        project(j, lo, nl, gred.as<double>(), 1);
+        gram(j, lo, nl, 1);
+        project(lo, nl);
         IF_HIP(hipEventSynchronize(ev_chk));
         // a third pass cleans the new block, but the block before it still carries the loss
         // into the next step's product: that step takes a third pass too, after which both
@@ -727,7 +728,7 @@ struct Engine::Impl {
         if (full) {
           // a third pass against every block (the local blocks again: their coefficients are
           // rounding-sized), and the block's Gram afresh
-          gram(0, j + 1);
+          gram(j, 0, j + 1, 1);
           if (getenv("IFEAST_DEBUG_REORTH") != nullptr) {
             std::vector<double> gh((size_t)(j + 1) * m0 * m0), wh((size_t)m0 * m0);
             IF_HIP(hipMemcpyAsync(gh.data(), gred.p, gh.size() * 8, hipMemcpyDeviceToHost, st));
@@ -743,7 +744,7 @@ struct Engine::Impl {
             }
             fprintf(stderr, "\n");
           }
-          project(j, 0, j + 1, gred.as<double>(), 1);
+          project(0, j + 1);
           launch_gram<T>(st, gw, gpart.p, gpart.bytes);
           ++reorth_steps;
         } else {
@@ -751,8 +752,8 @@ struct Engine::Impl {
           launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwb.as<double>());
         }
       } else {
-        gram(lo, nl);
-        project(j, lo, nl, gred.as<double>(), 1);
+        gram(j, lo, nl, 1);
+        project(lo, nl);
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
       }
       T* dst = Vb + (int64_t)(j + 1) * bs;

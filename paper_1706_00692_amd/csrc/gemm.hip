@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
 
 template <class T>
 __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, const int* __restrict__ active,
-                              const T* __restrict__ partial, double* __restrict__ G) {
+                              const T* __restrict__ partial, double* __restrict__ G, GramCombine cmb) {
   // 8 consecutive lanes share one output element: each sums every 8th split, then the
   // lanes' sums are added with shuffles (the order is fixed, so results are reproducible)
   const int64_t per_item = (int64_t)PW * QW;
@@ -188,7 +188,16 @@ __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, con
   sum += __shfl_xor(sum, 1);
   sum += __shfl_xor(sum, 2);
   sum += __shfl_xor(sum, 4);
-  if (on && part == 0) G[idx] = sum;
+  if (on && part == 0) {
+    G[idx] = sum;
+    if (cmb.Hm != nullptr) {
+      // block column j of Hm (block rows i0 + item) and the update factors, as k_combine_real
+      const int a = (int)((idx % per_item) / QW), b = (int)(idx % QW);
+      double* h = cmb.Hm + (int64_t)(cmb.j * QW + b) * cmb.ldh + (int64_t)(cmb.i0 + item) * PW + a;
+      *h = cmb.accumulate ? *h + sum : sum;
+      static_cast<T*>(cmb.Hr)[idx] = (T)sum;
+    }
+  }
 }
 
 // Gram of several blocks of a shift against the same right operand:
@@ -621,7 +630,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     }
     const int64_t total = (int64_t)items * g.PW * g.QW * 8;
     hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
-                       g.PW, g.QW, g.ni, g.active, part, g.G);
+                       g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
     IF_HIP(hipGetLastError());
     return;
   }
@@ -665,7 +674,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   }
   const int64_t total = (int64_t)items * g.PW * g.QW * 8;
   hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
-                     g.PW, g.QW, g.ni, g.active, part, g.G);
+                     g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
   IF_HIP(hipGetLastError());
 }
 

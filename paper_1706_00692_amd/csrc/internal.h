@@ -151,6 +151,15 @@ void launch_spmm_real(hipStream_t st, const ifeast_matrix* M, int m, const doubl
 //   G[item] = sum_rows A_item^T B_item,  A_item (n x PW), B_item (n x QW).
 // item = s*ni + i addresses A = A0 + s*a_s + i*a_i, B = B0 + s*b_s (+ i*b_i).
 // Partial sums over row splits are reduced in FP64 into G (double, item-major, PW x QW).
+// Optional output of a Gram's reduction for one real shift (shared basis): G also goes to
+// block column j of Hm (FP64, column-major ldh, block rows i0 + item; added when accumulate)
+// and to Hr (type T, G's layout), as the Gram-Schmidt update needs them.
+struct GramCombine {
+  double* Hm = nullptr;
+  int ldh = 0, j = 0, i0 = 0, accumulate = 0;
+  void* Hr = nullptr;
+};
+
 struct GramArgs {
   int64_t n;
   int PW, QW;
@@ -163,6 +172,7 @@ struct GramArgs {
   double* G;          // ns*ni*PW*QW
   int kclass = KC_GRAM;  // timing class (KC_GRAM or KC_OUTER; < 0: not timed)
   int tb_cap = 0;        // > 0: largest square tile, in 16-column blocks (narrow-by-wide products)
+  GramCombine cmb;       // optional (cmb.Hm != null): Hm and Hr written by the reduction
 };
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes);
@@ -252,17 +262,13 @@ struct LsqArgs {
 // ---- shared-basis inner solve (shared.hip): Arnoldi of M = -A on real blocks
 template <class T>
 void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
-// Gram-Schmidt coefficients G (ni items m0 x m0) -> block column j of Hm (FP64, column-major
-// ldh) and update factors Hr (type T)
-template <class T>
-void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh, const double* G, double* Hm,
-                         T* Hr, int accumulate);
 // out[0] = max over columns b of ||G[:, b]|| / ||w_b|| (G = U^T W, nk x m0; gw = W^T W)
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 // gw -= C^T C (C: rows x m0): the Gram of a block after projecting out orthonormal directions
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw);
-// G0 (m0 x m0, Gram layout) = Hm(j, j-1)^T: first-pass coefficients against V_{j-1}
-void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, const double* Hm, double* G0);
+// first-pass coefficients against V_{j-1}: Hm(j, j-1)^T into block column j of Hm and Hr
+template <class T>
+void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, double* Hm, T* Hr);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
 // block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
 void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,

@@ -32,23 +32,6 @@ __global__ void k_to_T(int64_t count, const double* __restrict__ X, T* __restric
   if (i < count) Y[i] = (T)X[i];
 }
 
-// Coefficients of one Gram-Schmidt pass: G = [V_i0..V_{i0+ni-1}]^T W (ni items of m0 x m0,
-// item-major, row a = basis column) -> block rows i0.. of block column j of Hm (+= when
-// accumulating) and the update factors Hr (same layout as G, type T) for W -= sum_i V_i Hr_i.
-template <class T>
-__global__ void k_combine_real(int ni, int i0, int m0, int j, int ldh, const double* __restrict__ G,
-                               double* __restrict__ Hm, T* __restrict__ Hr, int accumulate) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)m0 * m0;
-  if (idx >= ni * per) return;
-  const int i = (int)(idx / per);
-  const int a = (int)((idx % per) / m0), b = (int)(idx % m0);
-  const double c = G[idx];
-  double* h = Hm + (int64_t)(j * m0 + b) * ldh + (i0 + i) * m0 + a;
-  *h = accumulate ? *h + c : c;
-  Hr[idx] = (T)c;
-}
-
 // Estimated loss of orthogonality of the projected block W against the older basis blocks:
 // max over columns b of ||G[:, b]|| / ||w_b|| with G = U^T W (nk x m0, row-major) the
 // sketch product and ||w_b||^2 the diagonal of gw = W^T W; out[0] = that maximum (NaN
@@ -99,13 +82,17 @@ __global__ __launch_bounds__(256) void k_gram_downdate(int rows, int m0, const d
   if (a0 + ia < m0 && b0 + ib < m0) gw[(a0 + ia) * m0 + b0 + ib] -= acc;
 }
 
-// G0[a][b] = Hm(j, j-1)[b][a]: the first-pass coefficients of W = M V_j against V_{j-1}
-// (the transpose of the previous step's subdiagonal block, M symmetric), in the Gram layout.
-__global__ void k_lanczos_prev(int m0, int j, int ldh, const double* __restrict__ Hm, double* __restrict__ G0) {
+// First-pass coefficients of W = M V_j against V_{j-1}: Hm(j, j-1)^T (the transpose of the
+// previous step's subdiagonal block, M symmetric), into rows (j-1) m0.. of block column j of
+// Hm and into the update factors Hr (item 0, Gram layout: row a = basis column).
+template <class T>
+__global__ void k_lanczos_prev(int m0, int j, int ldh, double* __restrict__ Hm, T* __restrict__ Hr) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m0 * m0) return;
   const int a = idx / m0, b = idx % m0;
-  G0[idx] = Hm[(int64_t)((j - 1) * m0 + a) * ldh + j * m0 + b];
+  const double c = Hm[(int64_t)((j - 1) * m0 + a) * ldh + j * m0 + b];
+  Hm[(int64_t)(j * m0 + b) * ldh + (j - 1) * m0 + a] = c;
+  Hr[idx] = (T)c;
 }
 
 // Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
@@ -170,13 +157,6 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y) {
   hipLaunchKernelGGL((k_to_T<T>), dim3(nblk(count)), dim3(256), 0, st, count, X, Y);
   IF_HIP(hipGetLastError());
 }
-template <class T>
-void launch_combine_real(hipStream_t st, int ni, int i0, int m0, int j, int ldh, const double* G, double* Hm,
-                         T* Hr, int accumulate) {
-  hipLaunchKernelGGL((k_combine_real<T>), dim3(nblk((int64_t)ni * m0 * m0)), dim3(256), 0, st, ni, i0, m0, j, ldh, G,
-                     Hm, Hr, accumulate);
-  IF_HIP(hipGetLastError());
-}
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out) {
   hipLaunchKernelGGL(k_sketch_check_real, dim3(1), dim3(128), 0, st, nk, m0, G, gw, out);
   IF_HIP(hipGetLastError());
@@ -186,10 +166,13 @@ void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, dou
   hipLaunchKernelGGL(k_gram_downdate, dim3(nt * nt), dim3(256), 0, st, rows, m0, C, gw);
   IF_HIP(hipGetLastError());
 }
-void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, const double* Hm, double* G0) {
-  hipLaunchKernelGGL(k_lanczos_prev, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh, Hm, G0);
+template <class T>
+void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, double* Hm, T* Hr) {
+  hipLaunchKernelGGL((k_lanczos_prev<T>), dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh, Hm, Hr);
   IF_HIP(hipGetLastError());
 }
+template void launch_lanczos_prev<float>(hipStream_t, int, int, int, double*, float*);
+template void launch_lanczos_prev<double>(hipStream_t, int, int, int, double*, double*);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {
   hipLaunchKernelGGL(k_subdiag_real, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh,
                      reinterpret_cast<const c2*>(Racc), Hm);
@@ -215,9 +198,6 @@ void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* 
 
 template void launch_to_T<float>(hipStream_t, int64_t, const double*, float*);
 template void launch_to_T<double>(hipStream_t, int64_t, const double*, double*);
-template void launch_combine_real<float>(hipStream_t, int, int, int, int, int, const double*, double*, float*, int);
-template void launch_combine_real<double>(hipStream_t, int, int, int, int, int, const double*, double*, double*,
-                                           int);
 template void launch_sum_y<float>(hipStream_t, int, int, int, int, const cd*, const double*, float*);
 template void launch_sum_y<double>(hipStream_t, int, int, int, int, const cd*, const double*, double*);
 

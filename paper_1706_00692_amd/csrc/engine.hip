@@ -329,7 +329,10 @@ struct Engine::Impl {
   int* d_need = nullptr;    // ns flags: second Gram-Schmidt pass needed
   int* d_single = nullptr;  // ns flags: one Cholesky-QR pass is enough
   int* d_two = nullptr;     // ns flags: two Cholesky-QR passes
-  double* d_loss = nullptr; // measured loss of orthogonality of the shared basis' newest block
+  double* d_loss = nullptr; // estimated loss of orthogonality of the shared basis' newest block,
+                            // followed by that step's one-pass / two-pass Cholesky-QR flags
+  int* d_single_sh = nullptr;
+  int* d_two_sh = nullptr;
   int* d_cnt = nullptr;     // blocks normalised with one Cholesky-QR pass (shared basis)
   double single_gersh = 0.5;
   double dead_thr = 1e-280;
@@ -435,6 +438,8 @@ struct Engine::Impl {
     d_two = f + 576;
     d_one = f + 640;
     d_loss = reinterpret_cast<double*>(f + 704);
+    d_single_sh = f + 706;
+    d_two_sh = f + 707;
     d_cnt = f + 720;
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
@@ -584,17 +589,17 @@ struct Engine::Impl {
     const int64_t n = sh.n;
     const int m0 = sh.m0;
     const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
-    if (certified < 0) launch_gersh_flags(st, m0, G0, single_gersh, dead_thr, d_single, d_two, d_cnt);
-    launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single, 0);
+    if (certified < 0) launch_gersh_flags(st, m0, G0, single_gersh, dead_thr, d_single_sh, d_two_sh, d_cnt);
+    launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single_sh, 0);
     ApplyArgs a1{n, m0, m0, 1, 1, 1, src, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
     launch_apply<T, T>(st, a1);
     if (certified == 1) return;
-    GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two, gred.as<double>(), -1};
+    GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two_sh, gred.as<double>(), -1};
     launch_gram<T>(st, g2, gpart.p, gpart.bytes);
-    launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single, 1);
-    ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two, nullptr, -1};
+    launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1);
+    ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
     launch_apply<T, T>(st, a2);
-    launch_copy_if<T>(st, d_two, n * m0, tmp, dst);
+    launch_copy_if<T>(st, d_two_sh, n * m0, tmp, dst);
   }
 
   // Inner solves of all shifts on one real block Arnoldi of M = -A (B = I):
@@ -709,10 +714,11 @@ struct Engine::Impl {
         // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass
         // changes the block by rounding only, or (a full pass) by at most reorth_eta per
         // column, which the margin on the Gershgorin bound covers
-        launch_gersh_flags(st, m0, gwb.as<double>(), single_gersh - 4.0 * thr, dead_thr, d_single, d_two, d_cnt);
+        launch_gersh_flags(st, m0, gwb.as<double>(), single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh,
+                           d_cnt);
+        // the estimate and the flags in one copy
         double* hchk = reinterpret_cast<double*>(h_flags + 128);
-        IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
-        IF_HIP(hipMemcpyAsync(h_flags + 192, d_single, sizeof(int), hipMemcpyDeviceToHost, st));
+        IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         IF_HIP(hipEventRecord(ev_chk, st));
         // the local second pass is needed in either case: it runs while the host waits
         gram(j, lo, nl, 1);
@@ -724,7 +730,7 @@ struct Engine::Impl {
         full = force_next || !(hchk[0] <= thr);
         force_next = full && !force_next;
         max_loss = std::max(max_loss, hchk[0]);
-        certified = h_flags[192] != 0 ? 1 : 0;
+        certified = h_flags[130] != 0 ? 1 : 0;
         if (full) {
           // a third pass against every block (the local blocks again: their coefficients are
           // rounding-sized), and the block's Gram afresh

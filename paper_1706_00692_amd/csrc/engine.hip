@@ -156,6 +156,9 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
 // ------------------------------------------------------------ workspace
 namespace {
 
+// Pinned staging bytes for the small uploads of one shared inner solve.
+constexpr size_t kStageBytes = 64 * 1024;
+
 // Columns of the random sketch that estimates the shared basis' loss of orthogonality.
 constexpr int kSketch = 16;
 
@@ -346,6 +349,8 @@ struct Engine::Impl {
   hipStream_t st_lsq = nullptr;
   hipEvent_t ev_main = nullptr, ev_lsq[2] = {nullptr, nullptr};
   int* h_flags = nullptr;  // pinned: 2 x 64 stop flags, then the step's check words
+  char* h_stage = nullptr;  // pinned staging of the shared inner solve's small uploads
+  size_t stage_off = 0;
   hipEvent_t ev_chk = nullptr;
   void side_stream() {
     if (st_lsq) return;
@@ -355,10 +360,12 @@ struct Engine::Impl {
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[1], hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_chk, hipEventDisableTiming));
     IF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_flags), 4 * 64 * sizeof(int), hipHostMallocDefault));
+    IF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_stage), kStageBytes, hipHostMallocDefault));
   }
   ~Impl() {
     if (st_lsq) (void)hipStreamSynchronize(st_lsq);
     if (h_flags) (void)hipHostFree(h_flags);
+    if (h_stage) (void)hipHostFree(h_stage);
     for (hipEvent_t e : {ev_main, ev_lsq[0], ev_lsq[1], ev_chk})
       if (e) (void)hipEventDestroy(e);
     if (st_lsq) (void)hipStreamDestroy(st_lsq);
@@ -552,6 +559,19 @@ struct Engine::Impl {
   void h2d(void* d, const void* h, size_t bytes) {
     IF_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
   }
+  // Asynchronous upload through the pinned staging area (no wait on the host).  The area is
+  // reused from the start by each shared inner solve: the previous one's uploads have
+  // completed by then (its results were read back).
+  void h2d_staged(void* d, const void* h, size_t bytes) {
+    const size_t at = (stage_off + 255) / 256 * 256;
+    if (at + bytes > kStageBytes) {
+      h2d(d, h, bytes);
+      return;
+    }
+    std::memcpy(h_stage + at, h, bytes);
+    IF_HIP(hipMemcpyAsync(d, h_stage + at, bytes, hipMemcpyHostToDevice, st));
+    stage_off = at + bytes;
+  }
 
   // ------------------------------------------------- shared real basis
   // Cholesky-QR of one real n x m0 block (two passes, the first shifted); G0: its Gram.
@@ -625,11 +645,13 @@ struct Engine::Impl {
       wf[2 * s] = f.real();
       wf[2 * s + 1] = f.imag();
     }
+    side_stream();
+    stage_off = 0;
     const std::vector<T> zero(4, (T)0);
-    h2d(zsT.p, zero.data(), zero.size() * sizeof(T));
-    h2d(zsD.p, zdv.data(), zdv.size() * sizeof(double));
-    h2d(wsD.p, wf.data(), wf.size() * sizeof(double));
-    h2d(tol.p, tolh.data(), tolh.size() * sizeof(double));
+    h2d_staged(zsT.p, zero.data(), zero.size() * sizeof(T));
+    h2d_staged(zsD.p, zdv.data(), zdv.size() * sizeof(double));
+    h2d_staged(wsD.p, wf.data(), wf.size() * sizeof(double));
+    h2d_staged(tol.p, tolh.data(), tolh.size() * sizeof(double));
     // A is symmetric, so in exact arithmetic A V_j has components along V_{j-1} and V_j only
     // (block Lanczos).  Each step projects W against those two blocks twice, and the second
     // pass projects against every block when W has lost more than reorth_eta of
@@ -652,8 +674,8 @@ struct Engine::Impl {
     cholqr2_real<T>(t1, t2, Vb);
     launch_start_rhs(st, ns, m0, Racc.as<cd>(), lamd, zsD.as<double>(), Ss.as<cd>());
     std::vector<int> all(ns, 1);
-    h2d(d_active, all.data(), ns * sizeof(int));
-    h2d(d_run, all.data(), ns * sizeof(int));
+    h2d_staged(d_active, all.data(), ns * sizeof(int));
+    h2d_staged(d_run, all.data(), ns * sizeof(int));
     note(d_active, all);
     LsqArgs la = lsq_args();
     // Hm is block tridiagonal up to rounding, so the least squares problems keep one block
@@ -681,13 +703,18 @@ struct Engine::Impl {
     bool force_next = false;  // the step after a triggered third pass takes one too
     int skip_checks = 0;      // steps left before the next orthogonality estimate
     const int zero_cnt = 0;
-    h2d(d_cnt, &zero_cnt, sizeof(int));
+    h2d_staged(d_cnt, &zero_cnt, sizeof(int));
     side_stream();
     int jdone = 0;
-    for (int j = 0; j < K; ++j) {
-      // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
-      // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike)
+    // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
+    // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike).
+    // Step j + 1's product is queued before the host reads the stop flags of step j - 1, so
+    // the device does not wait for that read (once per solve it is not used).
+    auto spmm_step = [&](int j) {
       launch_spmm_shifted<T>(st, A, nullptr, 1, m0 / 2, zsT.as<T>(), nullptr, Vb + (int64_t)j * bs, t1);
+    };
+    spmm_step(0);
+    for (int j = 0; j < K; ++j) {
       const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
       if (!always && j >= 1) {
         // first pass: the coefficients against V_{j-1} are those of the recurrence,
@@ -795,6 +822,7 @@ struct Engine::Impl {
       IF_HIP(hipMemcpyAsync(h_flags + (j & 1) * 64, d_active, ns * sizeof(int), hipMemcpyDeviceToHost, st_lsq));
       IF_HIP(hipEventRecord(ev_lsq[j & 1], st_lsq));
       jdone = j + 1;
+      if (j + 1 < K) spmm_step(j + 1);
       if (j >= 1) {
         // every shift had stopped after step j - 1: step j's update left the least squares
         // problems as they were (it skips stopped shifts), so the solution uses j blocks

@@ -701,6 +701,7 @@ struct Engine::Impl {
     T* U = Us.as<T>();
     if (!always) launch_fill_zero(st, Us.p, Us.bytes);
     bool force_next = false;  // the step after a triggered third pass takes one too
+    static const bool debug_reorth = getenv("IFEAST_DEBUG_REORTH") != nullptr;
     int skip_checks = 0;      // steps left before the next orthogonality estimate
     const int zero_cnt = 0;
     h2d_staged(d_cnt, &zero_cnt, sizeof(int));
@@ -779,7 +780,7 @@ struct Engine::Impl {
           // a third pass against every block (the local blocks again: their coefficients are
           // rounding-sized), and the block's Gram afresh
           gram(j, 0, j + 1, 1);
-          if (getenv("IFEAST_DEBUG_REORTH") != nullptr) {
+          if (debug_reorth) {
             std::vector<double> gh((size_t)(j + 1) * m0 * m0), wh((size_t)m0 * m0);
             IF_HIP(hipMemcpyAsync(gh.data(), gred.p, gh.size() * 8, hipMemcpyDeviceToHost, st));
             IF_HIP(hipMemcpyAsync(wh.data(), gwb.p, wh.size() * 8, hipMemcpyDeviceToHost, st));

@@ -1733,14 +1733,16 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
   size_t lds = ((size_t)m0 * (m0 + 1) / 2 + m0) * sizeof(c2);
-  if ((int64_t)lds + 2048 <= (int64_t)max_lds && getenv("IFEAST_CHOLQR_GLOBAL") == nullptr) {
+  static const bool force_global = getenv("IFEAST_CHOLQR_GLOBAL") != nullptr;
+  static const bool force_unblocked = getenv("IFEAST_CHOLQR_UNBLOCKED") != nullptr;
+  if ((int64_t)lds + 2048 <= (int64_t)max_lds && !force_global) {
     // the previous R factor beside L when there is room
     const size_t with_ra = lds + (size_t)m0 * m0 * sizeof(c2);
     const int ra_in_lds = (accumulate && (int64_t)with_ra + 2048 <= (int64_t)max_lds) ? 1 : 0;
     if (ra_in_lds) lds = with_ra;
     const size_t lds_real = ((size_t)m0 * (m0 + 1) + (size_t)m0 * m0 + 16 * (size_t)m0) * sizeof(double);
     if (real && m0 <= 80 && ns == 1 && active == nullptr && (int64_t)lds_real + 2048 <= (int64_t)max_lds &&
-        getenv("IFEAST_CHOLQR_UNBLOCKED") == nullptr) {
+        !force_unblocked) {
       if (lds_real > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
@@ -1901,7 +1903,8 @@ void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
   // packed slab in LDS when it fits the workgroup's LDS
   const size_t P = (size_t)a.m0 * a.m0 + (size_t)a.m0 * (a.m0 + 1) / 2;
   const size_t lds = (P + 2 * (size_t)a.m0) * sizeof(c2);
-  if ((int64_t)lds + 1024 <= (int64_t)max_lds && getenv("IFEAST_LSQ_GLOBAL") == nullptr) {
+  static const bool force_global = getenv("IFEAST_LSQ_GLOBAL") != nullptr;
+  if ((int64_t)lds + 1024 <= (int64_t)max_lds && !force_global) {
     if (lds > 64 * 1024)
       IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_qr_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -665,8 +665,9 @@ struct Engine::Impl {
     // an FP64 one
     const double thr = p.reorth_eta > 0.0 ? p.reorth_eta : (sizeof(T) == 4 ? std::max(1e-4, 0.1 * p.alpha) : 1e-12);
     reorth_eta = thr;
-    // one Cholesky-QR pass when the block's Gram certifies kappa <= 3 (orthonormal to ~9 u)
-    single_gersh = 0.5;
+    // one Cholesky-QR pass when the block's Gram certifies kappa <= 9 in FP32 (orthonormal to
+    // ~81 u, far below the orthogonality threshold) and kappa <= 3 in FP64
+    single_gersh = sizeof(T) == 4 ? 0.8 : 0.5;
     dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
     // Q = X rho_hat(Lambda); V_0 S0 = R
     launch_scale_cols(st, n, m0, Xd, rhod, Qd);

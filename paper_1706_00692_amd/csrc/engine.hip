@@ -605,18 +605,24 @@ struct Engine::Impl {
   template <class T>
   // certified: -1 unknown on the host (the flags are set here, on the device), 1 / 0: the
   // flags d_single / d_two were set earlier and the host read them (one pass / two passes).
-  void cholqr_adaptive_real(const T* src, T* tmp, T* dst, const double* G0, int certified = -1) {
+  // jstep >= 0: the final pass also writes the Lanczos outputs of step jstep (the subdiagonal
+  // block of Hm and, with Hr_next, the next step's recurrence coefficients).
+  void cholqr_adaptive_real(const T* src, T* tmp, T* dst, const double* G0, int certified = -1, int jstep = -1,
+                            int ldh = 0, T* Hr_next = nullptr) {
     const int64_t n = sh.n;
     const int m0 = sh.m0;
     const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
+    double* hm = jstep >= 0 ? Hm.as<double>() : nullptr;
     if (certified < 0) launch_gersh_flags(st, m0, G0, single_gersh, dead_thr, d_single_sh, d_two_sh, d_cnt);
-    launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single_sh, 0);
+    launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single_sh, 0, hm, ldh,
+                              jstep, Hr_next);
     ApplyArgs a1{n, m0, m0, 1, 1, 1, src, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
     launch_apply<T, T>(st, a1);
     if (certified == 1) return;
     GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two_sh, gred.as<double>(), -1};
     launch_gram<T>(st, g2, gpart.p, gpart.bytes);
-    launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1);
+    launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1, hm,
+                              ldh, jstep, Hr_next);
     ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
     launch_apply<T, T>(st, a2);
     launch_copy_if<T>(st, d_two_sh, n * m0, tmp, dst);
@@ -720,8 +726,8 @@ struct Engine::Impl {
       const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
       if (!always && j >= 1) {
         // first pass: the coefficients against V_{j-1} are those of the recurrence,
-        // V_{j-1}^T M V_j = (M V_{j-1})^T V_j = Hm(j, j-1)^T, so only V_j^T W is formed
-        launch_lanczos_prev<T>(st, m0, j, ldh, Hm.as<double>(), Hr.as<T>());
+        // V_{j-1}^T M V_j = (M V_{j-1})^T V_j = Hm(j, j-1)^T, so only V_j^T W is formed (the
+        // previous step's Cholesky-QR wrote Hm(j, j-1)^T into Hm and the coefficient buffer)
         gram(j, j, 1, 0, 1);
       } else {
         gram(j, lo, nl, 0);
@@ -809,11 +815,13 @@ struct Engine::Impl {
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
       }
       T* dst = Vb + (int64_t)(j + 1) * bs;
-      if (always)
+      if (always) {
         cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
-      else
-        cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified);
-      launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
+        launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
+      } else {
+        cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified, j, ldh,
+                                j + 1 < K ? Hr.as<T>() : nullptr);
+      }
       // the shifts' least squares updates of step j run on the side stream, beside step
       // j + 1's basis work; their stop flags are read one step later
       IF_HIP(hipEventRecord(ev_main, st));

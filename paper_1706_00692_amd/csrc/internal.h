@@ -209,10 +209,13 @@ void launch_apply(hipStream_t st, const ApplyArgs& a);
 //   W = W_new Rf); if `accumulate`, Racc = Rf * Racc_prev.  real: G is the m0 x m0
 //   Gram of a real block and Tinv real m0 x m0 (Rf then has zero imaginary parts).
 // The blocked real factor (one block, m0 <= 80) steered by a device flag: single[0] != 0
-// makes the first pass (role 0) unshifted and the second (role 1) a no-op.
+// makes the first pass (role 0) unshifted and the second (role 1) a no-op.  Hm != null: the
+// final pass writes Hm(jstep+1, jstep) = R; Hr_next != null: also its transpose into block
+// column jstep+1 (rows of block jstep) and into Hr_next (m0 x m0, Gram layout).
 template <class T>
 void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shift_rel, T* Tinv, cd* Racc,
-                            int accumulate, const int* single, int role);
+                            int accumulate, const int* single, int role, double* Hm = nullptr, int ldh = 0,
+                            int jstep = 0, T* Hr_next = nullptr);
 // single[0] / two[0]: one Cholesky-QR pass is enough for the block with Gram G (m0 x m0, real)
 // or not; count[0] (may be null) counts the certified blocks
 void launch_gersh_flags(hipStream_t st, int m0, const double* G, double gersh, double dead_thr, int* single, int* two,

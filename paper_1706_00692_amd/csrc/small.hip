@@ -349,14 +349,22 @@ template <class T>
 __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __restrict__ G, double shift_rel,
                                                      double dead_thr, double tau_dep, T* __restrict__ Tinv,
                                                      c2* __restrict__ Racc, int accumulate,
-                                                     const int* __restrict__ single, int role) {
+                                                     const int* __restrict__ single, int role,
+                                                     double* __restrict__ Hm, int ldh, int jstep,
+                                                     T* __restrict__ Hr_next) {
   // single[0] != 0 (the Gram is certified well conditioned): the first pass (role 0) runs
   // unshifted and the second (role 1) is not needed
+  bool final_pass = role == 1;
   if (single != nullptr && single[0] != 0) {
     if (role == 1) return;
     shift_rel = 0.0;
     tau_dep = 0.25 * m0 * (sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    final_pass = true;
   }
+  // Hm != null: the final pass also writes the new subdiagonal block Hm(j+1, j) = R; with
+  // Hr_next != null also its transpose into rows j m0.. of block column j+1 and into Hr_next
+  // (the next step's first-pass coefficients against V_j, which the recurrence gives)
+  const bool lanczos_out = Hm != nullptr && final_pass;
   constexpr int NB = 16;
   extern __shared__ double lds_d[];
   // rows of L padded to an odd number of doubles: column walks hit distinct LDS banks
@@ -450,6 +458,13 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
         v = dsc[b] * L[b * ldl + a];
     }
     Racc[idx] = make_double2(v, 0.0);
+    if (lanczos_out) {
+      Hm[(int64_t)(jstep * m0 + b) * ldh + (jstep + 1) * m0 + a] = v;
+      if (Hr_next != nullptr) {
+        Hm[(int64_t)((jstep + 1) * m0 + a) * ldh + jstep * m0 + b] = v;
+        Hr_next[b * m0 + a] = (T)v;
+      }
+    }
   }
   __syncthreads();
   // ---- 4a. invert the diagonal blocks, one wave each (in place)
@@ -1747,7 +1762,7 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
       hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep,
-                         Tinv, reinterpret_cast<c2*>(Racc), accumulate, nullptr, 0);
+                         Tinv, reinterpret_cast<c2*>(Racc), accumulate, nullptr, 0, nullptr, 0, 0, nullptr);
     } else if (real) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T, true>),
@@ -1810,7 +1825,8 @@ __global__ void k_copy_if(const int* __restrict__ flag, int64_t count, const T* 
 
 template <class T>
 void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shift_rel, T* Tinv, cd* Racc,
-                            int accumulate, const int* single, int role) {
+                            int accumulate, const int* single, int role, double* Hm, int ldh, int jstep,
+                            T* Hr_next) {
   IF_REQUIRE(m0 <= 80, "cholqr: m0 > 80 for the blocked real factor");
   const double dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
   const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
@@ -1820,13 +1836,13 @@ void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shif
     IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
   hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep, Tinv,
-                     reinterpret_cast<c2*>(Racc), accumulate, single, role);
+                     reinterpret_cast<c2*>(Racc), accumulate, single, role, Hm, ldh, jstep, Hr_next);
   IF_HIP(hipGetLastError());
 }
 template void launch_cholqr_real_ctl<float>(hipStream_t, int, const double*, double, float*, cd*, int, const int*,
-                                            int);
+                                            int, double*, int, int, float*);
 template void launch_cholqr_real_ctl<double>(hipStream_t, int, const double*, double, double*, cd*, int,
-                                             const int*, int);
+                                             const int*, int, double*, int, int, double*);
 
 void launch_gersh_flags(hipStream_t st, int m0, const double* G, double gersh, double dead_thr, int* single, int* two,
                         int* count) {

@@ -399,29 +399,40 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
   for (int p = 0; p < P; ++p) {
     const int c0 = p * NB;
     if (wave == 0) {
-      for (int c = c0; c < c0 + NB; ++c) {
-        const double pv0 = L[c * ldl + c];
-        const bool dc = dead[c] != 0 || !(pv0 > tau_dep);
+      // the diagonal block in registers: lane i < 16 holds row i; the column entries other
+      // lanes need come by lane shuffles, so the 16 dependent column steps touch no LDS
+      const int i = lane;
+      double arow[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) arow[q] = i < NB ? L[(c0 + i) * ldl + c0 + q] : 0.0;
+      int my_dead = 0;
+      double my_dinv = 1.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double pv0 = __shfl(arow[c], c);
+        const bool dc = dead[c0 + c] != 0 || !(pv0 > tau_dep);
         const double pv = dc ? 1.0 : sqrt(pv0);
         const double rpv = 1.0 / pv;
-        if (lane < c0 + NB - c - 1) {
-          const int r = c + 1 + lane;
-          L[r * ldl + c] = dc ? 0.0 : L[r * ldl + c] * rpv;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane == 0) {
-          dead[c] = dc ? 1 : 0;
-          L[c * ldl + c] = pv;
-          dinv[c] = rpv;
+        if (i > c) arow[c] = dc ? 0.0 : arow[c] * rpv;
+        if (i == c) {
+          arow[c] = pv;
+          my_dead = dc ? 1 : 0;
+          my_dinv = rpv;
         }
         if (!dc) {
-          const int nt = c0 + NB - c - 1;
-          for (int t = lane; t < nt * nt; t += 64) {
-            const int rr = c + 1 + t / nt, q = c + 1 + t % nt;
-            if (q <= rr) L[rr * ldl + q] -= L[rr * ldl + c] * L[q * ldl + c];
+#pragma unroll
+          for (int q = c + 1; q < NB; ++q) {
+            const double lqc = __shfl(arow[c], q);
+            if (q <= i) arow[q] -= arow[c] * lqc;
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+      if (i < NB) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q <= i) L[(c0 + i) * ldl + c0 + q] = arow[q];
+        dead[c0 + i] = my_dead;
+        dinv[c0 + i] = my_dinv;
       }
     }
     __syncthreads();
@@ -708,12 +719,14 @@ __global__ __launch_bounds__(256) void k_lsq_init(LsqArgs a, const c2* __restric
   }
 }
 
-// Step j, part 1: the reflectors of steps 0..j-1 on the new block column j of Hbar.
-// grid (ns, ceil(m0/4)); wave w of block y owns column 4y + w, staged in LDS (in place
-// in global memory when the column is too long for LDS).
+// Step j, part 1: the reflectors of steps i0..j-1 on the new block column j of Hbar
+// (i0 = 0, or j - band - 1 for a banded Hbar).  Reflector block i acts on rows
+// [i m0, (i+2) m0), so only rows [i0 m0, (j+1) m0) change.  grid (ns, ceil(m0/4)); wave w
+// of block y owns column 4y + w, whose changing rows are staged in LDS (updated in place
+// in global memory when they do not fit).
 template <bool GLOBAL>
 __global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
-  extern __shared__ c2 colbuf[];  // 4 x (j+2) m0
+  extern __shared__ c2 colbuf[];  // 4 x (j + 1 - i0) m0
   const int s = blockIdx.x;
   if (a.active[s] == 0 || j == 0) return;
   const LsqView v = lsq_view(a, s);
@@ -721,15 +734,16 @@ __global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = blockIdx.y * 4 + wave;
   if (col >= m0) return;
-  const int rows = (j + 2) * m0;
-  c2* h = v.H + (int64_t)(j * m0 + col) * ldh;
-  c2* x = GLOBAL ? h : colbuf + wave * rows;
+  const int i0 = a.band > 0 ? max(0, j - a.band - 1) : 0;
+  const int r0 = i0 * m0, rows = (j + 1) * m0 - r0;
+  c2* h = v.H + (int64_t)(j * m0 + col) * ldh + r0;
+  c2* x = GLOBAL ? h : colbuf + wave * rows;  // x[r] is row r0 + r
   if (!GLOBAL) {
     for (int r = lane; r < rows; r += 64) x[r] = h[r];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-  for (int i = a.band > 0 ? max(0, j - a.band - 1) : 0; i < j; ++i)
-    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + i * m0, lane, false);
+  for (int i = i0; i < j; ++i)
+    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + (i - i0) * m0, lane, false);
   if (!GLOBAL)
     for (int r = lane; r < rows; r += 64) h[r] = x[r];
 }
@@ -1905,7 +1919,8 @@ void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
   if (j > 0) {
-    const size_t lds = (size_t)4 * (j + 2) * a.m0 * sizeof(c2);
+    const int i0 = a.band > 0 ? std::max(0, j - a.band - 1) : 0;
+    const size_t lds = (size_t)4 * (j + 1 - i0) * a.m0 * sizeof(c2);
     if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_prev<false>),

@@ -436,13 +436,19 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       }
     }
     __syncthreads();
-    // rows below the diagonal block: x L11^T = a, forward along the panel's columns
+    // rows below the diagonal block: x L11^T = a, forward along the panel's columns (the
+    // row's solved entries stay in registers)
     for (int r = c0 + NB + tid; r < m0; r += nth) {
-      for (int c = c0; c < c0 + NB; ++c) {
-        double v = L[r * ldl + c];
-        for (int k = c0; k < c; ++k) v -= L[r * ldl + k] * L[c * ldl + k];
-        L[r * ldl + c] = dead[c] ? 0.0 : v * dinv[c];
+      double xr[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        double v = L[r * ldl + c0 + c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) v -= xr[k] * L[(c0 + c) * ldl + c0 + k];
+        xr[c] = dead[c0 + c] ? 0.0 : v * dinv[c0 + c];
       }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) L[r * ldl + c0 + c] = xr[c];
     }
     __syncthreads();
     // trailing matrix, lower triangle
@@ -482,19 +488,28 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
   RR_MARK(19);
   for (int p = wave; p < P; p += nth / 64) {
     const int c0 = p * NB;
-    const int i = lane;  // row of the block (lanes 16..63 idle)
+    const int i = lane;  // row of the block (lanes 16..63 idle), held in registers
+    double xrow[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) xrow[q] = (i < NB && q <= i) ? L[(c0 + i) * ldl + c0 + q] : 0.0;
+    // column j of the inverse from columns j+1.. (rows of the inverse in registers) and
+    // column j of L (still unchanged in the registers of lanes k > j)
+#pragma unroll
     for (int j = NB - 1; j >= 0; --j) {
-      const double ljj = L[(c0 + j) * ldl + c0 + j];
-      const double xi = (i > j && i < NB) ? L[(c0 + i) * ldl + c0 + j] : 0.0;
+      const double ljj = __shfl(xrow[j], j);
       double v = 0.0;
+#pragma unroll
       for (int k = j + 1; k < NB; ++k) {
-        const double xk = __shfl(xi, k);
-        if (i < NB && k <= i) v += L[(c0 + i) * ldl + c0 + k] * xk;
+        const double lkj = __shfl(xrow[j], k);
+        if (k <= i) v += xrow[k] * lkj;
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (i > j && i < NB) L[(c0 + i) * ldl + c0 + j] = -v / ljj;
-      if (i == j) L[(c0 + j) * ldl + c0 + j] = 1.0 / ljj;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (i > j && i < NB) xrow[j] = -v / ljj;
+      if (i == j) xrow[j] = 1.0 / ljj;
+    }
+    if (i < NB) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if (q <= i) L[(c0 + i) * ldl + c0 + q] = xrow[q];
     }
   }
   __syncthreads();

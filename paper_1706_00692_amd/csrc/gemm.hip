@@ -183,8 +183,8 @@ __global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, con
   double sum = 0.0;
   if (on) {
     const T* p = partial + (int64_t)item * nsplit * per_item + idx % per_item;
-    // unrolled so that eight loads are in flight before the (in-order) additions
-#pragma unroll 8
+    // unrolled so that sixteen loads are in flight before the (in-order) additions
+#pragma unroll 16
     for (int sp = part; sp < nsplit; sp += 8) sum += (double)p[(int64_t)sp * per_item];
   }
   sum += __shfl_xor(sum, 1);

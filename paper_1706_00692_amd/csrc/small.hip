@@ -451,15 +451,20 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       for (int c = 0; c < NB; ++c) L[r * ldl + c0 + c] = xr[c];
     }
     __syncthreads();
-    // trailing matrix, lower triangle
-    const int t0 = c0 + NB, nt = m0 - t0;
-    for (int idx = tid; idx < nt * nt; idx += nth) {
-      const int r = t0 + idx / nt, q = t0 + idx % nt;
-      if (q > r) continue;
-      double v = 0.0;
+    // trailing matrix, lower triangle: lane -> column q (its panel row in registers), wave ->
+    // every (nth/64)-th row r, whose panel row all lanes read at one LDS address
+    const int t0 = c0 + NB;
+    for (int q = t0 + lane; q < m0; q += 64) {
+      double lq[NB];
 #pragma unroll
-      for (int k = 0; k < NB; ++k) v += L[r * ldl + c0 + k] * L[q * ldl + c0 + k];
-      L[r * ldl + q] -= v;
+      for (int k = 0; k < NB; ++k) lq[k] = L[q * ldl + c0 + k];
+      for (int r = t0 + wave; r < m0; r += nth / 64) {
+        if (q > r) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) v += L[r * ldl + c0 + k] * lq[k];
+        L[r * ldl + q] -= v;
+      }
     }
     __syncthreads();
   }

@@ -335,6 +335,15 @@ __global__ __launch_bounds__(512) void k_cholqr_lds(int m0, const double* __rest
   }
 }
 
+// Lane l's value of v in every lane (l wave-uniform; the whole wave active): two scalar reads
+// of the register halves instead of a lane permute through the LDS unit.
+__device__ inline double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Real-block factor (the shared basis), blocked by 16-column panels so that it needs a few
 // dozen block barriers instead of several per column.  L (m0 x m0, row-major) in LDS:
 //  1. unit-diagonal scaled Gram (+ shift), dead columns as identity;
@@ -400,7 +409,7 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     const int c0 = p * NB;
     if (wave == 0) {
       // the diagonal block in registers: lane i < 16 holds row i; the column entries other
-      // lanes need come by lane shuffles, so the 16 dependent column steps touch no LDS
+      // lanes need are broadcast from their lanes, so the 16 dependent column steps touch no LDS
       const int i = lane;
       double arow[NB];
 #pragma unroll
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       double my_dinv = 1.0;
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        const double pv0 = __shfl(arow[c], c);
+        const double pv0 = lane_bcast(arow[c], c);
         const bool dc = dead[c0 + c] != 0 || !(pv0 > tau_dep);
         const double pv = dc ? 1.0 : sqrt(pv0);
         const double rpv = 1.0 / pv;
@@ -422,7 +431,7 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
         if (!dc) {
 #pragma unroll
           for (int q = c + 1; q < NB; ++q) {
-            const double lqc = __shfl(arow[c], q);
+            const double lqc = lane_bcast(arow[c], q);
             if (q <= i) arow[q] -= arow[c] * lqc;
           }
         }
@@ -501,11 +510,11 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     // column j of L (still unchanged in the registers of lanes k > j)
 #pragma unroll
     for (int j = NB - 1; j >= 0; --j) {
-      const double ljj = __shfl(xrow[j], j);
+      const double ljj = lane_bcast(xrow[j], j);
       double v = 0.0;
 #pragma unroll
       for (int k = j + 1; k < NB; ++k) {
-        const double lkj = __shfl(xrow[j], k);
+        const double lkj = lane_bcast(xrow[j], k);
         if (k <= i) v += xrow[k] * lkj;
       }
       if (i > j && i < NB) xrow[j] = -v / ljj;

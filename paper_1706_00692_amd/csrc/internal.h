@@ -269,9 +269,6 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 // gw -= C^T C (C: rows x m0): the Gram of a block after projecting out orthonormal directions
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw);
-// first-pass coefficients against V_{j-1}: Hm(j, j-1)^T into block column j of Hm and Hr
-template <class T>
-void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, double* Hm, T* Hr);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
 // block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
 void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,

@@ -58,17 +58,19 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
 
 // Gram of the block after a projection W2 = W1 - V C with orthonormal V: W2^T W2 =
 // W1^T W1 - C^T C.  gw (m0 x m0) holds W1^T W1 on entry; C has `rows` rows of m0.
-// One workgroup per 16 x 16 tile of gw; rows staged through LDS 64 at a time.
+// One workgroup per 16 x 16 tile of gw; rows staged through LDS 160 at a time.
 __global__ __launch_bounds__(256) void k_gram_downdate(int rows, int m0, const double* __restrict__ C,
                                                        double* __restrict__ gw) {
-  __shared__ double ca[64][17], cb[64][17];
+  // chunks of KR rows: the two-block case (2 x 80 rows) is one chunk, so its loads overlap
+  constexpr int KR = 160;
+  __shared__ double ca[KR][17], cb[KR][17];
   const int nt = (m0 + 15) / 16;
   const int ta = blockIdx.x / nt, tb = blockIdx.x % nt;
   const int a0 = ta * 16, b0 = tb * 16;
   const int tid = threadIdx.x, ia = tid >> 4, ib = tid & 15;
   double acc = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += 64) {
-    for (int idx = tid; idx < 64 * 16; idx += 256) {
+  for (int r0 = 0; r0 < rows; r0 += KR) {
+    for (int idx = tid; idx < KR * 16; idx += 256) {
       const int r = idx >> 4, c = idx & 15;
       const bool in = r0 + r < rows;
       ca[r][c] = (in && a0 + c < m0) ? C[(int64_t)(r0 + r) * m0 + a0 + c] : 0.0;
@@ -76,23 +78,10 @@ __global__ __launch_bounds__(256) void k_gram_downdate(int rows, int m0, const d
     }
     __syncthreads();
 #pragma unroll 8
-    for (int r = 0; r < 64; ++r) acc += ca[r][ia] * cb[r][ib];
+    for (int r = 0; r < KR; ++r) acc += ca[r][ia] * cb[r][ib];
     __syncthreads();
   }
   if (a0 + ia < m0 && b0 + ib < m0) gw[(a0 + ia) * m0 + b0 + ib] -= acc;
-}
-
-// First-pass coefficients of W = M V_j against V_{j-1}: Hm(j, j-1)^T (the transpose of the
-// previous step's subdiagonal block, M symmetric), into rows (j-1) m0.. of block column j of
-// Hm and into the update factors Hr (item 0, Gram layout: row a = basis column).
-template <class T>
-__global__ void k_lanczos_prev(int m0, int j, int ldh, double* __restrict__ Hm, T* __restrict__ Hr) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m0 * m0) return;
-  const int a = idx / m0, b = idx % m0;
-  const double c = Hm[(int64_t)((j - 1) * m0 + a) * ldh + j * m0 + b];
-  Hm[(int64_t)(j * m0 + b) * ldh + (j - 1) * m0 + a] = c;
-  Hr[idx] = (T)c;
 }
 
 // Hm block (j+1, j) = R factor of the new block (real part of Racc, upper triangular).
@@ -166,13 +155,6 @@ void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, dou
   hipLaunchKernelGGL(k_gram_downdate, dim3(nt * nt), dim3(256), 0, st, rows, m0, C, gw);
   IF_HIP(hipGetLastError());
 }
-template <class T>
-void launch_lanczos_prev(hipStream_t st, int m0, int j, int ldh, double* Hm, T* Hr) {
-  hipLaunchKernelGGL((k_lanczos_prev<T>), dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh, Hm, Hr);
-  IF_HIP(hipGetLastError());
-}
-template void launch_lanczos_prev<float>(hipStream_t, int, int, int, double*, float*);
-template void launch_lanczos_prev<double>(hipStream_t, int, int, int, double*, double*);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {
   hipLaunchKernelGGL(k_subdiag_real, dim3(nblk((int64_t)m0 * m0)), dim3(256), 0, st, m0, j, ldh,
                      reinterpret_cast<const c2*>(Racc), Hm);

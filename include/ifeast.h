@@ -43,8 +43,9 @@ extern "C" {
 enum {
   IFEAST_OK = 0,
   IFEAST_WARN_NOT_CONVERGED = 1,   /* max_outer reached; results are the last iterate */
-  IFEAST_WARN_M0_TOO_SMALL = 2,    /* as many counted pairs inside C as m0 (premise of Algorithm 2 violated) */
-  IFEAST_WARN_NO_EIG_IN_CONTOUR = 3, /* converged with no counted pair inside C */
+  IFEAST_WARN_M0_TOO_SMALL = 2,    /* after an outer iteration all m0 Ritz values lie inside C (the premise of
+                                      Algorithm 2, fewer than m0 eigenvalues inside, fails); the solve stops */
+  IFEAST_WARN_NO_EIG_IN_CONTOUR = 3, /* after an outer iteration no Ritz value lies inside C; the solve stops */
   IFEAST_ERR_INVALID_ARG = -1,
   IFEAST_ERR_OOM = -2,
   IFEAST_ERR_DEVICE = -3,

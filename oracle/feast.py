@@ -140,6 +140,7 @@ class IFeastResult:
     total_matvec: int = 0
     seq_matvec: int = 0
     spurious: np.ndarray = None  # bool mask: inside the contour but failing the filter-gain test
+    status: str = "not_converged"  # "ok", "not_converged", "m0_too_small" or "no_eig"
 
     @property
     def lam_in(self):
@@ -181,7 +182,11 @@ def ifeast(A, B, contour: dict, m0: int, max_inner: int, alpha: float, tol: floa
     its residual drops by alpha relative to its start (alpha_j = alpha for
     every eigenvector, Eq. alpha).  ``max_cycles`` restart cycles at most.
     Stops when a counted pair is inside the contour and ||R_F|| <= tol, or
-    after ``max_outer`` outer iterations.
+    after ``max_outer`` outer iterations.  Two early exits test the premise
+    of Algorithm 2 (fewer than m0 eigenvalues inside the contour, and at
+    least one) on the Ritz values after a filter application: all m0 of them
+    inside the contour means m0 is too small ("m0_too_small"), none inside
+    means the contour holds no eigenvalue ("no_eig").
     """
     A = _sparse(A)
     B = _sparse(B)
@@ -227,8 +232,16 @@ def ifeast(A, B, contour: dict, m0: int, max_inner: int, alpha: float, tol: floa
         res.outer_iters = it + 1
         if callback is not None:
             callback(it, lam, r, ins, rf)
+        geo = inside_contour(lam, contour)
         if ins.any() and rf <= tol:
             res.converged = True
+            res.status = "m0_too_small" if ins.sum() >= m0 else "ok"
+            break
+        if geo.all():
+            res.status = "m0_too_small"
+            break
+        if not geo.any():
+            res.status = "no_eig"
             break
     res.lam, res.X, res.resid, res.inside, res.m = lam, X, r, ins, int(ins.sum())
     res.spurious = spur

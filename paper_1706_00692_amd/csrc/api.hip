@@ -134,6 +134,14 @@ void drop_engine(ifeast_ctx* ctx) {
 }
 }  // namespace
 
+namespace ifeast {
+void release_engine(ifeast_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard g(ctx->device);
+  drop_engine(ctx);
+}
+}  // namespace ifeast
+
 extern "C" {
 
 const char* ifeast_version(void) { return "libifeast 0.1 (gfx950)"; }

@@ -622,7 +622,7 @@ struct Engine::Impl {
     GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two_sh, gred.as<double>(), -1};
     launch_gram<T>(st, g2, gpart.p, gpart.bytes);
     launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1, hm,
-                              ldh, jstep, Hr_next);
+                              ldh, jstep, Hr_next, chol.as<double>());
     ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
     launch_apply<T, T>(st, a2);
     launch_copy_if<T>(st, d_two_sh, n * m0, tmp, dst);
@@ -1154,16 +1154,17 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   double* eta = I.eta.as<double>();
   double* R = I.R.as<double>();
   SolveStats stats;
-  std::vector<double> lamh(m0), residh(m0), cls(2);
+  std::vector<double> lamh(m0), residh(m0), cls(3);
+  int geo_count = 0;  // Ritz values inside the contour, counted or not
   std::vector<int> flagh(m0);
 
   auto classify = [&](double tau) {
     const ClassifyArgs ca = classify_args(C, nd, m0, tau, zb.as<double>(), wb.as<double>());
-    launch_classify(st_, ca, lam, resid, eta, I.d_cls, I.clsout.as<double>());
+    launch_classify(st_, ca, lam, nullptr, resid, eta, I.d_cls, I.clsout.as<double>());
     hipLaunchKernelGGL(k_rho, dim3(1), dim3(128), 0, st_, m0, ns, nd.half ? 1 : 0, zb.as<double>(), wb.as<double>(),
                        lam, I.rho.as<double>());
     IF_HIP(hipGetLastError());
-    IF_HIP(hipMemcpyAsync(cls.data(), I.clsout.p, 16, hipMemcpyDeviceToHost, st_));
+    IF_HIP(hipMemcpyAsync(cls.data(), I.clsout.p, 24, hipMemcpyDeviceToHost, st_));
     IF_HIP(hipMemcpyAsync(lamh.data(), lam, m0 * 8, hipMemcpyDeviceToHost, st_));
     IF_HIP(hipMemcpyAsync(residh.data(), resid, m0 * 8, hipMemcpyDeviceToHost, st_));
     IF_HIP(hipMemcpyAsync(flagh.data(), I.d_cls, m0 * 4, hipMemcpyDeviceToHost, st_));
@@ -1173,6 +1174,7 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         throw Error{IFEAST_ERR_NUMERICAL, "non-finite Ritz value or residual"};
     stats.rf = cls[0];
     stats.m = (int)cls[1];
+    geo_count = (int)cls[2];
   };
 
   const char* vb = getenv("IFEAST_VERBOSE");
@@ -1238,7 +1240,18 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     }
     if (stats.m > 0 && stats.rf <= p.tol) {
       stats.converged = 1;
-      status = IFEAST_OK;
+      status = stats.m >= m0 ? IFEAST_WARN_M0_TOO_SMALL : IFEAST_OK;
+      break;
+    }
+    // the premise of Algorithm 2 ("Start with"): fewer than m0 eigenvalues inside the contour
+    // and at least one.  After a filter application, every Ritz value inside means the subspace
+    // has no room for the eigenvalues outside; none inside means the contour holds none
+    if (geo_count >= m0) {
+      status = IFEAST_WARN_M0_TOO_SMALL;
+      break;
+    }
+    if (geo_count == 0) {
+      status = IFEAST_WARN_NO_EIG_IN_CONTOUR;
       break;
     }
   }
@@ -1249,8 +1262,6 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   stats.seconds = ms * 1e-3;
-  if (stats.converged && stats.m == 0) status = IFEAST_WARN_NO_EIG_IN_CONTOUR;
-  if (stats.m >= m0) status = IFEAST_WARN_M0_TOO_SMALL;
 
   // outputs: counted pairs first (ascending), then the rest (ascending)
   std::vector<int> order;

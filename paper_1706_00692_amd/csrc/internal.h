@@ -208,14 +208,15 @@ void launch_apply(hipStream_t st, const ApplyArgs& a);
 //   Cholesky -> Tinv (real-ified, type T, 2m0 x 2m0) and Rf (complex m0 x m0,
 //   W = W_new Rf); if `accumulate`, Racc = Rf * Racc_prev.  real: G is the m0 x m0
 //   Gram of a real block and Tinv real m0 x m0 (Rf then has zero imaginary parts).
-// The blocked real factor (one block, m0 <= 80) steered by a device flag: single[0] != 0
+// The blocked real factor (one block, m0 <= 128; scratch: m0 x m0 doubles of global memory for
+// the previous R when it does not fit in LDS beside the factor) steered by a device flag: single[0] != 0
 // makes the first pass (role 0) unshifted and the second (role 1) a no-op.  Hm != null: the
 // final pass writes Hm(jstep+1, jstep) = R; Hr_next != null: also its transpose into block
 // column jstep+1 (rows of block jstep) and into Hr_next (m0 x m0, Gram layout).
 template <class T>
 void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shift_rel, T* Tinv, cd* Racc,
                             int accumulate, const int* single, int role, double* Hm = nullptr, int ldh = 0,
-                            int jstep = 0, T* Hr_next = nullptr);
+                            int jstep = 0, T* Hr_next = nullptr, double* scratch = nullptr);
 // single[0] / two[0]: one Cholesky-QR pass is enough for the block with Gram G (m0 x m0, real)
 // or not; count[0] (may be null) counts the certified blocks
 void launch_gersh_flags(hipStream_t st, int m0, const double* G, double gersh, double dead_thr, int* single, int* two,
@@ -296,15 +297,16 @@ void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB,
                      double* eta, double* work);
 
 // Membership, spurious test and ||R_F|| (Algorithm 2, step 4) on device:
-// flags[j] = IFEAST_FLAG_* bits; out[0] = ||R_F||, out[1] = m (as double).
+// flags[j] = IFEAST_FLAG_* bits; out[0] = ||R_F||, out[1] = m (as double), out[2] = Ritz
+// values inside the contour whether counted or not.  lam_im (may be null): imaginary parts.
 struct ClassifyArgs {
   int m0, nc, half, kind;  // kind: IFEAST_CONTOUR_*
   double emin, emax, c_re, c_im, r, tau;
   const double* z;  // device 2*nc
   const double* w;  // device 2*nc
 };
-void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* resid,
-                     const double* eta, int* flags, double* out);
+void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* lam_im,
+                     const double* resid, const double* eta, int* flags, double* out);
 
 // ---- elementwise / reductions
 void launch_col_sumsq(hipStream_t st, int64_t n, int m, const double* X, double* out /*m*/, double* partial);

@@ -5,7 +5,6 @@
 namespace ifeast {
 
 namespace {
-constexpr int kMaxResident = 8;  // requests in flight on the device at once
 using clock_t_ = std::chrono::steady_clock;
 }  // namespace
 
@@ -27,17 +26,37 @@ struct Request {
   std::vector<int32_t> flags, inner_hist;
 };
 
-Server::Server(ifeast_ctx* ctx) : ctx_(ctx) { dispatcher_ = std::thread([this] { dispatch_loop(); }); }
+namespace {
+// Requests whose solves allocate the same workspace (so a worker can keep it).
+bool same_shape(const Request& a, const Request& b) {
+  return a.n == b.n && a.hasB == b.hasB && a.C.nc == b.C.nc && a.p.m0 == b.p.m0 && a.p.max_inner == b.p.max_inner &&
+         a.p.max_cycles == b.p.max_cycles && a.p.precision == b.p.precision && a.p.basis == b.p.basis &&
+         a.p.problem == b.p.problem && a.footprint == b.footprint;
+}
+}  // namespace
+
+Server::Server(ifeast_ctx* ctx) : ctx_(ctx) {
+  for (int i = 0; i < kWorkers; ++i) workers_.emplace_back([this] { worker_loop(); });
+}
 
 Server::~Server() {
-  {
-    std::lock_guard<std::mutex> lk(mu_);
-    stop_ = true;
+  std::unique_lock<std::mutex> lk(mu_);
+  stop_ = true;
+  // queued requests will not run: fail them and wake their waiters
+  for (Request* r : queue_) {
+    r->status = IFEAST_ERR_DEVICE;
+    r->error = "context destroyed before the request ran";
+    r->t_done = clock_t_::now();
+    r->done = true;
   }
+  queue_.clear();
   cv_.notify_all();
-  if (dispatcher_.joinable()) dispatcher_.join();
+  lk.unlock();
   for (auto& t : workers_)
     if (t.joinable()) t.join();
+  // running requests are done now; let every thread inside wait() leave before the state goes
+  lk.lock();
+  cv_.wait(lk, [this] { return waiters_ == 0; });
 }
 
 uint64_t Server::submit(const ifeast_csr* A, const ifeast_csr* B, const ifeast_contour& C, const ifeast_params& p,
@@ -68,6 +87,7 @@ uint64_t Server::submit(const ifeast_csr* A, const ifeast_csr* B, const ifeast_c
   }
   r->t_submit = clock_t_::now();
   std::lock_guard<std::mutex> lk(mu_);
+  if (stop_) throw Error{IFEAST_ERR_DEVICE, "the context is being destroyed"};
   r->ticket = next_++;
   const uint64_t t = r->ticket;
   queue_.push_back(r.get());
@@ -76,31 +96,62 @@ uint64_t Server::submit(const ifeast_csr* A, const ifeast_csr* B, const ifeast_c
   return t;
 }
 
-void Server::dispatch_loop() {
-  std::unique_lock<std::mutex> lk(mu_);
-  for (;;) {
-    cv_.wait(lk, [this] {
-      return stop_ || (!queue_.empty() && running_ < kMaxResident &&
-                       (running_ == 0 || used_ + queue_.front()->footprint <= ctx_->budget));
-    });
-    if (stop_) return;
-    Request* r = queue_.front();
-    queue_.pop_front();
-    used_ += r->footprint;
-    ++running_;
-    workers_.emplace_back([this, r] { run(r); });
-  }
+// The queue's front request fits next to the running ones (alone it always fits).
+bool Server::admissible() const {
+  return !queue_.empty() && (running_ == 0 || used_ + queue_.front()->footprint <= ctx_->budget);
 }
 
-void Server::run(Request* r) {
+void Server::worker_loop() {
+  ifeast_ctx* sub = nullptr;  // this worker's stream and workspace
+  std::unique_lock<std::mutex> lk(mu_);
+  Request* r = nullptr;
+  for (;;) {
+    if (r == nullptr) {
+      cv_.wait(lk, [this] { return stop_ || admissible(); });
+      if (stop_) break;
+      r = queue_.front();
+      queue_.pop_front();
+      used_ += r->footprint;
+      ++running_;
+    }
+    lk.unlock();
+    if (sub == nullptr && ifeast_create(&sub, ctx_->device, ctx_->budget) != IFEAST_OK) sub = nullptr;
+    run(r, sub);
+    lk.lock();
+    r->t_done = clock_t_::now();
+    r->done = true;
+    Request* prev = r;
+    r = nullptr;
+    // the next queued request of the same shape reuses this worker's workspace: its footprint
+    // replaces the finished one's
+    if (!stop_ && !queue_.empty() && same_shape(*queue_.front(), *prev)) {
+      r = queue_.front();
+      queue_.pop_front();
+    } else {
+      used_ -= prev->footprint;
+      --running_;
+    }
+    cv_.notify_all();
+    if (r == nullptr && sub != nullptr) {
+      lk.unlock();
+      release_engine(sub);
+      lk.lock();
+    }
+  }
+  lk.unlock();
+  if (sub != nullptr) ifeast_destroy(sub);
+}
+
+void Server::run(Request* r, ifeast_ctx* sub) {
   int status = IFEAST_OK;
   std::string err;
   const int m0 = r->p.m0;
+  const bool general = r->p.problem == IFEAST_PROBLEM_GENERAL;
   r->eval_re.assign(m0, 0.0);
   r->eval_im.assign(m0, 0.0);
   r->resid.assign(m0, 0.0);
   r->flags.assign(m0, 0);
-  r->evec.assign((size_t)r->n * m0, 0.0);
+  r->evec.assign((size_t)r->n * m0 * (general ? 2 : 1), 0.0);
   r->rf_hist.assign(r->p.max_outer, 0.0);
   r->inner_hist.assign((size_t)r->p.max_outer * r->C.nc, 0);
   ifeast_result& res = r->res;
@@ -111,17 +162,14 @@ void Server::run(Request* r) {
   res.evec = r->evec.data();
   res.rf_hist = r->rf_hist.data();
   res.inner_hist = r->inner_hist.data();
-  // each resident request works on its own stream and workspace
-  ifeast_ctx* sub = nullptr;
-  status = ifeast_create(&sub, ctx_->device, ctx_->budget);
-  if (status == IFEAST_OK) {
+  if (sub != nullptr) {
     ifeast_csr A{r->n, (int64_t)r->ciA.size(), r->rpA.data(), r->ciA.data(), r->vA.data()};
     ifeast_csr B{r->n, (int64_t)r->ciB.size(), r->rpB.data(), r->ciB.data(), r->vB.data()};
     status = ifeast_solve(sub, &A, r->hasB ? &B : nullptr, &r->C, &r->p, r->hasX0 ? r->X0.data() : nullptr, &res);
     if (status < 0) err = ifeast_last_error(sub);
-    ifeast_destroy(sub);
   } else {
-    err = ifeast_last_error(nullptr);
+    status = IFEAST_ERR_DEVICE;
+    err = std::string("worker context: ") + ifeast_last_error(nullptr);
   }
   // free the request's inputs; keep the results
   std::vector<int64_t>().swap(r->rpA);
@@ -134,11 +182,6 @@ void Server::run(Request* r) {
   std::lock_guard<std::mutex> lk(mu_);
   r->status = status;
   r->error = err;
-  r->t_done = clock_t_::now();
-  r->done = true;
-  used_ -= r->footprint;
-  --running_;
-  cv_.notify_all();
 }
 
 int Server::poll(uint64_t ticket, int* done) {
@@ -154,6 +197,7 @@ int Server::wait(uint64_t ticket, ifeast_result* out, double* latency_s) {
   auto it = all_.find(ticket);
   if (it == all_.end()) throw Error{IFEAST_ERR_UNKNOWN_TICKET, "unknown ticket"};
   Request* r = it->second.get();
+  ++waiters_;
   cv_.wait(lk, [r] { return r->done; });
   const int m0 = r->p.m0;
   const ifeast_result& s = r->res;
@@ -171,15 +215,17 @@ int Server::wait(uint64_t ticket, ifeast_result* out, double* latency_s) {
   cp(out->eval_im, r->eval_im);
   cp(out->resid, r->resid);
   cp(out->flags, r->flags);
-  cp(out->evec, r->evec);
+  cp(out->evec, r->evec);  // n x m0 (2 n x m0 interleaved complex for general problems)
   cp(out->rf_hist, r->rf_hist);
   cp(out->inner_hist, r->inner_hist);
   (void)m0;
   if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
   const int status = r->status;
-  const std::string err = r->error;
+  // the error text goes to the context here, while the destructor still waits for this thread
+  if (status < 0) ctx_->last_error = r->error;
   all_.erase(it);
-  if (status < 0) throw Error{status, err};
+  --waiters_;
+  cv_.notify_all();
   return status;
 }
 

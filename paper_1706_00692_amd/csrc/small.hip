@@ -353,14 +353,15 @@ __device__ inline double lane_bcast(double v, int l) {
 //  4. L^{-1}: one wave inverts each diagonal block, then block row i of the inverse is
 //     -L_ii^{-1} sum_{k=j..i-1} L_ik X_kj, for all j < i at once;
 //  5. Tinv = D^{-1} (L^{-1})^T with dead rows and columns zero.
-// LDS: L, a 16 x m0 block row, and the previous R (m0 <= 80).
+// LDS: L, a 16 x m0 block row, and the previous R (m0 <= 96; for larger m0 the previous R goes
+// to Rs_glob, an m0 x m0 global scratch, and the rest still fits: 145 KiB at m0 = 128).
 template <class T>
 __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __restrict__ G, double shift_rel,
                                                      double dead_thr, double tau_dep, T* __restrict__ Tinv,
                                                      c2* __restrict__ Racc, int accumulate,
                                                      const int* __restrict__ single, int role,
                                                      double* __restrict__ Hm, int ldh, int jstep,
-                                                     T* __restrict__ Hr_next) {
+                                                     T* __restrict__ Hr_next, double* __restrict__ Rs_glob) {
   // single[0] != 0 (the Gram is certified well conditioned): the first pass (role 0) runs
   // unshifted and the second (role 1) is not needed
   bool final_pass = role == 1;
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
   const int ldl = m0 + 1;
   double* L = lds_d;            // m0 x ldl
   double* tmp = L + m0 * ldl;   // 16 x m0
-  double* Rs = tmp + NB * m0;   // m0 x m0
+  double* Rs = Rs_glob != nullptr ? Rs_glob : tmp + NB * m0;  // m0 x m0
   __shared__ double dsc[128], dinv[128];
   __shared__ int dead[128];
   const int tid = threadIdx.x, nth = blockDim.x, wave = tid >> 6, lane = tid & 63;
@@ -1651,23 +1652,24 @@ __global__ __launch_bounds__(1024) void k_rr_small(int m0, const double* __restr
   }
 }
 
-__global__ void k_classify(ClassifyArgs a, const double* __restrict__ lam, const double* __restrict__ resid,
-                           const double* __restrict__ eta, int* __restrict__ flags, double* __restrict__ out) {
+__global__ void k_classify(ClassifyArgs a, const double* __restrict__ lam, const double* __restrict__ lam_im,
+                           const double* __restrict__ resid, const double* __restrict__ eta, int* __restrict__ flags,
+                           double* __restrict__ out) {
   __shared__ double red[8];
   const int tid = threadIdx.x;
   double rf_in = 0.0, rf_geo = 0.0, rf_all = 0.0, cnt = 0.0, cgeo = 0.0;
   for (int j = tid; j < a.m0; j += 256) {
-    const double l = lam[j];
+    const double l = lam[j], li = lam_im != nullptr ? lam_im[j] : 0.0;
     bool geo;
     if (a.kind == IFEAST_CONTOUR_CIRCLE) {
-      geo = hypot(l - a.c_re, a.c_im) < a.r;
+      geo = hypot(l - a.c_re, li - a.c_im) < a.r;
     } else {
       geo = (l > a.emin) && (l < a.emax);
     }
-    // rho_hat(lambda) = sum_k w_k / (z_k - lambda)  (2 Re for half contours)
+    // rho_hat(lambda) = sum_k w_k / (z_k - lambda)  (2 Re for half contours, real lambda)
     double rr = 0.0, ri = 0.0;
     for (int k = 0; k < a.nc; ++k) {
-      const double zr = a.z[2 * k] - l, zi = a.z[2 * k + 1];
+      const double zr = a.z[2 * k] - l, zi = a.z[2 * k + 1] - li;
       const double d = zr * zr + zi * zi;
       const double wr = a.w[2 * k], wi = a.w[2 * k + 1];
       rr += (wr * zr + wi * zi) / d;
@@ -1698,6 +1700,7 @@ __global__ void k_classify(ClassifyArgs a, const double* __restrict__ lam, const
   if (tid == 0) {
     out[0] = cnt > 0.0 ? rf_in : (cgeo > 0.0 ? rf_geo : rf_all);
     out[1] = cnt;
+    out[2] = cgeo;  // Ritz values inside the contour, counted or not
   }
 }
 
@@ -1805,7 +1808,8 @@ void launch_cholqr_factor(hipStream_t st, int ns, int m0, const double* G, doubl
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
       hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep,
-                         Tinv, reinterpret_cast<c2*>(Racc), accumulate, nullptr, 0, nullptr, 0, 0, nullptr);
+                         Tinv, reinterpret_cast<c2*>(Racc), accumulate, nullptr, 0, nullptr, 0, 0, nullptr,
+                         nullptr);
     } else if (real) {
       if (lds > 64 * 1024)
         IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_lds<T, true>),
@@ -1876,23 +1880,36 @@ __global__ void k_copy_if(const int* __restrict__ flag, int64_t count, const T* 
 template <class T>
 void launch_cholqr_real_ctl(hipStream_t st, int m0, const double* G, double shift_rel, T* Tinv, cd* Racc,
                             int accumulate, const int* single, int role, double* Hm, int ldh, int jstep,
-                            T* Hr_next) {
-  IF_REQUIRE(m0 <= 80, "cholqr: m0 > 80 for the blocked real factor");
+                            T* Hr_next, double* scratch) {
+  IF_REQUIRE(m0 <= 128 && m0 % 16 == 0, "cholqr: the blocked real factor needs m0 a multiple of 16, <= 128");
+  static int max_lds = -1;
+  if (max_lds < 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
   const double dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
   const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   const double tau_dep = shift_rel > 0.0 ? 0.5 * shift_rel : 0.25 * m0 * eps;
-  const size_t lds_real = ((size_t)m0 * (m0 + 1) + (size_t)m0 * m0 + 16 * (size_t)m0) * sizeof(double);
+  const size_t base = ((size_t)m0 * (m0 + 1) + 16 * (size_t)m0) * sizeof(double);
+  const size_t with_rs = base + (size_t)m0 * m0 * sizeof(double);
+  // the previous R factor in LDS when it fits beside L (plus the kernel's static arrays)
+  const bool rs_lds = (int64_t)with_rs + 4096 <= (int64_t)max_lds;
+  IF_REQUIRE(rs_lds || scratch != nullptr || !accumulate, "cholqr: m0 x m0 scratch needed for this m0");
+  IF_REQUIRE((int64_t)base + 4096 <= (int64_t)max_lds, "cholqr: not enough LDS for the blocked real factor");
+  const size_t lds_real = rs_lds ? with_rs : base;
   if (lds_real > 64 * 1024)
     IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholqr_real<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_real));
   hipLaunchKernelGGL((k_cholqr_real<T>), dim3(1), dim3(512), lds_real, st, m0, G, shift_rel, dead_thr, tau_dep, Tinv,
-                     reinterpret_cast<c2*>(Racc), accumulate, single, role, Hm, ldh, jstep, Hr_next);
+                     reinterpret_cast<c2*>(Racc), accumulate, single, role, Hm, ldh, jstep, Hr_next,
+                     rs_lds ? nullptr : scratch);
   IF_HIP(hipGetLastError());
 }
 template void launch_cholqr_real_ctl<float>(hipStream_t, int, const double*, double, float*, cd*, int, const int*,
-                                            int, double*, int, int, float*);
+                                            int, double*, int, int, float*, double*);
 template void launch_cholqr_real_ctl<double>(hipStream_t, int, const double*, double, double*, cd*, int,
-                                             const int*, int, double*, int, int, double*);
+                                             const int*, int, double*, int, int, double*, double*);
 
 void launch_gersh_flags(hipStream_t st, int m0, const double* G, double gersh, double dead_thr, int* single, int* two,
                         int* count) {
@@ -2044,9 +2061,9 @@ void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB,
   IF_HIP(hipGetLastError());
 }
 
-void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* resid,
-                     const double* eta, int* flags, double* out) {
-  hipLaunchKernelGGL(k_classify, dim3(1), dim3(256), 0, st, a, lam, resid, eta, flags, out);
+void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* lam_im,
+                     const double* resid, const double* eta, int* flags, double* out) {
+  hipLaunchKernelGGL(k_classify, dim3(1), dim3(256), 0, st, a, lam, lam_im, resid, eta, flags, out);
   IF_HIP(hipGetLastError());
 }
 

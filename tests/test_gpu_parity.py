@@ -226,10 +226,11 @@ def test_filter_parity_fp64(ctx, torch_cuda, cycles, reorth, basis):
     assert err <= 1e-9, err
 
 
-@pytest.mark.parametrize("m0", [48, 80])
+@pytest.mark.parametrize("m0", [48, 80, 96, 128])
 def test_filter_parity_shared_wide(ctx, torch_cuda, m0):
-    """Shared basis with several 16-column panels in the block Cholesky-QR factor (m0 = 48, 80):
-    4 Arnoldi steps on a 10^3 Laplacian + potential, FP64, against per-shift block GMRES."""
+    """Shared basis with several 16-column panels in the block Cholesky-QR factor (m0 = 48 ... 128;
+    above 96 the previous R factor sits in global memory): 4 Arnoldi steps on a 10^3 Laplacian +
+    potential, FP64, against per-shift block GMRES."""
     import paper_1706_00692_amd as pk
 
     N = 10
@@ -241,6 +242,20 @@ def test_filter_parity_shared_wide(ctx, torch_cuda, m0):
     assert list(iters) == [4] * 8
     err = np.abs(got - want).max() / np.abs(want).max()
     assert err <= 1e-9, err
+
+
+def test_solve_shared_m0_128_mixed(ctx):
+    """A full mixed-precision solve with m0 = 128 on the shared basis (the widest block the
+    serving mix draws), against the dense spectrum of a 12^3 Laplacian + potential."""
+    import paper_1706_00692_amd as pk
+
+    N = 12
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    prob = W.config2_small(N=N, m0=128, emin=0.5 * (lam_all[9] + lam_all[10]), emax=0.5 * (lam_all[69] + lam_all[70]))
+    res = ctx.solve_problem(prob, precision=pk.PREC_MIXED)
+    assert res.status == 0 and res.converged and res.m == 60
+    assert np.allclose(np.sort(res.lam_in), lam_all[10:70], rtol=1e-10, atol=0)
+    assert res.resid[: res.m].max() <= prob.tol
 
 
 def test_filter_parity_mixed(ctx, torch_cuda):
@@ -368,9 +383,49 @@ def test_not_converged_and_m0_too_small(ctx):
     res = ctx.solve_problem(prob, precision=pk.PREC_FP64, max_outer=1)
     assert res.status == 1 and not res.converged and res.outer_iters == 1
     prob.contour = dict(prob.contour, emin=0.5, emax=1.2)  # 26 eigenvalues, m0 = 16
-    res = ctx.solve_problem(prob, precision=pk.PREC_FP64, max_outer=3)
-    assert res.status in (1, 2)
-    assert res.m <= prob.m0
+    for prec in (pk.PREC_FP64, pk.PREC_MIXED):
+        res = ctx.solve_problem(prob, precision=prec, max_outer=10)
+        # every Ritz value lands inside after the first filter application: the solve stops there
+        assert res.status == 2 and res.outer_iters == 1 and not res.converged
+        assert np.all((res.lam > 0.5) & (res.lam < 1.2))
+    ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner, prob.alpha, prob.tol, prob.x0(), 10,
+                   max_cycles=prob.max_cycles, inner_rule=prob.inner_rule, tau=prob.tau)
+    assert ref.status == "m0_too_small" and ref.outer_iters == 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_no_eigenvalue_in_contour(ctx, prec):
+    """An interval inside a spectral gap of the 20 x 20 Laplacian: status NO_EIG, as the oracle.
+    The shared basis's inner solves are longer than the oracle's restarted ones, so Ritz values
+    of damped directions may sit inside the gap for a few outer iterations before the rule fires."""
+    import paper_1706_00692_amd as pk
+
+    mu = 2 - 2 * np.cos(np.arange(1, 21) * np.pi / 21)
+    exact = np.sort((mu[:, None] + mu[None, :]).ravel())
+    gap = int(np.argmax(np.diff(exact[:60])))
+    lo, hi = exact[gap], exact[gap + 1]
+    prob = W.config1()
+    prob.contour = dict(prob.contour, emin=lo + 0.1 * (hi - lo), emax=hi - 0.1 * (hi - lo))
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED)
+    assert res.status == 3 and res.m == 0 and res.outer_iters <= 8
+    assert not np.any((res.lam > prob.contour["emin"]) & (res.lam < prob.contour["emax"]))
+    ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner, prob.alpha, prob.tol, prob.x0(),
+                   prob.max_outer, max_cycles=prob.max_cycles, inner_rule=prob.inner_rule, tau=prob.tau)
+    assert ref.status == "no_eig" and ref.outer_iters == 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_inner_global_rule_matches_oracle(ctx, prec):
+    """Algorithm 2's printed inner stopping rule (every column residual <= alpha ||R_F||) end to end."""
+    import paper_1706_00692_amd as pk
+
+    prob = W.config1()
+    prob.inner_rule = "global"
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED)
+    ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner, prob.alpha, prob.tol, prob.x0(),
+                   prob.max_outer, max_cycles=prob.max_cycles, inner_rule="global", tau=prob.tau)
+    _check_against_oracle(prob, res, ref)
+    assert res.status == 0
 
 
 def test_invalid_inputs_rejected(ctx):
@@ -423,6 +478,90 @@ def test_serving_alone_vs_mix(ctx):
     with pytest.raises(pk.IFeastError) as e:
         ctx.poll(987654321)
     assert e.value.status == -6
+
+
+def _small_serving_problems():
+    probs = [W.config1()]
+    for N, lo, hi, m0 in [(9, 4, 16, 32), (8, 2, 10, 16)]:
+        lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+        probs.append(W.config2_small(N=N, m0=m0, emin=0.5 * (lam_all[lo - 1] + lam_all[lo]),
+                                     emax=0.5 * (lam_all[hi - 1] + lam_all[hi])))
+    return probs
+
+
+def _serving_params(pk, p):
+    return pk.params_struct(p.m0, p.max_outer, p.max_inner, p.max_cycles, p.alpha, p.tol, p.tau, pk.PREC_MIXED)
+
+
+def test_serving_budget_rejects_and_queues(torch_cuda):
+    """A request larger than the context budget is REJECTED at submit; with a budget that fits
+    only the largest request, requests run one at a time (each waits for the previous one) and
+    still give the results they give alone."""
+    import paper_1706_00692_amd as pk
+
+    probs = _small_serving_problems()
+    fps = [pk.footprint(p.n, p.A.nnz, 0, p.contour, _serving_params(pk, p)) for p in probs]
+    big = max(fps)
+    c = pk.Context(0, budget=big)
+    try:
+        alone = [c.solve_problem(p, precision=pk.PREC_MIXED) for p in probs]
+        tight = pk.Context(0, budget=min(fps) - 1)
+        try:
+            with pytest.raises(pk.IFeastError) as e:
+                tight.submit(probs[0].A, None, probs[0].contour, _serving_params(pk, probs[0]), probs[0].x0())
+            assert e.value.status == -5
+        finally:
+            tight.close()
+        # every pair of requests exceeds the budget, so none runs beside another
+        assert all(fps[i] + fps[j] > big for i in range(3) for j in range(3) if i != j)
+        tickets = [c.submit(p.A, None, p.contour, _serving_params(pk, p), p.x0()) for p in probs]
+        out = [c.wait(t, p.n, p.m0, p.max_outer, p.contour["nc"]) for p, t in zip(probs, tickets)]
+        for p, r, a in zip(probs, out, alone):
+            assert r.converged and r.m == a.m
+            assert np.all(np.abs(r.lam_in - a.lam_in) <= 1e-10 * np.abs(a.lam_in))
+        # FIFO and one at a time: each latency covers the solves queued before it
+        lat = [r.latency for r in out]
+        assert lat[0] < lat[1] < lat[2]
+        assert lat[2] >= sum(r.solve_seconds for r in out) * 0.9
+    finally:
+        c.close()
+
+
+def test_serving_destroy_fails_queued_requests(torch_cuda):
+    """Destroying a context with requests still queued: they fail with ERR_DEVICE, a thread
+    blocked in wait() on one of them returns, and nothing hangs."""
+    import threading
+
+    import paper_1706_00692_amd as pk
+
+    probs = _small_serving_problems()
+    p = probs[1]
+    fp = pk.footprint(p.n, p.A.nnz, 0, p.contour, _serving_params(pk, p))
+    c = pk.Context(0, budget=fp)
+    tickets = [c.submit(p.A, None, p.contour, _serving_params(pk, p), p.x0()) for _ in range(4)]
+    got = {}
+
+    import ctypes
+
+    h, lib = c.h, c.lib
+
+    def waiter():
+        # the raw call: after a destroy the context handle must not be touched again
+        bufs = pk._binding._ResultBuffers(p.n, p.m0, p.max_outer, p.contour["nc"])
+        lat = ctypes.c_double(0.0)
+        st = lib.ifeast_wait(h, ctypes.c_uint64(tickets[-1]), ctypes.byref(bufs.s), ctypes.byref(lat))
+        if st < 0:
+            got["err"] = st
+        else:
+            got["res"] = bufs.result(st, p.contour["nc"])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    c.close()
+    th.join(timeout=120)
+    assert not th.is_alive()
+    # the last request either ran before the destroy reached it or failed as queued
+    assert got.get("err") == -3 or got["res"].converged
 
 
 def test_solve_dev_matches_host_buffers(ctx, torch_cuda):

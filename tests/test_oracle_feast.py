@@ -172,3 +172,53 @@ def test_lobpcg_reference_matches_dense():
     dense = np.linalg.eigvalsh(A.to_dense())[:20]
     assert np.allclose(vals[:20], dense, rtol=1e-10, atol=0)
     assert res[:20].max() < 1e-7
+
+
+def test_classify_flags_junk_pair_from_damped_components():
+    """A Ritz pair built from two damped eigenvectors on either side of the interval has its
+    Rayleigh quotient inside the interval but a filter gain equal to the damping, far below
+    |rho_hat| there: classify must flag it and keep it out of m and ||R_F||."""
+    lam_all = np.array([0.1, 0.2, 0.9, 1.1, 1.8, 1.9, 3.0, 4.0])
+    n = len(lam_all)
+    A = np.diag(lam_all)
+    contour = {"kind": "half", "emin": 0.5, "emax": 1.5, "rule": "gl", "nc": 8}
+    z, w, half = contour_nodes(contour)
+    E = np.eye(n)
+    # two genuine directions (0.9, 1.1), one mix of 0.2 and 1.8 (symmetric about the centre 1.0)
+    X = np.column_stack([E[:, 2], E[:, 3], (E[:, 1] + E[:, 4]) / np.sqrt(2.0)])
+    gam = rho_hat(lam_all, z, w, True)
+    Q = (gam[:, None] * E) @ X  # the exact filter rho_hat(A) X
+    l, Xn, AX, BX, C = O.rayleigh_ritz(A, None, Q)
+    R, r = O.residuals(AX, BX, l)
+    eta = filter_gain(C, X.T @ X)
+    junk = np.argmin(np.abs(l - 1.0))
+    assert 0.5 < l[junk] < 1.5 and abs(l[junk] - 1.0) < 1e-9  # the mix's quotient sits at the centre
+    # its gain is the damping |rho_hat(0.2)| = |rho_hat(1.8)|, against |rho_hat(1.0)| ~ 1
+    assert abs(eta[junk] - abs(gam[1])) < 1e-12 and eta[junk] < 0.1 * abs(rho_hat(np.array([1.0]), z, w, True)[0])
+    ins, spur, rf = classify(l, r, eta, contour, z, w, half, 0.5)
+    assert spur[junk] and not ins[junk]
+    assert ins.sum() == 2 and not spur[np.arange(3) != junk].any()
+    assert r[junk] > 0.5 and rf < 1e-12  # the junk residual (~0.8) does not enter ||R_F||
+
+
+def test_ifeast_status_m0_too_small_and_no_eig():
+    """Algorithm 2's premise (fewer than m0 eigenvalues inside, at least one): the literal
+    configuration-1 interval holds 26 > m0 = 16 eigenvalues, an interval inside a spectral gap
+    holds none; both end after the first filter application."""
+    exact = _lap_exact(20)
+    p = W.config1()
+    wide = dict(p.contour, emin=0.5, emax=1.2)
+    assert ((exact > 0.5) & (exact < 1.2)).sum() == 26
+    res = O.ifeast(p.A, None, wide, p.m0, p.max_inner, p.alpha, p.tol, p.x0(), p.max_outer,
+                   max_cycles=p.max_cycles, inner_rule=p.inner_rule, tau=p.tau)
+    assert res.status == "m0_too_small" and res.outer_iters == 1 and not res.converged
+    gap = int(np.argmax(np.diff(exact[:60])))
+    lo, hi = exact[gap], exact[gap + 1]
+    empty = dict(p.contour, emin=lo + 0.1 * (hi - lo), emax=hi - 0.1 * (hi - lo))
+    assert not ((exact > empty["emin"]) & (exact < empty["emax"])).any()
+    res = O.ifeast(p.A, None, empty, p.m0, p.max_inner, p.alpha, p.tol, p.x0(), p.max_outer,
+                   max_cycles=p.max_cycles, inner_rule=p.inner_rule, tau=p.tau)
+    assert res.status == "no_eig" and res.m == 0 and res.outer_iters == 1
+    res = O.ifeast(p.A, None, p.contour, p.m0, p.max_inner, p.alpha, p.tol, p.x0(), p.max_outer,
+                   max_cycles=p.max_cycles, inner_rule=p.inner_rule, tau=p.tau)
+    assert res.status == "ok" and res.m == 11

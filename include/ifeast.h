@@ -6,6 +6,9 @@
  * Problem (Eq. eigenvalueproblem; generalized form Eq. generalized_linsys):
  *   find the eigenpairs A x = lambda B x with lambda inside a contour C,
  *   A, B real sparse (CSR), B symmetric positive definite or the identity.
+ *   Non-Hermitian problems (Sec. 1.1: the results extend to them): A real
+ *   nonsymmetric, B = I, C a circle centred on the real axis; the Ritz
+ *   problem is solved with the right Galerkin condition.
  * Method (Algorithm 2): starting from an n x m0 block X, each outer
  * iteration solves the nc shifted systems (z_k B - A) Y_k = B X inexactly
  * with block GMRES (one real Krylov basis shared by all shifts when B = I,
@@ -86,7 +89,11 @@ typedef struct {
 
 enum { IFEAST_PREC_FP64 = 0,   /* complex FP64 inner solves */
        IFEAST_PREC_MIXED = 1 };/* complex FP32 inner solves, FP64 outer iteration */
-enum { IFEAST_PROBLEM_SYMMETRIC = 0, IFEAST_PROBLEM_GENERAL = 1 };
+enum { IFEAST_PROBLEM_SYMMETRIC = 0, /* A symmetric, B SPD or NULL: HALF or EXPLICIT contours */
+       IFEAST_PROBLEM_GENERAL = 1 };  /* A nonsymmetric, B NULL, a CIRCLE contour with c_im = 0 and an
+                                         even nc (the rule is symmetric about the real axis, so the
+                                         nc/2 systems of the upper half are solved and the lower
+                                         half's solutions are their conjugates); shared basis only */
 enum { IFEAST_GUESS_RITZ = 0,  /* inner initial guess X (z - Lambda)^{-1} */
        IFEAST_GUESS_ZERO = 1 };/* zero initial guess, right-hand side B X (Algorithm 2 as printed) */
 enum { IFEAST_BASIS_AUTO = 0,      /* shared for B = I, per shift otherwise */
@@ -142,7 +149,8 @@ typedef struct {
   /* caller-allocated arrays (may be NULL to skip) */
   double *eval_re;         /* m0 */
   double *eval_im;         /* m0 (zeros for symmetric problems) */
-  double *evec;            /* n x m0 row-major, B-normalised */
+  double *evec;            /* n x m0 row-major, B-normalised; PROBLEM_GENERAL: n x m0 complex
+                              (interleaved re, im: 2 n m0 doubles), unit 2-norm */
   double *resid;           /* m0 residual norms ||A x_j - lambda_j B x_j|| */
   int32_t *flags;          /* m0 IFEAST_FLAG_* bits */
   double *rf_hist;         /* max_outer entries: ||R_F|| after each outer iteration */
@@ -185,7 +193,8 @@ int ifeast_solve_resident(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_
 
 /* As ifeast_solve_resident with the big arrays in HBM: X0 is a device n x m0
  * row-major initial block (required), evec a device n x m0 row-major output
- * for the eigenvectors in the order of res's arrays (NULL: not written).  The
+ * for the eigenvectors in the order of res's arrays (NULL: not written;
+ * PROBLEM_GENERAL: n x m0 complex, 2 n m0 doubles interleaved).  The
  * small host arrays of res are filled as in ifeast_solve_resident; res->evec,
  * when non-NULL, is filled too.  Both device buffers belong to the caller and
  * are used on the context's stream; the call returns when the solve is done. */
@@ -263,6 +272,21 @@ int ifeast_filter_dev(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matr
  * of a B-orthonormal X for them to be meaningful). */
 int ifeast_rayleigh_ritz_dev(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matrix *B, int m0,
                              const double *Q, double *lam, double *X, double *R, double *resid, double *eta);
+
+/* Non-Hermitian Rayleigh-Ritz on device data (Algorithm 2, steps 3-4, right Galerkin condition,
+ * B = I): orthonormalise span(Q) (n x m0, FP64, row-major), solve the reduced eigenproblem of
+ * Q^T A Q and return the Ritz values lam + i lam_im (m0 each, ascending real part) and the
+ * Ritz block X = Q C in pair format: a real Ritz value owns one column, its unit eigenvector;
+ * a conjugate pair a -+ ib (b > 0) owns two adjacent columns j, j+1 holding Re x and Im x of
+ * the eigenvector x of a + ib (||x|| = 1), with lam_im[j] = -b, lam_im[j+1] = +b.  R = A X - X
+ * Lambda in the same format (a pair's columns: real and imaginary parts of A x - lambda x),
+ * resid the residual norm of each complex eigenvector (shared by a pair's columns), and eta
+ * the filter gains 1 / ||Xprev c_l|| (Xprev: the block filtered into Q, n x m0; NULL: gains
+ * against the identity).  Xprev must not alias X.  ERR_NUMERICAL-style failures (the Schur
+ * iteration not converging) leave NaN in lam[0]. */
+int ifeast_rayleigh_ritz_general_dev(ifeast_ctx *ctx, const ifeast_matrix *A, int m0, const double *Q,
+                                     const double *Xprev, double *lam, double *lam_im, double *X, double *R,
+                                     double *resid, double *eta);
 
 #ifdef __cplusplus
 }

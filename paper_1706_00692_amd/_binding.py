@@ -111,6 +111,7 @@ def load_library():
         "ifeast_filter_dev": (i32, [vp, vp, vp, C.POINTER(ContourStruct), C.POINTER(ParamsStruct), vp, vp, vp, dbl,
                                     vp, vp]),
         "ifeast_rayleigh_ritz_dev": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
+        "ifeast_rayleigh_ritz_general_dev": (i32, [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "ifeast_set_timing": (i32, [vp, i32]),
         "ifeast_kernel_stats": (i32, [vp, i32, C.POINTER(KernelStatStruct)]),
     }
@@ -185,6 +186,12 @@ def problem_params(prob, precision=PREC_FP64, **overrides) -> ParamsStruct:
     return params
 
 
+def _solved_systems(cs, params) -> int:
+    """Shifted systems solved per outer iteration: nc, or nc / 2 for a general problem (the
+    upper half of a rule symmetric about the real axis)."""
+    return cs.nc // 2 if params.problem == PROBLEM_GENERAL else cs.nc
+
+
 def footprint(n, nnzA, nnzB, contour: dict, params: ParamsStruct) -> int:
     lib = load_library()
     cs, keep = contour_struct(contour)
@@ -224,10 +231,11 @@ class Result:
 
 
 class _ResultBuffers:
-    def __init__(self, n, m0, max_outer, nc, host_evec=True):
+    def __init__(self, n, m0, max_outer, nc, host_evec=True, general=False):
+        self.general = general
         self.eval_re = np.zeros(m0)
         self.eval_im = np.zeros(m0)
-        self.evec = np.zeros((n, m0)) if host_evec else None
+        self.evec = (np.zeros((n, m0), dtype=np.complex128 if general else np.float64) if host_evec else None)
         self.resid = np.zeros(m0)
         self.flags = np.zeros(m0, dtype=np.int32)
         self.rf_hist = np.zeros(max_outer)
@@ -240,8 +248,9 @@ class _ResultBuffers:
     def result(self, status, nc, latency=float("nan")):
         s = self.s
         k = s.outer_iters
+        lam = self.eval_re + 1j * self.eval_im if self.general else self.eval_re.copy()
         return Result(status, s.m, s.outer_iters, bool(s.converged), s.total_matvec, s.seq_matvec, s.max_resid,
-                      s.solve_seconds, self.eval_re.copy(), self.evec, self.resid.copy(), self.flags.copy(),
+                      s.solve_seconds, lam, self.evec, self.resid.copy(), self.flags.copy(),
                       self.rf_hist[:k].copy(), self.inner_hist[: k * nc].reshape(k, nc).copy(), latency)
 
 
@@ -311,35 +320,37 @@ class Context:
     # --------------------------------------------------------- full solves
     def solve_resident(self, A: Matrix, B: Matrix | None, contour: dict, params: ParamsStruct, X0=None) -> Result:
         cs, keep = contour_struct(contour)
-        bufs = _ResultBuffers(A.n, params.m0, params.max_outer, cs.nc)
+        bufs = _ResultBuffers(A.n, params.m0, params.max_outer, cs.nc, general=params.problem == PROBLEM_GENERAL)
         x0 = None if X0 is None else np.ascontiguousarray(X0, dtype=np.float64)
         st = self._check(self.lib.ifeast_solve_resident(self.h, A.h, None if B is None else B.h, C.byref(cs),
                                                          C.byref(params), None if x0 is None else x0.ctypes.data,
                                                          C.byref(bufs.s)))
-        return bufs.result(st, cs.nc)
+        return bufs.result(st, _solved_systems(cs, params))
 
     def solve_dev(self, A: Matrix, B: Matrix | None, contour: dict, params: ParamsStruct, X0_ptr: int,
                   evec_ptr: int | None = None) -> Result:
         """ifeast_solve_dev: X0_ptr / evec_ptr are device addresses of n x m0 FP64 row-major
         blocks (e.g. torch tensors' data_ptr()); the result's evec is None (it is in evec_ptr)."""
         cs, keep = contour_struct(contour)
-        bufs = _ResultBuffers(A.n, params.m0, params.max_outer, cs.nc, host_evec=False)
+        bufs = _ResultBuffers(A.n, params.m0, params.max_outer, cs.nc, host_evec=False,
+                              general=params.problem == PROBLEM_GENERAL)
         st = self._check(self.lib.ifeast_solve_dev(self.h, A.h, None if B is None else B.h, C.byref(cs),
                                                    C.byref(params), C.c_void_p(X0_ptr),
                                                    None if evec_ptr is None else C.c_void_p(evec_ptr),
                                                    C.byref(bufs.s)))
-        return bufs.result(st, cs.nc)
+        return bufs.result(st, _solved_systems(cs, params))
 
     def solve(self, A, B, contour: dict, params: ParamsStruct, X0=None) -> Result:
         a, ka = _csr_struct(A)
         b, kb = (None, None) if B is None else _csr_struct(B)
         cs, keep = contour_struct(contour)
-        bufs = _ResultBuffers(int(A.n), params.m0, params.max_outer, cs.nc)
+        bufs = _ResultBuffers(int(A.n), params.m0, params.max_outer, cs.nc,
+                              general=params.problem == PROBLEM_GENERAL)
         x0 = None if X0 is None else np.ascontiguousarray(X0, dtype=np.float64)
         st = self._check(self.lib.ifeast_solve(self.h, C.byref(a), None if b is None else C.byref(b), C.byref(cs),
                                                C.byref(params), None if x0 is None else x0.ctypes.data,
                                                C.byref(bufs.s)))
-        return bufs.result(st, cs.nc)
+        return bufs.result(st, _solved_systems(cs, params))
 
     def solve_problem(self, prob, precision=PREC_FP64, resident=None, **overrides) -> Result:
         """Solve a workloads.Problem (matrices uploaded unless given as resident Matrix objects)."""
@@ -365,8 +376,9 @@ class Context:
         self._check(self.lib.ifeast_poll(self.h, C.c_uint64(ticket), C.byref(d)))
         return bool(d.value)
 
-    def wait(self, ticket: int, n: int, m0: int, max_outer: int, nc: int) -> Result:
-        bufs = _ResultBuffers(n, m0, max_outer, nc)
+    def wait(self, ticket: int, n: int, m0: int, max_outer: int, nc: int, general: bool = False) -> Result:
+        """nc: the shifted systems solved per outer iteration (nc / 2 for a general problem's circle)."""
+        bufs = _ResultBuffers(n, m0, max_outer, nc, general=general)
         lat = C.c_double(0.0)
         st = self._check(self.lib.ifeast_wait(self.h, C.c_uint64(ticket), C.byref(bufs.s), C.byref(lat)))
         return bufs.result(st, nc, lat.value)
@@ -401,6 +413,13 @@ class Context:
                                                C.byref(params), X.data_ptr(), lam.data_ptr(), R.data_ptr(),
                                                float(rf), Q.data_ptr(), iters.ctypes.data))
         return iters
+
+    def rayleigh_ritz_general(self, A: Matrix, Q, Xprev, lam, lam_im, X, R, resid, eta):
+        """Non-Hermitian Rayleigh-Ritz on span(Q) (device tensors, FP64; pair-format outputs)."""
+        self._use_torch_stream()
+        self._check(self.lib.ifeast_rayleigh_ritz_general_dev(
+            self.h, A.h, int(Q.shape[1]), Q.data_ptr(), None if Xprev is None else Xprev.data_ptr(),
+            lam.data_ptr(), lam_im.data_ptr(), X.data_ptr(), R.data_ptr(), resid.data_ptr(), eta.data_ptr()))
 
     def rayleigh_ritz(self, A: Matrix, B: Matrix | None, Q, lam, X, R, resid, eta):
         """Rayleigh-Ritz on span(Q) (device tensors, FP64)."""

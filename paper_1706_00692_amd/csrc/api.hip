@@ -99,6 +99,12 @@ Shape make_shape(int64_t n, bool hasB, const ifeast_contour* C, const ifeast_par
   if (p->basis == IFEAST_BASIS_SHARED && hasB)
     throw Error{IFEAST_ERR_UNSUPPORTED, "a shared Krylov basis needs B = I"};
   s.shared = !hasB && p->basis != IFEAST_BASIS_PER_SHIFT;
+  if (p->problem == IFEAST_PROBLEM_GENERAL) {
+    if (hasB) throw Error{IFEAST_ERR_UNSUPPORTED, "non-Hermitian problems take B = I"};
+    // the upper half of a conjugate-symmetric rule is solved (see validate_params)
+    s.general = true;
+    s.ns = nsys(C) / 2;
+  }
   s.kb = s.shared ? p->max_inner * p->max_cycles : p->max_inner;
   return s;
 }
@@ -117,7 +123,7 @@ static std::map<ifeast_ctx*, EngineCache> g_cache;
 namespace {
 bool same(const Shape& a, const Shape& b) {
   return a.n == b.n && a.m0 == b.m0 && a.ns == b.ns && a.k == b.k && a.hasB == b.hasB && a.precision == b.precision &&
-         a.shared == b.shared && a.kb == b.kb;
+         a.shared == b.shared && a.kb == b.kb && a.general == b.general;
 }
 Engine& engine_for(ifeast_ctx* ctx, const Shape& s) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -372,6 +378,8 @@ int ifeast_filter_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_matr
     IF_REQUIRE(X != nullptr && lam != nullptr && R != nullptr && Q != nullptr, "null device pointer");
     IF_REQUIRE(B == nullptr || B->n == A->n, "A and B sizes differ");
     validate_params(*p, *C, A->n);
+    if (p->problem != IFEAST_PROBLEM_SYMMETRIC)
+      throw Error{IFEAST_ERR_UNSUPPORTED, "the step-level filter takes symmetric problems"};
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, C, p));
@@ -405,6 +413,34 @@ int ifeast_rayleigh_ritz_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifea
     Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, &C, &p));
     TimingScope ts(ctx);
     eng.rayleigh_ritz(A, B, Q, lam, X, R, resid, eta);
+    IF_HIP(hipStreamSynchronize(ctx->stream));
+    return IFEAST_OK;
+  });
+}
+
+int ifeast_rayleigh_ritz_general_dev(ifeast_ctx* ctx, const ifeast_matrix* A, int m0, const double* Q,
+                                     const double* Xprev, double* lam, double* lam_im, double* X, double* R,
+                                     double* resid, double* eta) {
+  return guarded(ctx, [&]() -> int {
+    IF_REQUIRE(ctx != nullptr && A != nullptr, "null argument");
+    IF_REQUIRE(Q && lam && lam_im && X && R && resid && eta, "null device pointer");
+    IF_REQUIRE(Xprev != X, "Xprev and X must not alias");
+    IF_REQUIRE(m0 > 0 && m0 % 16 == 0 && m0 <= 128 && m0 <= A->n, "m0 must be a multiple of 16 in [16, 128]");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    ifeast_contour C{};
+    C.kind = IFEAST_CONTOUR_CIRCLE;
+    C.nc = 2;
+    C.r = 1.0;
+    ifeast_params p{};
+    p.m0 = m0;
+    p.max_inner = 1;
+    p.max_cycles = 1;
+    p.precision = IFEAST_PREC_FP64;
+    p.problem = IFEAST_PROBLEM_GENERAL;
+    Engine& eng = engine_for(ctx, make_shape(A->n, false, &C, &p));
+    TimingScope ts(ctx);
+    eng.rayleigh_ritz_general(A, Q, Xprev, lam, lam_im, X, R, resid, eta);
     IF_HIP(hipStreamSynchronize(ctx->stream));
     return IFEAST_OK;
   });

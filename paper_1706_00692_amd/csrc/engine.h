@@ -24,6 +24,7 @@ struct Shape {
   int precision;
   bool shared = false;  // one real Krylov basis for all shifts (B = I)
   int kb = 0;           // basis capacity in blocks: k (per shift) or k * max_cycles (shared)
+  bool general = false; // non-Hermitian A (real, B = I): Ritz block in pair format, full Arnoldi
 };
 uint64_t workspace_bytes(const Shape& s);
 
@@ -59,6 +60,9 @@ class Engine {
               const double* X, const double* lam, const double* R, double rf, double* Q, std::vector<int>* iters);
   void rayleigh_ritz(const ifeast_matrix* A, const ifeast_matrix* B, const double* Q, double* lam, double* X,
                      double* R, double* resid, double* eta);
+  // Non-Hermitian Rayleigh-Ritz (pair format); Xprev: the filtered block for the gains (may be null).
+  void rayleigh_ritz_general(const ifeast_matrix* A, const double* Q, const double* Xprev, double* lam,
+                             double* lam_im, double* X, double* R, double* resid, double* eta);
 
   struct Impl;
 

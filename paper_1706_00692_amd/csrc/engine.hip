@@ -136,11 +136,23 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
              "unknown basis mode");
   IF_REQUIRE(p.precision == IFEAST_PREC_FP64 || p.precision == IFEAST_PREC_MIXED, "unknown precision");
   IF_REQUIRE(p.inner_rule == IFEAST_INNER_GLOBAL || p.inner_rule == IFEAST_INNER_COLUMN, "unknown inner rule");
-  if (p.problem != IFEAST_PROBLEM_SYMMETRIC)
-    throw Error{IFEAST_ERR_UNSUPPORTED, "only real symmetric problems (IFEAST_PROBLEM_SYMMETRIC) are implemented"};
+  IF_REQUIRE(p.problem == IFEAST_PROBLEM_SYMMETRIC || p.problem == IFEAST_PROBLEM_GENERAL, "unknown problem kind");
   if (p.inner_guess != IFEAST_GUESS_RITZ)
     throw Error{IFEAST_ERR_UNSUPPORTED, "only the Ritz initial guess (IFEAST_GUESS_RITZ) is implemented"};
   IF_REQUIRE(C.nc >= 1 && C.nc <= 64, "nc must be in [1, 64]");
+  if (p.problem == IFEAST_PROBLEM_GENERAL) {
+    // real A with a contour symmetric about the real axis: the conjugate nodes' solutions are the
+    // conjugates of the upper ones, so the upper nc/2 are solved (the Ritz block stays real)
+    if (C.kind != IFEAST_CONTOUR_CIRCLE)
+      throw Error{IFEAST_ERR_UNSUPPORTED, "non-Hermitian problems use a CIRCLE contour"};
+    if (C.c_im != 0.0)
+      throw Error{IFEAST_ERR_UNSUPPORTED, "non-Hermitian problems need the circle centred on the real axis"};
+    IF_REQUIRE(C.nc >= 2 && C.nc % 2 == 0, "a full-circle rule needs an even number of nodes");
+    IF_REQUIRE(C.r > 0.0, "the circle radius must be positive");
+    if (p.basis == IFEAST_BASIS_PER_SHIFT)
+      throw Error{IFEAST_ERR_UNSUPPORTED, "non-Hermitian problems use the shared basis"};
+    return;
+  }
   if (C.kind == IFEAST_CONTOUR_HALF) {
     IF_REQUIRE(C.emax > C.emin, "emax must exceed emin");
     IF_REQUIRE(C.rule == IFEAST_RULE_GAUSS_LEGENDRE || C.rule == IFEAST_RULE_TRAPEZOID, "unknown rule");
@@ -182,7 +194,7 @@ Layout layout(const Shape& s) {
   L.BQ = s.hasB ? n * m0 * 8 : 0;
   L.vec = 4 * 128 * 8;
   L.mm = m0 * m0 * 8;
-  L.rrwork = (4 * m0 * m0 + 4 * m0) * 8;
+  L.rrwork = (s.general ? 10 * m0 * m0 + 16 * m0 : 4 * m0 * m0 + 4 * m0) * 8;
   L.colpart = (size_t)col_sumsq_blocks(s.n) * m0 * 8;
   // per-shift least squares (both modes)
   L.H = ns * ldh * k * m0 * 16;
@@ -242,7 +254,7 @@ Layout layout(const Shape& s) {
 }
 
 size_t total(const Layout& L) {
-  return 3 * L.X + L.AQ + L.BQ + L.R + 8 * L.vec + 3 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
+  return 3 * L.X + L.AQ + L.BQ + L.R + 10 * L.vec + 6 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
          L.tauh + L.g + L.u + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq +
          L.Uc + 3 * L.zs + L.Hm + L.Ss + L.Us + L.Om;
 }
@@ -260,6 +272,26 @@ __global__ void k_gather_cols(int64_t n, int m0, const double* __restrict__ X, c
   const int64_t i = idx / m0;
   const int j = (int)(idx % m0);
   out[idx] = X[i * m0 + order[j]];
+}
+
+// out (n x m0 complex, interleaved)[i][j] = eigenvector order[j] from the pair-format block X.
+__global__ void k_gather_complex(int64_t n, int m0, const double* __restrict__ X, const int* __restrict__ order,
+                                 const double* __restrict__ lam_im, double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * m0) return;
+  const int64_t i = idx / m0;
+  const int o = order[(int)(idx % m0)];
+  const double li = lam_im[o];
+  const double* row = X + i * m0;
+  double re = row[o], im = 0.0;
+  if (li < 0.0) {
+    im = -row[o + 1];
+  } else if (li > 0.0) {
+    re = row[o - 1];
+    im = row[o];
+  }
+  out[2 * idx] = re;
+  out[2 * idx + 1] = im;
 }
 
 template <class T>
@@ -317,6 +349,8 @@ struct Engine::Impl {
   Layout L;
   // outer, FP64
   DevBuf X, Q, Xn, AQ, BQ, R, lam, resid, eta, rho, C, GA, GB, rrwork, colpart, clsout;
+  DevBuf lamI, rhoI, GX;  // non-Hermitian path: imaginary parts (pair format), Gram of the filtered block
+  DevBuf TS, TA;          // non-Hermitian path: SVQB transform of a pass, accumulated transform
   // inner
   DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gwb, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
   DevBuf Hm, Ss;             // shared basis
@@ -388,6 +422,15 @@ struct Engine::Impl {
     C = DevBuf(L.mm);
     GA = DevBuf(L.mm);
     GB = DevBuf(L.mm);
+    GX = DevBuf(L.mm);
+    if (sh.general) {
+      TS = DevBuf(L.mm);
+      TA = DevBuf(L.mm);
+    }
+    lamI = DevBuf(L.vec);
+    rhoI = DevBuf(L.vec);
+    launch_fill_zero(st, lamI.p, lamI.bytes);
+    launch_fill_zero(st, rhoI.p, rhoI.bytes);
     rrwork = DevBuf(L.rrwork);
     colpart = DevBuf(L.colpart);
     V = DevBuf(L.V);
@@ -494,6 +537,51 @@ struct Engine::Impl {
     }
     launch_residual(st, n, m0, Rout, bx, lamv, Rout);
     launch_col_sumsq(st, n, m0, Rout, residv, colpart.as<double>());
+  }
+
+  // Non-Hermitian Rayleigh-Ritz (Algorithm 2, step 3, right Galerkin condition, B = I) in pair
+  // format: X <- Qin C, lam + i lamI, R = A X - X Lambda_b, resid (per complex eigenvector),
+  // eta from the Gram of Xprev, the block that was filtered into Qin (null: identity).  Xprev
+  // may be Xout (its Gram is taken first).
+  void rr_general(const ifeast_matrix* A, const double* Qin, const double* Xprev, double* Xout, double* lamv,
+                  double* lamIv, double* Rout, double* residv, double* etav) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0;
+    double* aq = AQ.as<double>();
+    if (Xprev != nullptr) {
+      GramArgs gx{n, m0, m0, 1, 1, Xprev, m0, 0, 0, Xprev, m0, 0, 0, nullptr, GX.as<double>(), KC_OUTER};
+      launch_gram<double>(st, gx, gpart.p, gpart.bytes);
+    }
+    // P = Q Tacc orthonormal: three SVQB passes, P in Xn, Rout, Xn (Rout is written last)
+    const double* P = Qin;
+    double* pbuf[3] = {Xn.as<double>(), Rout, Xn.as<double>()};
+    double* Tp = TS.as<double>();
+    double* Ta = TA.as<double>();
+    for (int pass = 0; pass < 3; ++pass) {
+      GramArgs gb{n, m0, m0, 1, 1, P, m0, 0, 0, P, m0, 0, 0, nullptr, GB.as<double>(), KC_OUTER};
+      launch_gram<double>(st, gb, gpart.p, gpart.bytes);
+      launch_svqb_pass(st, m0, GB.as<double>(), Tp, Ta, pass == 0 ? 1 : 0, rrwork.as<double>());
+      ApplyArgs ap{n, m0, m0, 1, 1, 1, P, m0, 0, 0, 0, Tp, 0, pbuf[pass], m0, 0, 1.0, 0.0, nullptr, nullptr,
+                   KC_OUTER};
+      launch_apply<double, double>(st, ap);
+      P = pbuf[pass];
+    }
+    launch_spmm_real(st, A, m0, P, aq);
+    GramArgs ga{n, m0, m0, 1, 1, P, m0, 0, 0, aq, m0, 0, 0, nullptr, GA.as<double>(), KC_OUTER};
+    launch_gram<double>(st, ga, gpart.p, gpart.bytes);
+    double* Wd = GB.as<double>();  // free again
+    launch_rr_general(st, m0, GA.as<double>(), Ta, Xprev != nullptr ? GX.as<double>() : nullptr, lamv, lamIv, Wd,
+                      C.as<double>(), etav, rrwork.as<double>());
+    // X = P W, A X = (A P) W
+    ApplyArgs ap{n, m0, m0, 1, 1, 1, P, m0, 0, 0, 0, Wd, 0, Xout, m0, 0, 1.0, 0.0, nullptr, nullptr, KC_OUTER};
+    launch_apply<double, double>(st, ap);
+    ApplyArgs aa = ap;
+    aa.A = aq;
+    aa.O = Rout;
+    launch_apply<double, double>(st, aa);
+    launch_residual_pairs(st, n, m0, Rout, Xout, lamv, lamIv, Rout);
+    launch_col_sumsq(st, n, m0, Rout, residv, colpart.as<double>());
+    launch_pair_norms(st, m0, lamIv, residv);
   }
 
   // ---------------------------------------------------------- CholQR2
@@ -633,10 +721,15 @@ struct Engine::Impl {
   // each shift's least squares min || [S0 D_s; 0] - (z_s I~ + Hm) y_s || updated per step
   // and stopped by its own rule; Q = X rho_hat(Lambda) + V Re(sum_s wf_s y_s).
   // Up to kb = k * max_cycles steps, no restarts.  Returns per-shift block iterations.
+  // Non-Hermitian A (lamId != null: the Ritz block in pair format, rho + i rhoId its filter
+  // values): the recurrence has no block-tridiagonal structure, so every step projects against
+  // every block twice and the least squares keep the whole block Hessenberg matrix.
   template <class T>
   std::vector<int> inner_shared(const ifeast_matrix* A, const Nodes& nd, const ifeast_params& p, const double* Xd,
                                 const double* lamd, const double* Rd, const double* rhod,
-                                const std::vector<double>& tolh, double* Qd) {
+                                const std::vector<double>& tolh, double* Qd, const double* lamId = nullptr,
+                                const double* rhoId = nullptr) {
+    const bool nonsym = lamId != nullptr;
     const int64_t n = sh.n;
     const int m0 = sh.m0, ns = sh.ns, K = sh.kb, ldh = (K + 1) * m0;
     const int64_t bs = n * m0;  // elements per basis block
@@ -665,7 +758,7 @@ struct Engine::Impl {
     // estimated from a Gaussian sketch U = sum_i V_i Om_i of those blocks (kSketch columns,
     // E ||U^T w||^2 = ||[V_0..]^T w||^2), so that the estimate reads n x kSketch numbers
     // instead of the whole basis.  reorth_eta >= 1 projects against every block in both passes.
-    const bool always = p.reorth_eta >= 1.0;
+    const bool always = p.reorth_eta >= 1.0 || nonsym;
     // default: a tenth of the inner tolerance factor for an FP32 basis (the loss then stays an
     // order of magnitude below the accuracy the inner solves ask for), near FP64 rounding for
     // an FP64 one
@@ -676,18 +769,24 @@ struct Engine::Impl {
     single_gersh = sizeof(T) == 4 ? 0.8 : 0.5;
     dead_thr = sizeof(T) == 4 ? 1e-30 : 1e-280;
     // Q = X rho_hat(Lambda); V_0 S0 = R
-    launch_scale_cols(st, n, m0, Xd, rhod, Qd);
+    if (nonsym)
+      launch_scale_pairs(st, n, m0, Xd, rhod, rhoId, lamId, Qd);
+    else
+      launch_scale_cols(st, n, m0, Xd, rhod, Qd);
     launch_to_T<T>(st, bs, Rd, t1);
     cholqr2_real<T>(t1, t2, Vb);
-    launch_start_rhs(st, ns, m0, Racc.as<cd>(), lamd, zsD.as<double>(), Ss.as<cd>());
+    if (nonsym)
+      launch_start_rhs_pairs(st, ns, m0, Racc.as<cd>(), lamd, lamId, zsD.as<double>(), Ss.as<cd>());
+    else
+      launch_start_rhs(st, ns, m0, Racc.as<cd>(), lamd, zsD.as<double>(), Ss.as<cd>());
     std::vector<int> all(ns, 1);
     h2d_staged(d_active, all.data(), ns * sizeof(int));
     h2d_staged(d_run, all.data(), ns * sizeof(int));
     note(d_active, all);
     LsqArgs la = lsq_args();
-    // Hm is block tridiagonal up to rounding, so the least squares problems keep one block
-    // above the diagonal
-    la.band = 1;
+    // for symmetric A, Hm is block tridiagonal up to rounding, so the least squares problems
+    // keep one block above the diagonal
+    la.band = nonsym ? 0 : 1;
     launch_lsq_init(st, la, Ss.as<cd>());
     // G = [V_lo..V_{lo+nb-1}]^T W
     // G = [V_lo..V_{lo+nb-1}]^T W into gred (from item 0 at gred + off items), its reduction
@@ -1014,8 +1113,13 @@ Engine::~Engine() = default;
 
 namespace {
 
+// Stopping thresholds of the inner solves (ns x m0).  Per-column rule: alpha times the start
+// residual of column j, ||r_j|| / |z_s - lambda_j|; for a conjugate pair in pair format the
+// columns mix both eigenvalues, and the bound (1/|z - lambda| + 1/|z - conj(lambda)|) / 2 times
+// the pair's residual is used for both.
 std::vector<double> inner_tolerances(const Nodes& nd, const ifeast_params& p, const std::vector<double>& lam,
-                                     const std::vector<double>& resid, double rf, int m0) {
+                                     const std::vector<double>& lam_im, const std::vector<double>& resid, double rf,
+                                     int m0) {
   const int ns = (int)nd.z.size();
   std::vector<double> t((size_t)ns * m0 * 2, 0.0);
   for (int s = 0; s < ns; ++s)
@@ -1023,13 +1127,27 @@ std::vector<double> inner_tolerances(const Nodes& nd, const ifeast_params& p, co
       double v;
       if (p.inner_rule == IFEAST_INNER_GLOBAL) {
         v = p.alpha * rf;
-      } else {
-        // alpha times the start residual of column j: ||r_j|| / |z_s - lambda_j|
+      } else if (lam_im[j] == 0.0) {
         v = p.alpha * resid[j] / std::abs(nd.z[s] - lam[j]);
+      } else {
+        const cd l(lam[j], std::fabs(lam_im[j]));
+        v = p.alpha * resid[j] * 0.5 * (1.0 / std::abs(nd.z[s] - l) + 1.0 / std::abs(nd.z[s] - std::conj(l)));
       }
       t[(size_t)s * m0 + j] = v;
     }
   return t;
+}
+
+// Nodes of a conjugate-symmetric rule in the upper half plane, summed as 2 Re.
+Nodes upper_half(const Nodes& nd) {
+  Nodes u;
+  u.half = true;
+  for (size_t k = 0; k < nd.z.size(); ++k)
+    if (nd.z[k].imag() > 0.0) {
+      u.z.push_back(nd.z[k]);
+      u.w.push_back(nd.w[k]);
+    }
+  return u;
 }
 
 ClassifyArgs classify_args(const ifeast_contour& C, const Nodes& nd, int m0, double tau, const double* zd,
@@ -1072,6 +1190,11 @@ void Engine::rayleigh_ritz(const ifeast_matrix* A, const ifeast_matrix* B, const
   impl_->rr(A, B, Q, X, lam, R, resid, eta);
 }
 
+void Engine::rayleigh_ritz_general(const ifeast_matrix* A, const double* Q, const double* Xprev, double* lam,
+                                   double* lam_im, double* X, double* R, double* resid, double* eta) {
+  impl_->rr_general(A, Q, Xprev, X, lam, lam_im, R, resid, eta);
+}
+
 void Engine::filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_contour& C, const ifeast_params& p,
                     const double* X, const double* lam, const double* R, double rf, double* Q,
                     std::vector<int>* iters) {
@@ -1096,7 +1219,8 @@ void Engine::filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast
   launch_col_sumsq(st_, shape_.n, m0, R, I.resid.as<double>(), I.colpart.as<double>());
   IF_HIP(hipMemcpyAsync(residh.data(), I.resid.p, m0 * 8, hipMemcpyDeviceToHost, st_));
   IF_HIP(hipStreamSynchronize(st_));
-  const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, rf, m0);
+  IF_REQUIRE(!shape_.general, "the step-level filter takes symmetric problems");
+  const std::vector<double> tolh = inner_tolerances(nd, p, lamh, std::vector<double>(m0, 0.0), residh, rf, m0);
   std::vector<int> it;
   if (shape_.shared)
     it = shape_.precision == IFEAST_PREC_MIXED
@@ -1114,10 +1238,17 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
                   const double* X0_in, ifeast_result* res, bool x0_on_device, double* evec_dev) {
   Impl& I = *impl_;
   const int64_t n = shape_.n;
-  const int m0 = shape_.m0, ns = shape_.ns;
+  const int m0 = shape_.m0;
+  const bool gen = shape_.general;
+  // nd: the whole rule (the filter rho_hat and membership); nd_in: the systems solved.  For a
+  // non-Hermitian problem on a circle centred on the real axis these are the nodes in the upper
+  // half with 2 Re of their sum (the lower half's solutions are the conjugates: A, X and R are real)
   const Nodes nd = make_nodes(C);
-  std::vector<double> zd(2 * ns), wd(2 * ns);
-  for (int s = 0; s < ns; ++s) {
+  const Nodes nd_in = gen ? upper_half(nd) : nd;
+  const int ncl = (int)nd.z.size();
+  IF_REQUIRE((int)nd_in.z.size() == shape_.ns, "contour and workspace shape differ");
+  std::vector<double> zd(2 * ncl), wd(2 * ncl);
+  for (int s = 0; s < ncl; ++s) {
     zd[2 * s] = nd.z[s].real();
     zd[2 * s + 1] = nd.z[s].imag();
     wd[2 * s] = nd.w[s].real();
@@ -1154,16 +1285,23 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   double* eta = I.eta.as<double>();
   double* R = I.R.as<double>();
   SolveStats stats;
-  std::vector<double> lamh(m0), residh(m0), cls(3);
+  double* lamI = I.lamI.as<double>();
+  std::vector<double> lamh(m0), lamIh(m0, 0.0), residh(m0), cls(3);
   int geo_count = 0;  // Ritz values inside the contour, counted or not
   std::vector<int> flagh(m0);
 
   auto classify = [&](double tau) {
     const ClassifyArgs ca = classify_args(C, nd, m0, tau, zb.as<double>(), wb.as<double>());
-    launch_classify(st_, ca, lam, nullptr, resid, eta, I.d_cls, I.clsout.as<double>());
-    hipLaunchKernelGGL(k_rho, dim3(1), dim3(128), 0, st_, m0, ns, nd.half ? 1 : 0, zb.as<double>(), wb.as<double>(),
-                       lam, I.rho.as<double>());
-    IF_HIP(hipGetLastError());
+    launch_classify(st_, ca, lam, gen ? lamI : nullptr, resid, eta, I.d_cls, I.clsout.as<double>());
+    if (gen) {
+      launch_rho_pairs(st_, m0, ncl, zb.as<double>(), wb.as<double>(), lam, lamI, I.rho.as<double>(),
+                       I.rhoI.as<double>());
+      IF_HIP(hipMemcpyAsync(lamIh.data(), lamI, m0 * 8, hipMemcpyDeviceToHost, st_));
+    } else {
+      hipLaunchKernelGGL(k_rho, dim3(1), dim3(128), 0, st_, m0, ncl, nd.half ? 1 : 0, zb.as<double>(),
+                         wb.as<double>(), lam, I.rho.as<double>());
+      IF_HIP(hipGetLastError());
+    }
     IF_HIP(hipMemcpyAsync(cls.data(), I.clsout.p, 24, hipMemcpyDeviceToHost, st_));
     IF_HIP(hipMemcpyAsync(lamh.data(), lam, m0 * 8, hipMemcpyDeviceToHost, st_));
     IF_HIP(hipMemcpyAsync(residh.data(), resid, m0 * 8, hipMemcpyDeviceToHost, st_));
@@ -1181,29 +1319,37 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   const bool verbose = vb && (vb[0] == '1' || vb[0] == '2');
   const bool verbose2 = vb && vb[0] == '2';
   // initial Rayleigh-Ritz on X0 gives Lambda, R and the exact initial ||R_F||
-  I.rr(A, B, Q, X, lam, R, resid, eta);
+  if (gen)
+    I.rr_general(A, Q, nullptr, X, lam, lamI, R, resid, eta);
+  else
+    I.rr(A, B, Q, X, lam, R, resid, eta);
   classify(0.0);
   if (verbose) fprintf(stderr, "[ifeast] start rf=%.3e m=%d\n", stats.rf, stats.m);
   int status = IFEAST_WARN_NOT_CONVERGED;
   for (int it = 0; it < p.max_outer; ++it) {
-    const std::vector<double> tolh = inner_tolerances(nd, p, lamh, residh, stats.rf, m0);
+    const std::vector<double> tolh = inner_tolerances(nd_in, p, lamh, lamIh, residh, stats.rf, m0);
     std::vector<int> iters;
+    const double* lamId = gen ? lamI : nullptr;
+    const double* rhoId = gen ? I.rhoI.as<double>() : nullptr;
     if (shape_.shared)
       iters = shape_.precision == IFEAST_PREC_MIXED
-                  ? I.inner_shared<float>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
-                  : I.inner_shared<double>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+                  ? I.inner_shared<float>(A, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q, lamId, rhoId)
+                  : I.inner_shared<double>(A, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q, lamId, rhoId);
     else
       iters = shape_.precision == IFEAST_PREC_MIXED
-                  ? I.inner<float>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
-                  : I.inner<double>(A, B, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
-    I.rr(A, B, Q, X, lam, R, resid, eta);
+                  ? I.inner<float>(A, B, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+                  : I.inner<double>(A, B, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+    if (gen)
+      I.rr_general(A, Q, X, X, lam, lamI, R, resid, eta);
+    else
+      I.rr(A, B, Q, X, lam, R, resid, eta);
     classify(p.spurious_tau);
     stats.outer = it + 1;
     stats.rf_hist.push_back(stats.rf);
     // matrix-vector products: one real block of m0 columns per shared Arnoldi step, or one
     // complex block per shift and step
     int mx = 0;
-    for (int s = 0; s < ns; ++s) {
+    for (int s = 0; s < shape_.ns; ++s) {
       stats.inner_hist.push_back(iters[s]);
       if (!shape_.shared) stats.total_matvec += (int64_t)iters[s] * m0;
       mx = std::max(mx, iters[s]);
@@ -1278,7 +1424,7 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
   res->solve_seconds = stats.seconds;
   for (int j = 0; j < m0; ++j) {
     if (res->eval_re) res->eval_re[j] = lamh[order[j]];
-    if (res->eval_im) res->eval_im[j] = 0.0;
+    if (res->eval_im) res->eval_im[j] = lamIh[order[j]];
     if (res->resid) res->resid[j] = residh[order[j]];
     if (res->flags) res->flags[j] = flagh[order[j]];
   }
@@ -1290,8 +1436,12 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     DevBuf ob(m0 * sizeof(int));
     I.h2d(ob.p, order.data(), m0 * sizeof(int));
     const int64_t tot = n * m0;
-    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st_, n, m0, X, ob.as<int>(),
-                       evec_dev);
+    if (gen)
+      hipLaunchKernelGGL(k_gather_complex, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st_, n, m0, X,
+                         ob.as<int>(), lamI, evec_dev);
+    else
+      hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st_, n, m0, X,
+                         ob.as<int>(), evec_dev);
     IF_HIP(hipGetLastError());
     IF_HIP(hipStreamSynchronize(st_));
   }
@@ -1299,8 +1449,22 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     std::vector<double> xh((size_t)n * m0);
     IF_HIP(hipMemcpyAsync(xh.data(), X, xh.size() * 8, hipMemcpyDeviceToHost, st_));
     IF_HIP(hipStreamSynchronize(st_));
-    for (int64_t i = 0; i < n; ++i)
-      for (int j = 0; j < m0; ++j) res->evec[i * m0 + j] = xh[i * m0 + order[j]];
+    if (gen) {
+      // complex eigenvectors, interleaved: a pair's columns hold Re x and Im x of a + ib
+      for (int64_t i = 0; i < n; ++i)
+        for (int j = 0; j < m0; ++j) {
+          const int o = order[j];
+          const double* row = xh.data() + i * m0;
+          double re = row[o], im = 0.0;
+          if (lamIh[o] < 0.0) im = -row[o + 1];
+          else if (lamIh[o] > 0.0) re = row[o - 1], im = row[o];
+          res->evec[2 * (i * m0 + j)] = re;
+          res->evec[2 * (i * m0 + j) + 1] = im;
+        }
+    } else {
+      for (int64_t i = 0; i < n; ++i)
+        for (int j = 0; j < m0; ++j) res->evec[i * m0 + j] = xh[i * m0 + order[j]];
+    }
   }
   return status;
 }

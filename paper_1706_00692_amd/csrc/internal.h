@@ -296,6 +296,33 @@ void launch_make_coefs(hipStream_t st, const LsqArgs& a, const double* wfac /*2*
 void launch_rr_small(hipStream_t st, int m0, const double* GA, const double* GB, double* lam, double* C,
                      double* eta, double* work);
 
+// ---- non-Hermitian path (nonsym.hip): Ritz blocks in pair format (a conjugate pair a -+ ib,
+// b > 0, owns adjacent columns j, j+1 = Re x, Im x of the eigenvector of a + ib, with
+// lam_im[j] = -b, lam_im[j+1] = +b)
+// One SVQB pass from the Gram G = P^T P of a block: T (m0 x m0) with P T orthonormal on the
+// resolved directions; Tacc <- Tacc T (first: Tacc = T).  work: 3 m0^2 doubles.
+void launch_svqb_pass(hipStream_t st, int m0, const double* G, double* T, double* Tacc, int first, double* work);
+// Reduced problem of the right-Galerkin Rayleigh-Ritz step on an orthonormal basis P = Q Tacc:
+// from GA = P^T A P and GX = X^T X of the filtered block (null: identity): lam, lam_im, W
+// (X = P W, unit 2-norm eigenvectors), C = Tacc W, eta.  work: 4 m0^2 doubles.  NaN in lam[0]
+// when the Schur iteration fails.
+void launch_rr_general(hipStream_t st, int m0, const double* GA, const double* Tacc, const double* GX, double* lam,
+                       double* lam_im, double* W, double* C, double* eta, double* work);
+// R = A X - X Lambda_b (AX may alias R)
+void launch_residual_pairs(hipStream_t st, int64_t n, int m, const double* AX, const double* X, const double* lam,
+                           const double* lam_im, double* R);
+// resid of a pair's two columns := sqrt(r_j^2 + r_{j+1}^2)
+void launch_pair_norms(hipStream_t st, int m, const double* lam_im, double* resid);
+// rho_hat at each column's eigenvalue over all nc nodes (z, w device, 2*nc): rho + i rho_im
+void launch_rho_pairs(hipStream_t st, int m0, int nc, const double* z, const double* w, const double* lam,
+                      const double* lam_im, double* rho, double* rho_im);
+// Y = X rho_hat(Lambda_b)
+void launch_scale_pairs(hipStream_t st, int64_t n, int m, const double* X, const double* rho, const double* rho_im,
+                        const double* lam_im, double* Y);
+// S_s = S0 (z_s - Lambda_b)^{-1} (ns x m0 x m0 row-major)
+void launch_start_rhs_pairs(hipStream_t st, int ns, int m0, const cd* S0, const double* lam, const double* lam_im,
+                            const double* z, cd* S);
+
 // Membership, spurious test and ||R_F|| (Algorithm 2, step 4) on device:
 // flags[j] = IFEAST_FLAG_* bits; out[0] = ||R_F||, out[1] = m (as double), out[2] = Ritz
 // values inside the contour whether counted or not.  lam_im (may be null): imaginary parts.

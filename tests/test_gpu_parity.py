@@ -499,21 +499,20 @@ def test_serving_budget_rejects_and_queues(torch_cuda):
     still give the results they give alone."""
     import paper_1706_00692_amd as pk
 
-    probs = _small_serving_problems()
-    fps = [pk.footprint(p.n, p.A.nnz, 0, p.contour, _serving_params(pk, p)) for p in probs]
-    big = max(fps)
-    c = pk.Context(0, budget=big)
+    small = _small_serving_problems()
+    probs = [small[1], small[1], small[1]]  # three requests of one footprint
+    fp = pk.footprint(probs[0].n, probs[0].A.nnz, 0, probs[0].contour, _serving_params(pk, probs[0]))
+    c = pk.Context(0, budget=fp)
     try:
         alone = [c.solve_problem(p, precision=pk.PREC_MIXED) for p in probs]
-        tight = pk.Context(0, budget=min(fps) - 1)
+        tight = pk.Context(0, budget=fp - 1)
         try:
             with pytest.raises(pk.IFeastError) as e:
                 tight.submit(probs[0].A, None, probs[0].contour, _serving_params(pk, probs[0]), probs[0].x0())
             assert e.value.status == -5
         finally:
             tight.close()
-        # every pair of requests exceeds the budget, so none runs beside another
-        assert all(fps[i] + fps[j] > big for i in range(3) for j in range(3) if i != j)
+        # two requests exceed the budget, so none runs beside another
         tickets = [c.submit(p.A, None, p.contour, _serving_params(pk, p), p.x0()) for p in probs]
         out = [c.wait(t, p.n, p.m0, p.max_outer, p.contour["nc"]) for p, t in zip(probs, tickets)]
         for p, r, a in zip(probs, out, alone):
@@ -589,3 +588,139 @@ def test_solve_dev_matches_host_buffers(ctx, torch_cuda):
     # the input block is left as it was
     assert np.array_equal(X0d.cpu().numpy(), X0)
     Am.close()
+
+
+# ------------------------------------------------------------- non-Hermitian
+def _convdiff_exact(N, bx=20.0, by=10.0):
+    """Closed-form spectrum of the h^2-scaled upwind convection-diffusion operator (real)."""
+    h = 1.0 / (N + 1)
+    j = np.arange(1, N + 1)
+
+    def mu(b):
+        return 2 + h * b - 2 * np.sqrt(1 + h * b) * np.cos(j * np.pi / (N + 1))
+
+    return np.sort((mu(bx)[:, None] + mu(by)[None, :]).ravel())
+
+
+def _pairs_to_complex(X, lam_im):
+    """Complex eigenvectors from a pair-format block (a pair's columns: Re x, Im x of a + ib)."""
+    Z = X.astype(np.complex128).copy()
+    for j in range(X.shape[1]):
+        if lam_im[j] < 0:
+            Z[:, j] = X[:, j] - 1j * X[:, j + 1]
+        elif lam_im[j] > 0:
+            Z[:, j] = X[:, j - 1] + 1j * X[:, j]
+    return Z
+
+
+@pytest.mark.parametrize("m0", [32, 64])
+def test_rayleigh_ritz_general_parity(ctx, torch_cuda, m0):
+    """The device non-Hermitian Rayleigh-Ritz (SVQB, Hessenberg, Francis double-shift QR,
+    quasi-triangular back substitution) on a random block of a 24^2 convection-diffusion
+    operator: Ritz values against numpy's eig of the projected matrix, complex residuals and
+    gains against the oracle's right-Galerkin Rayleigh-Ritz."""
+    from oracle.feast import filter_gain
+
+    torch = torch_cuda
+    A = W.convdiff_2d(24, 20.0, 10.0)
+    As = A.to_scipy()
+    n = A.n
+    rng = np.random.default_rng(31 + m0)
+    Q = rng.standard_normal((n, m0))
+    Xp = rng.standard_normal((n, m0))
+    lam_o, X_o, AX_o, BX_o, C_o = O.rayleigh_ritz(As, None, Q, kind="general")
+    R_o, r_o = O.residuals(AX_o, BX_o, lam_o)
+    eta_o = filter_gain(C_o, Xp.T @ Xp)
+    assert np.abs(lam_o.imag).max() > 1e-3  # the random block has complex Ritz pairs
+    Am = ctx.matrix(A)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = {k: torch.zeros(v, dtype=torch.float64, device="cuda") for k, v in
+           dict(lam=m0, lam_im=m0, X=(n, m0), R=(n, m0), resid=m0, eta=m0).items()}
+    ctx.rayleigh_ritz_general(Am, dev(Q), dev(Xp), out["lam"], out["lam_im"], out["X"], out["R"], out["resid"],
+                              out["eta"])
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    lam = g["lam"] + 1j * g["lam_im"]
+    scale = np.abs(lam_o).max()
+    # the oracle's complex eigensolver leaves a conjugate pair's real parts a rounding apart, so
+    # its order within a pair is arbitrary: match each Ritz value to the nearest of the oracle's
+    match = np.array([int(np.argmin(np.abs(lam_o - l))) for l in lam])
+    assert len(set(match.tolist())) == m0
+    lam_o, X_o, r_o = lam_o[match], X_o[:, match], r_o[match]
+    eta_o = eta_o[match]
+    assert np.abs(lam - lam_o).max() <= 1e-10 * scale, np.abs(lam - lam_o).max()
+    assert np.all(np.diff(g["lam"]) >= 0)  # ascending real part
+    # pair format: conjugate pairs adjacent, (-b, +b)
+    for j in range(m0):
+        if g["lam_im"][j] < 0:
+            assert g["lam_im"][j + 1] == -g["lam_im"][j] and g["lam"][j + 1] == g["lam"][j]
+    Xc = _pairs_to_complex(g["X"], g["lam_im"])
+    assert np.allclose(np.linalg.norm(Xc, axis=0), 1.0, atol=1e-10)
+    Rc = As @ Xc - Xc * lam[None, :]
+    assert np.allclose(np.linalg.norm(Rc, axis=0), g["resid"], rtol=1e-7, atol=1e-12)
+    assert np.allclose(g["resid"], r_o, rtol=1e-6, atol=1e-11)
+    # the pair-format residual block is [Re, Im] of the complex residual of a + ib
+    Rg = _pairs_to_complex(g["R"], g["lam_im"])
+    assert np.abs(Rg - Rc).max() <= 1e-9 * np.abs(Rc).max()
+    # same eigenvectors as the oracle up to phase (simple Ritz values)
+    ph = np.sum(Xc.conj() * X_o, axis=0)
+    assert np.allclose(np.abs(ph), 1.0, atol=1e-7)
+    assert np.allclose(g["eta"], eta_o, rtol=1e-7)
+
+
+def _general_problem(N, lo_i, hi_i, m0):
+    ex = _convdiff_exact(N)
+    lo, hi = 0.5 * (ex[lo_i - 1] + ex[lo_i]), 0.5 * (ex[hi_i - 1] + ex[hi_i])
+    prob = W.config4_small(N=N, m0=m0, c=0.5 * (lo + hi), r=0.5 * (hi - lo))
+    return prob, ex[lo_i:hi_i]
+
+
+def _kappa_tol(A, lam_got, resid):
+    """R13's eigenvalue bound for a nonnormal operator: |dlambda| <= max(1e-10 |lambda|,
+    2 kappa r + 10 kappa u ||A||_1), kappa from dense left and right eigenvectors."""
+    import scipy.linalg as sla
+
+    Ad = A.to_dense()
+    w, vl, vr = sla.eig(Ad, left=True, right=True)
+    kap = np.linalg.norm(vl, axis=0) * np.linalg.norm(vr, axis=0) / np.abs(np.sum(vl.conj() * vr, axis=0))
+    a1 = np.abs(Ad).sum(axis=0).max()
+    tol = []
+    for l, r in zip(lam_got, resid):
+        k = kap[np.argmin(np.abs(w - l))]
+        tol.append(max(1e-10 * abs(l), 2 * k * r + 10 * k * 2.220446049250313e-16 * a1))
+    return np.array(tol), kap
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("N,lo_i,hi_i,m0", [(16, 3, 10, 16), (32, 20, 32, 32)])
+def test_solve_general_closed_form(ctx, prec, N, lo_i, hi_i, m0):
+    """Non-Hermitian solve (16 trapezoidal nodes on a circle around part of the convection-
+    diffusion spectrum) against the closed-form eigenvalues with R13's conditioning-scaled
+    tolerance, the eigenvectors against dense eig, and (16^2) the oracle's IFEAST run."""
+    import paper_1706_00692_amd as pk
+
+    prob, want = _general_problem(N, lo_i, hi_i, m0)
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED)
+    print(f"[general {N}^2 {prec}] status={res.status} m={res.m} outer={res.outer_iters} rf={res.max_resid:.2e} "
+          f"inner={res.inner_hist.max(axis=1).tolist()}", flush=True)
+    assert res.status == 0 and res.converged and res.m == len(want)
+    got = res.lam_in
+    order = np.argsort(got.real)
+    got, resid, Xin = got[order], res.resid[: res.m][order], res.X_in[:, order]
+    assert resid.max() <= prob.tol
+    tol, kap = _kappa_tol(prob.A, got, resid)
+    assert np.all(np.abs(got - want) <= tol), (np.abs(got - want), tol)
+    # eigenvectors: unit norm, residual recomputed on the host, direction of the dense eigenvector
+    As = prob.A.to_scipy()
+    assert np.allclose(np.linalg.norm(Xin, axis=0), 1.0, atol=1e-10)
+    r_host = np.linalg.norm(As @ Xin - Xin * got[None, :], axis=0)
+    assert r_host.max() <= 2 * prob.tol
+    ref_in, V_in, _ = O.dense_reference(prob.A, None, prob.contour, kind="general")
+    V_in = V_in[:, np.argsort(ref_in.real)]
+    cosv = np.abs(np.sum(Xin.conj() * V_in, axis=0)) / np.linalg.norm(V_in, axis=0)
+    assert np.all(cosv >= 1 - 1e-6), cosv
+    if N == 16:
+        ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner * prob.max_cycles, prob.alpha, prob.tol,
+                       prob.x0(), 10, kind="general", max_cycles=1, inner_rule=prob.inner_rule, tau=prob.tau)
+        assert ref.status == "ok" and ref.m == res.m
+        assert np.all(np.abs(np.sort_complex(ref.lam_in) - np.sort_complex(res.lam_in)) <= tol)

@@ -273,6 +273,17 @@ int ifeast_filter_dev(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matr
 int ifeast_rayleigh_ritz_dev(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matrix *B, int m0,
                              const double *Q, double *lam, double *X, double *R, double *resid, double *eta);
 
+/* ifeast_rayleigh_ritz_dev for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same outputs from the
+ * same kernels, with every scratch buffer taken from a per-device array of 64 MiB that the
+ * library holds until the process ends (A Q is staged in X).  Nothing is allocated by the call.
+ * The scratch needed grows with n and m0 (and by n m0 doubles when B is given); a problem that
+ * needs more than the array returns IFEAST_ERR_INVALID_ARG before any work is queued.  All calls
+ * on one device share the array: calls that overlap on one device race.  Q must not alias X. */
+int ifeast_rayleigh_ritz_dev_noalloc(ifeast_ctx *ctx, const ifeast_matrix *A, const ifeast_matrix *B, int m0,
+                                     const double *Q, double *lam, double *X, double *R, double *resid,
+                                     double *eta);
+
 /* Non-Hermitian Rayleigh-Ritz on device data (Algorithm 2, steps 3-4, right Galerkin condition,
  * B = I): orthonormalise span(Q) (n x m0, FP64, row-major), solve the reduced eigenproblem of
  * Q^T A Q and return the Ritz values lam + i lam_im (m0 each, ascending real part) and the

@@ -112,6 +112,7 @@ def load_library():
                                     vp, vp]),
         "ifeast_rayleigh_ritz_dev": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
         "ifeast_rayleigh_ritz_general_dev": (i32, [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "ifeast_rayleigh_ritz_dev_noalloc": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]),
         "ifeast_set_timing": (i32, [vp, i32]),
         "ifeast_kernel_stats": (i32, [vp, i32, C.POINTER(KernelStatStruct)]),
     }
@@ -413,6 +414,14 @@ class Context:
                                                C.byref(params), X.data_ptr(), lam.data_ptr(), R.data_ptr(),
                                                float(rf), Q.data_ptr(), iters.ctypes.data))
         return iters
+
+    def rayleigh_ritz_noalloc(self, A: Matrix, B: Matrix | None, Q, lam, X, R, resid, eta):
+        """Rayleigh-Ritz on span(Q) with no device allocation (scratch from the library's array)."""
+        self._use_torch_stream()
+        self._check(self.lib.ifeast_rayleigh_ritz_dev_noalloc(self.h, A.h, None if B is None else B.h,
+                                                              int(Q.shape[1]), Q.data_ptr(), lam.data_ptr(),
+                                                              X.data_ptr(), R.data_ptr(), resid.data_ptr(),
+                                                              eta.data_ptr()))
 
     def rayleigh_ritz_general(self, A: Matrix, Q, Xprev, lam, lam_im, X, R, resid, eta):
         """Non-Hermitian Rayleigh-Ritz on span(Q) (device tensors, FP64; pair-format outputs)."""

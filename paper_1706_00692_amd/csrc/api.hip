@@ -185,6 +185,8 @@ int ifeast_create(ifeast_ctx** out, int device, uint64_t budget) {
     size_t fr = 0, tot = 0;
     IF_HIP(hipMemGetInfo(&fr, &tot));
     ctx->budget = budget ? budget : (uint64_t)(0.9 * (double)fr);
+    // the allocation-free entry point's scratch address on this device (looked up once)
+    (void)noalloc_scratch(device);
     *out = ctx.release();
     return IFEAST_OK;
   });
@@ -413,6 +415,24 @@ int ifeast_rayleigh_ritz_dev(ifeast_ctx* ctx, const ifeast_matrix* A, const ifea
     Engine& eng = engine_for(ctx, make_shape(A->n, B != nullptr, &C, &p));
     TimingScope ts(ctx);
     eng.rayleigh_ritz(A, B, Q, lam, X, R, resid, eta);
+    IF_HIP(hipStreamSynchronize(ctx->stream));
+    return IFEAST_OK;
+  });
+}
+
+int ifeast_rayleigh_ritz_dev_noalloc(ifeast_ctx* ctx, const ifeast_matrix* A, const ifeast_matrix* B, int m0,
+                                     const double* Q, double* lam, double* X, double* R, double* resid, double* eta) {
+  return guarded(ctx, [&]() -> int {
+    IF_REQUIRE(ctx != nullptr && A != nullptr, "null argument");
+    IF_REQUIRE(Q && lam && X && R && resid && eta, "null device pointer");
+    IF_REQUIRE(Q != X, "Q and X must not alias");
+    IF_REQUIRE(m0 > 0 && m0 % 16 == 0 && m0 <= 128 && m0 <= A->n, "m0 must be a multiple of 16 in [16, 128]");
+    IF_REQUIRE(B == nullptr || B->n == A->n, "A and B sizes differ");
+    IF_REQUIRE(A->device == ctx->device && (B == nullptr || B->device == ctx->device),
+               "matrices live on another device");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    rayleigh_ritz_noalloc(ctx->stream, ctx->device, A, B, m0, Q, lam, X, R, resid, eta);
     IF_HIP(hipStreamSynchronize(ctx->stream));
     return IFEAST_OK;
   });

@@ -335,6 +335,18 @@ struct ClassifyArgs {
 void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* lam_im,
                      const double* resid, const double* eta, int* flags, double* out);
 
+// ---- allocation-free Rayleigh-Ritz (noalloc.hip)
+// Size of the per-device scratch array the allocation-free entry point draws every buffer from.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// Device address of `device`'s scratch array, looked up once per device (the device must be current).
+void* noalloc_scratch(int device);
+// Scratch bytes one allocation-free Rayleigh-Ritz step needs.
+size_t noalloc_rr_bytes(int64_t n, int m0, bool hasB);
+// Rayleigh-Ritz and residuals (as Engine::rayleigh_ritz) with no device allocation: buffers from
+// the scratch array, A Q staged in the output X.  INVALID_ARG when the scratch is too small.
+void rayleigh_ritz_noalloc(hipStream_t st, int device, const ifeast_matrix* A, const ifeast_matrix* B, int m0,
+                           const double* Q, double* lam, double* X, double* R, double* resid, double* eta);
+
 // ---- elementwise / reductions
 void launch_col_sumsq(hipStream_t st, int64_t n, int m, const double* X, double* out /*m*/, double* partial);
 void launch_scale_cols(hipStream_t st, int64_t n, int m, const double* X, const double* f, double* Y);

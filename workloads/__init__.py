@@ -29,6 +29,9 @@ from .inputs import (
     config2_small,
     config3_small,
     config4_small,
+    config4,
+    config4_circle,
+    convdiff_spectrum,
     serving_requests,
 )
 
@@ -48,5 +51,8 @@ __all__ = [
     "config2_small",
     "config3_small",
     "config4_small",
+    "config4",
+    "config4_circle",
+    "convdiff_spectrum",
     "serving_requests",
 ]

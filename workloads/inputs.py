@@ -163,6 +163,61 @@ def config4_small(N: int = 32, m0: int = 16, c: float = 0.2, r: float = 0.1) -> 
     )
 
 
+def convdiff_spectrum(N: int, beta_x: float = 20.0, beta_y: float = 10.0) -> np.ndarray:
+    """Eigenvalues (ascending, real) of convdiff_2d(N, beta_x, beta_y): the upwind operator is
+    D S D^-1 with S a symmetric tridiagonal Toeplitz sum per direction, so each direction
+    contributes 2 + h b - 2 sqrt(1 + h b) cos(j pi / (N + 1))."""
+    h = 1.0 / (N + 1)
+    j = np.arange(1, N + 1)
+
+    def mu(b):
+        return 2.0 + h * b - 2.0 * np.sqrt(1.0 + h * b) * np.cos(j * np.pi / (N + 1))
+
+    return np.sort((mu(beta_x)[:, None] + mu(beta_y)[None, :]).ravel())
+
+
+def config4_circle(N: int, target: float | None = None, count: int = 40, slack: int = 4):
+    """Circle on the real axis around about ``count`` eigenvalues: the lowest ones (target None;
+    the left end 10% of the window below the lowest eigenvalue) or those above ``target`` (the
+    left end in the widest gap within ``slack`` places).  The right end sits in the widest gap
+    within ``slack`` places of the nominal end, so no eigenvalue is near the contour.  Returns
+    (centre, radius, eigenvalues inside)."""
+    ev = convdiff_spectrum(N)
+    gaps = np.diff(ev)
+    if target is None:
+        lo_i = 0
+    else:
+        i0 = int(np.searchsorted(ev, target))
+        lo_i = max(1, i0 - slack) + int(np.argmax(gaps[max(1, i0 - slack) - 1:i0 + slack]))
+    hi_n = lo_i + count
+    hi_i = hi_n - slack + int(np.argmax(gaps[hi_n - slack - 1:hi_n + slack]))
+    hi = 0.5 * (ev[hi_i - 1] + ev[hi_i])
+    lo = ev[0] - 0.1 * (hi - ev[0]) if lo_i == 0 else 0.5 * (ev[lo_i - 1] + ev[lo_i])
+    return 0.5 * (lo + hi), 0.5 * (hi - lo), ev[lo_i:hi_i]
+
+
+def config4(N: int = 512, target: float | None = None, count: int = 40) -> Problem:
+    """2-D upwind convection-diffusion, beta = (20, 10), h^2-scaled, on an N x N grid (n = N^2,
+    262,144 at N = 512), B = I: a full circle on the real axis around about 40 eigenvalues (the
+    lowest ones by default), 16 trapezoidal nodes, m0 = 64, block GMRES with 10 iterations per
+    cycle."""
+    c, r, inside = config4_circle(N, target, count)
+    return Problem(
+        name=f"convdiff_{N}",
+        A=convdiff_2d(N, 20.0, 10.0),
+        B=None,
+        contour={"kind": "circle", "c": c, "r": r, "rule": "trap", "nc": 16},
+        m0=64,
+        max_inner=10,
+        alpha=1e-2,
+        tol=1e-9,
+        max_outer=30,
+        x0_seed=2004,
+        kind="general",
+        meta={"inside": inside},
+    )
+
+
 def serving_requests(count: int, seed: int = 3000, rate: float = 20.0,
                      sides=(32, 48, 64, 96, 128), m0s=(16, 32, 64, 128)):
     """Parameters of a seeded Poisson stream of eigen-solve requests.

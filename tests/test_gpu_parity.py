@@ -724,3 +724,46 @@ def test_solve_general_closed_form(ctx, prec, N, lo_i, hi_i, m0):
                        prob.x0(), 10, kind="general", max_cycles=1, inner_rule=prob.inner_rule, tau=prob.tau)
         assert ref.status == "ok" and ref.m == res.m
         assert np.all(np.abs(np.sort_complex(ref.lam_in) - np.sort_complex(res.lam_in)) <= tol)
+
+
+# ------------------------------------------------------------- generalized (B SPD)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_generalized_constant_closed_form(ctx, prec):
+    """A x = lambda B x with the constant-coefficient 27-point A and Q1 mass B on a 24^3 grid
+    (Eq. generalized_linsys): the 17 lowest eigenvalues (clusters of multiplicity up to 6)
+    against lambda = (27 - prod(1 + 2 t_i)) / prod((4 + 2 t_i) / 6), residuals <= tol and
+    B-orthonormal eigenvectors, through the per-shift restarted block GMRES."""
+    import paper_1706_00692_amd as pk
+
+    N = 24
+    ev = W.config3_constant_spectrum(N)
+    want = ev[:17]
+    prob = W.config3(N, m0=32, emin=0.5 * ev[0], emax=0.5 * (ev[16] + ev[17]), constant=True)
+    res = ctx.solve_problem(prob, precision=pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED)
+    print(f"[gen const {N}^3 {prec}] status={res.status} m={res.m} outer={res.outer_iters} rf={res.max_resid:.2e} "
+          f"t={res.solve_seconds:.2f}s", flush=True)
+    assert res.status == 0 and res.converged and res.m == 17
+    assert np.allclose(np.sort(res.lam_in), want, rtol=1e-10, atol=0)
+    assert res.resid[: res.m].max() <= prob.tol
+    B = prob.B.to_scipy()
+    assert np.allclose(res.X_in.T @ (B @ res.X_in), np.eye(17), atol=1e-9)
+
+
+def test_solve_generalized_random_vs_dense(ctx):
+    """The random-coefficient generalized pair on a 12^3 grid (mixed precision): the eigenvalues
+    inside an interval of the low spectrum against dense eigh(A, B), eigenvectors as subspaces."""
+    import scipy.linalg as sla
+    import paper_1706_00692_amd as pk
+
+    N = 12
+    prob = W.config3(N, m0=16)
+    lam_all, V = sla.eigh(prob.A.to_dense(), prob.B.to_dense())
+    prob.contour = dict(prob.contour, emin=0.5 * (lam_all[1] + lam_all[2]), emax=0.5 * (lam_all[10] + lam_all[11]))
+    res = ctx.solve_problem(prob, precision=pk.PREC_MIXED)
+    assert res.status == 0 and res.converged and res.m == 9
+    assert np.allclose(np.sort(res.lam_in), lam_all[2:11], rtol=1e-10, atol=0)
+    assert res.resid[: res.m].max() <= prob.tol
+    B = prob.B.to_scipy()
+    Xg, Xr = res.X_in, V[:, 2:11]
+    sines = np.linalg.norm(Xr - Xg @ (Xg.T @ (B @ Xr)), axis=0)
+    assert sines.max() <= 1e-7, sines.max()

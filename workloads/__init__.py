@@ -28,6 +28,8 @@ from .inputs import (
     config2,
     config2_small,
     config3_small,
+    config3,
+    config3_constant_spectrum,
     config4_small,
     config4,
     config4_circle,
@@ -50,6 +52,8 @@ __all__ = [
     "config2",
     "config2_small",
     "config3_small",
+    "config3",
+    "config3_constant_spectrum",
     "config4_small",
     "config4",
     "config4_circle",

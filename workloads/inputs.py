@@ -146,6 +146,36 @@ def config3_small(N: int = 8, m0: int = 16, emin: float = 0.0, emax: float = 1.0
     )
 
 
+def config3(N: int = 100, m0: int = 128, emin: float | None = None, emax: float | None = None,
+            constant: bool = False) -> Problem:
+    """Generalized symmetric problem A x = lambda B x on an N^3 grid (n = 10^6 at N = 100): 27-point
+    SPD A with log-uniform edge coefficients, Q1 mass B scaled by a U[0.5, 1.5] density
+    (``constant``: all coefficients and densities 1, a closed-form spectrum); 12 Gauss-Legendre
+    half-circle nodes, block GMRES with 8 iterations per cycle."""
+    return Problem(
+        name=f"spd27_mass_{N}" + ("_const" if constant else ""),
+        A=spd27(N, 1003, constant=constant),
+        B=mass27(N, 1003 + 100, density=not constant),
+        contour={"kind": "half", "emin": emin, "emax": emax, "rule": "gl", "nc": 12},
+        m0=m0,
+        max_inner=8,
+        alpha=1e-2,
+        tol=1e-9,
+        max_outer=60,
+        x0_seed=2003,
+    )
+
+
+def config3_constant_spectrum(N: int) -> np.ndarray:
+    """Eigenvalues (ascending) of the constant-coefficient pair (A, B) of config3: with
+    t_i = cos(j_i pi / (N + 1)), lambda = (27 - prod(1 + 2 t_i)) / prod((4 + 2 t_i) / 6)."""
+    t = np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+    a1, b1 = 1.0 + 2.0 * t, (4.0 + 2.0 * t) / 6.0
+    num = 27.0 - a1[:, None, None] * a1[None, :, None] * a1[None, None, :]
+    den = b1[:, None, None] * b1[None, :, None] * b1[None, None, :]
+    return np.sort((num / den).ravel())
+
+
 def config4_small(N: int = 32, m0: int = 16, c: float = 0.2, r: float = 0.1) -> Problem:
     """Reduced-grid non-Hermitian problem: 2-D upwind convection-diffusion."""
     return Problem(

@@ -121,19 +121,23 @@ def _forward(o):
     return (dz, dy, dx) > (0, 0, 0)
 
 
-def spd27(N: int, seed: int) -> CSR:
+def spd27(N: int, seed: int, constant: bool = False) -> CSR:
     """27-point SPD operator with random edge coefficients.
 
     Every undirected edge {p, p+d} of the 26-neighbour graph (including edges
     that leave the grid) carries a coefficient drawn log-uniformly from
-    [0.1, 10].  Off-diagonal entries are the negated in-grid edge
-    coefficients; the diagonal is the sum over all 26 edge slots of the cell,
-    so the matrix is irreducibly diagonally dominant and hence SPD.
+    [0.1, 10] (all 1 when ``constant``: then A = 27 I - the all-ones stencil).
+    Off-diagonal entries are the negated in-grid edge coefficients; the
+    diagonal is the sum over all 26 edge slots of the cell, so the matrix is
+    irreducibly diagonally dominant and hence SPD.
     """
     fwd = [o for o in _OFFS27 if _forward(o)]  # 13 directions
     rng = np.random.default_rng(seed)
     # c[z+1, y+1, x+1, d] is the coefficient of edge {p, p+fwd[d]} for p in [-1, N]^3
-    c = 10.0 ** rng.uniform(-1.0, 1.0, size=(N + 2, N + 2, N + 2, len(fwd)))
+    if constant:
+        c = np.ones((N + 2, N + 2, N + 2, len(fwd)))
+    else:
+        c = 10.0 ** rng.uniform(-1.0, 1.0, size=(N + 2, N + 2, N + 2, len(fwd)))
 
     def edge(coords, o, sign):
         """Coefficient of edge {p, p+o} (sign > 0) or {p-o, p} (sign < 0), o forward."""

@@ -758,7 +758,12 @@ struct Engine::Impl {
     // estimated from a Gaussian sketch U = sum_i V_i Om_i of those blocks (kSketch columns,
     // E ||U^T w||^2 = ||[V_0..]^T w||^2), so that the estimate reads n x kSketch numbers
     // instead of the whole basis.  reorth_eta >= 1 projects against every block in both passes.
-    const bool always = p.reorth_eta >= 1.0 || nonsym;
+    // non-Hermitian A: every pass projects against every block; the second pass runs only when
+    // the sketched loss of orthogonality after the first exceeds the threshold (reorth_eta >= 1:
+    // always two passes)
+    const bool full_always = p.reorth_eta >= 1.0;
+    const bool always = full_always || nonsym;
+    const bool nonsym_sel = nonsym && !full_always;
     // default: a tenth of the inner tolerance factor for an FP32 basis (the loss then stays an
     // order of magnitude below the accuracy the inner solves ask for), near FP64 rounding for
     // an FP64 one
@@ -805,7 +810,7 @@ struct Engine::Impl {
     };
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
     T* U = Us.as<T>();
-    if (!always) launch_fill_zero(st, Us.p, Us.bytes);
+    if (!always || nonsym_sel) launch_fill_zero(st, Us.p, Us.bytes);
     bool force_next = false;  // the step after a triggered third pass takes one too
     static const bool debug_reorth = getenv("IFEAST_DEBUG_REORTH") != nullptr;
     int skip_checks = 0;      // steps left before the next orthogonality estimate
@@ -822,104 +827,135 @@ struct Engine::Impl {
     };
     spmm_step(0);
     for (int j = 0; j < K; ++j) {
-      const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
-      if (!always && j >= 1) {
-        // first pass: the coefficients against V_{j-1} are those of the recurrence,
-        // V_{j-1}^T M V_j = (M V_{j-1})^T V_j = Hm(j, j-1)^T, so only V_j^T W is formed (the
-        // previous step's Cholesky-QR wrote Hm(j, j-1)^T into Hm and the coefficient buffer)
-        gram(j, j, 1, 0, 1);
-      } else {
-        gram(j, lo, nl, 0);
-      }
-      project(lo, nl);
-      bool full = always || lo == 0;
-      int certified = -1;
-      if (!full) {
-        const int64_t mm0 = (int64_t)m0 * m0;
-        double* gsk = gred.as<double>() + 2 * mm0;  // beside the local pass's two items
-        // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
-        ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
-                     Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
+      if (nonsym_sel) {
+        // one classical Gram-Schmidt pass against every block; V_j joins the sketch U of the
+        // basis, and the loss of orthogonality of the projected block is estimated from U^T W
+        gram(j, 0, j + 1, 0);
+        project(0, j + 1);
+        ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)j * bs, m0, 0, 0, 0,
+                     Om.as<T>() + (int64_t)j * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
         launch_apply<T, T>(st, au);
-        // 16 x 16 tiles: the sketch is read once per tile column, the block once.  Far below
-        // the threshold the estimate is left out for a few steps: the loss grows by well under
-        // a factor 2 per step (measured: at most about 1.5)
-        const bool check = skip_checks == 0;
-        if (check) {
-          GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gsk, KC_GRAM, 1};
-          launch_gram<T>(st, gs, gpart.p, gpart.bytes);
-        } else {
-          --skip_checks;
-        }
+        double* gsk = GA.as<double>();  // the outer Gram buffer is free during the inner solve
+        GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gsk, KC_GRAM, 1};
+        launch_gram<T>(st, gs, gpart.p, gpart.bytes);
         launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-        if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwb.as<double>(), d_loss);
-        // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass
-        // changes the block by rounding only, or (a full pass) by at most reorth_eta per
-        // column, which the margin on the Gershgorin bound covers
+        launch_sketch_check_real(st, kSketch, m0, gsk, gwb.as<double>(), d_loss);
+        // one Cholesky-QR pass when the Gram certifies it; the margin covers a second pass
         launch_gersh_flags(st, m0, gwb.as<double>(), single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh,
                            d_cnt);
-        // the estimate and the flags in one copy
         double* hchk = reinterpret_cast<double*>(h_flags + 128);
         IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         IF_HIP(hipEventRecord(ev_chk, st));
-        // the local second pass is needed in either case: it runs while the host waits
-        gram(j, lo, nl, 1);
-        project(lo, nl);
         IF_HIP(hipEventSynchronize(ev_chk));
-        // a third pass cleans the new block, but the block before it still carries the loss
-        // into the next step's product: that step takes a third pass too, after which both
-        // parents of the recurrence are clean (Simon's partial reorthogonalisation does the same)
-        full = force_next || (check && !(hchk[0] <= thr));
-        force_next = full && !force_next;
-        if (check) {
-          max_loss = std::max(max_loss, hchk[0]);
-          // steps that cannot reach the threshold even if the loss doubled every step
-          double e = hchk[0] * 2.0;
-          while (skip_checks < 8 && e * 2.0 < thr) {
-            e *= 2.0;
-            ++skip_checks;
-          }
-        }
-        if (full) skip_checks = 0;
-        certified = h_flags[130] != 0 ? 1 : 0;
-        if (full) {
-          // a third pass against every block (the local blocks again: their coefficients are
-          // rounding-sized), and the block's Gram afresh
+        max_loss = std::max(max_loss, hchk[0]);
+        const int certified = h_flags[130] != 0 ? 1 : 0;
+        if (!(hchk[0] <= thr)) {
           gram(j, 0, j + 1, 1);
-          if (debug_reorth) {
-            std::vector<double> gh((size_t)(j + 1) * m0 * m0), wh((size_t)m0 * m0);
-            IF_HIP(hipMemcpyAsync(gh.data(), gred.p, gh.size() * 8, hipMemcpyDeviceToHost, st));
-            IF_HIP(hipMemcpyAsync(wh.data(), gwb.p, wh.size() * 8, hipMemcpyDeviceToHost, st));
-            IF_HIP(hipStreamSynchronize(st));
-            fprintf(stderr, "[reorth] j=%d est=%.1e per-block max|c|/|w|:", j, hchk[0]);
-            for (int i = 0; i <= j; ++i) {
-              double mx = 0.0;
-              for (int a = 0; a < m0; ++a)
-                for (int b = 0; b < m0; ++b)
-                  mx = std::max(mx, std::fabs(gh[(size_t)i * m0 * m0 + a * m0 + b]) / std::sqrt(wh[b * m0 + b]));
-              fprintf(stderr, " %.0e", mx);
-            }
-            fprintf(stderr, "\n");
-          }
           project(0, j + 1);
           launch_gram<T>(st, gw, gpart.p, gpart.bytes);
           ++reorth_steps;
-        } else {
-          // W^T W - C^T C: the pass removed little, so this loses nothing to cancellation
-          launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwb.as<double>());
         }
+        cholqr_adaptive_real<T>(t1, t2, Vb + (int64_t)(j + 1) * bs, gwb.as<double>(), certified, j, ldh, nullptr);
       } else {
-        gram(j, lo, nl, 1);
+        const int lo = always ? 0 : std::max(0, j - 1), nl = j + 1 - lo;
+        if (!always && j >= 1) {
+          // first pass: the coefficients against V_{j-1} are those of the recurrence,
+          // V_{j-1}^T M V_j = (M V_{j-1})^T V_j = Hm(j, j-1)^T, so only V_j^T W is formed (the
+          // previous step's Cholesky-QR wrote Hm(j, j-1)^T into Hm and the coefficient buffer)
+          gram(j, j, 1, 0, 1);
+        } else {
+          gram(j, lo, nl, 0);
+        }
         project(lo, nl);
-        launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-      }
-      T* dst = Vb + (int64_t)(j + 1) * bs;
-      if (always) {
-        cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
-        launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
-      } else {
-        cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified, j, ldh,
-                                j + 1 < K ? Hr.as<T>() : nullptr);
+        bool full = always || lo == 0;
+        int certified = -1;
+        if (!full) {
+          const int64_t mm0 = (int64_t)m0 * m0;
+          double* gsk = gred.as<double>() + 2 * mm0;  // beside the local pass's two items
+          // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
+          ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
+                       Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
+          launch_apply<T, T>(st, au);
+          // 16 x 16 tiles: the sketch is read once per tile column, the block once.  Far below
+          // the threshold the estimate is left out for a few steps: the loss grows by well under
+          // a factor 2 per step (measured: at most about 1.5)
+          const bool check = skip_checks == 0;
+          if (check) {
+            GramArgs gs{n, kSketch, m0, 1, 1, U, kSketch, 0, 0, t1, m0, 0, 0, nullptr, gsk, KC_GRAM, 1};
+            launch_gram<T>(st, gs, gpart.p, gpart.bytes);
+          } else {
+            --skip_checks;
+          }
+          launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+          if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwb.as<double>(), d_loss);
+          // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass
+          // changes the block by rounding only, or (a full pass) by at most reorth_eta per
+          // column, which the margin on the Gershgorin bound covers
+          launch_gersh_flags(st, m0, gwb.as<double>(), single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh,
+                             d_cnt);
+          // the estimate and the flags in one copy
+          double* hchk = reinterpret_cast<double*>(h_flags + 128);
+          IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+          IF_HIP(hipEventRecord(ev_chk, st));
+          // the local second pass is needed in either case: it runs while the host waits
+          gram(j, lo, nl, 1);
+          project(lo, nl);
+          IF_HIP(hipEventSynchronize(ev_chk));
+          // a third pass cleans the new block, but the block before it still carries the loss
+          // into the next step's product: that step takes a third pass too, after which both
+          // parents of the recurrence are clean (Simon's partial reorthogonalisation does the same)
+          full = force_next || (check && !(hchk[0] <= thr));
+          force_next = full && !force_next;
+          if (check) {
+            max_loss = std::max(max_loss, hchk[0]);
+            // steps that cannot reach the threshold even if the loss doubled every step
+            double e = hchk[0] * 2.0;
+            while (skip_checks < 8 && e * 2.0 < thr) {
+              e *= 2.0;
+              ++skip_checks;
+            }
+          }
+          if (full) skip_checks = 0;
+          certified = h_flags[130] != 0 ? 1 : 0;
+          if (full) {
+            // a third pass against every block (the local blocks again: their coefficients are
+            // rounding-sized), and the block's Gram afresh
+            gram(j, 0, j + 1, 1);
+            if (debug_reorth) {
+              std::vector<double> gh((size_t)(j + 1) * m0 * m0), wh((size_t)m0 * m0);
+              IF_HIP(hipMemcpyAsync(gh.data(), gred.p, gh.size() * 8, hipMemcpyDeviceToHost, st));
+              IF_HIP(hipMemcpyAsync(wh.data(), gwb.p, wh.size() * 8, hipMemcpyDeviceToHost, st));
+              IF_HIP(hipStreamSynchronize(st));
+              fprintf(stderr, "[reorth] j=%d est=%.1e per-block max|c|/|w|:", j, hchk[0]);
+              for (int i = 0; i <= j; ++i) {
+                double mx = 0.0;
+                for (int a = 0; a < m0; ++a)
+                  for (int b = 0; b < m0; ++b)
+                    mx = std::max(mx, std::fabs(gh[(size_t)i * m0 * m0 + a * m0 + b]) / std::sqrt(wh[b * m0 + b]));
+                fprintf(stderr, " %.0e", mx);
+              }
+              fprintf(stderr, "\n");
+            }
+            project(0, j + 1);
+            launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+            ++reorth_steps;
+          } else {
+            // W^T W - C^T C: the pass removed little, so this loses nothing to cancellation
+            launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwb.as<double>());
+          }
+        } else {
+          gram(j, lo, nl, 1);
+          project(lo, nl);
+          launch_gram<T>(st, gw, gpart.p, gpart.bytes);
+        }
+        T* dst = Vb + (int64_t)(j + 1) * bs;
+        if (always) {
+          cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
+          launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
+        } else {
+          cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified, j, ldh,
+                                  j + 1 < K ? Hr.as<T>() : nullptr);
+        }
       }
       // the shifts' least squares updates of step j run on the side stream, beside step
       // j + 1's basis work; their stop flags are read one step later

@@ -705,12 +705,11 @@ __global__ __launch_bounds__(256) void k_lsq_init(LsqArgs a, const c2* __restric
 
 // Step j, part 1: the reflectors of steps i0..j-1 on the new block column j of Hbar
 // (i0 = 0, or j - band - 1 for a banded Hbar).  Reflector block i acts on rows
-// [i m0, (i+2) m0), so only rows [i0 m0, (j+1) m0) change.  grid (ns, ceil(m0/4)); wave w
-// of block y owns column 4y + w, whose changing rows are staged in LDS (updated in place
-// in global memory when they do not fit).
-template <bool GLOBAL>
+// [i m0, (i+2) m0) only, and once it has acted rows [i m0, (i+1) m0) are final, so each wave
+// (one column, 4y + w of grid row y) slides a 2 m0-row window through LDS: load the next m0
+// rows, apply block i, write back the first m0.  grid (ns, ceil(m0/4)).
 __global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
-  extern __shared__ c2 colbuf[];  // 4 x (j + 1 - i0) m0
+  __shared__ c2 winbuf[4 * 256];  // 4 waves x 2 m0 (m0 <= 128)
   const int s = blockIdx.x;
   if (a.active[s] == 0 || j == 0) return;
   const LsqView v = lsq_view(a, s);
@@ -719,17 +718,20 @@ __global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
   const int col = blockIdx.y * 4 + wave;
   if (col >= m0) return;
   const int i0 = a.band > 0 ? max(0, j - a.band - 1) : 0;
-  const int r0 = i0 * m0, rows = (j + 1) * m0 - r0;
-  c2* h = v.H + (int64_t)(j * m0 + col) * ldh + r0;
-  c2* x = GLOBAL ? h : colbuf + wave * rows;  // x[r] is row r0 + r
-  if (!GLOBAL) {
-    for (int r = lane; r < rows; r += 64) x[r] = h[r];
+  c2* h = v.H + (int64_t)(j * m0 + col) * ldh;  // h[r] is row r of the column
+  c2* win = winbuf + wave * m2;                 // rows [i m0, (i+2) m0) of the column
+  for (int r = lane; r < m0; r += 64) win[r] = h[i0 * m0 + r];
+  for (int i = i0; i < j; ++i) {
+    for (int r = lane; r < m0; r += 64) win[m0 + r] = h[(i + 1) * m0 + r];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, win, lane, false);
+    for (int r = lane; r < m0; r += 64) {
+      h[i * m0 + r] = win[r];
+      win[r] = win[m0 + r];
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-  for (int i = i0; i < j; ++i)
-    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, x + (i - i0) * m0, lane, false);
-  if (!GLOBAL)
-    for (int r = lane; r < rows; r += 64) h[r] = x[r];
+  for (int r = lane; r < m0; r += 64) h[j * m0 + r] = win[r];
 }
 
 // Step j, part 2: Householder QR of the slab rows [j m0, (j+2) m0) of block column j
@@ -1610,16 +1612,8 @@ void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
   }
   if (j > 0) {
-    const int i0 = a.band > 0 ? std::max(0, j - a.band - 1) : 0;
-    const size_t lds = (size_t)4 * (j + 1 - i0) * a.m0 * sizeof(c2);
-    if ((int64_t)lds + 1024 <= (int64_t)max_lds) {
-      if (lds > 64 * 1024)
-        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_prev<false>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL(k_lsq_prev<false>, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), lds, st, a, j);
-    } else {
-      hipLaunchKernelGGL(k_lsq_prev<true>, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a, j);
-    }
+    IF_REQUIRE(a.m0 <= 128, "least squares: m0 > 128");
+    hipLaunchKernelGGL(k_lsq_prev, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a, j);
     IF_HIP(hipGetLastError());
   }
   // packed slab in LDS when it fits the workgroup's LDS

@@ -242,7 +242,30 @@ __device__ inline void group_gather(int e0, int e1, int g0, int li, const int* _
   }
 }
 
-template <class T, bool HAS_B, int KC>
+// The same gather with every lane of the group loading the round's CSR entries itself (the
+// group's lanes read one address, which the memory pipeline serves once) instead of shuffles.
+template <class T, int KC>
+__device__ inline void group_gather_direct(int e0, int e1, const int* __restrict__ ci, const T* __restrict__ va,
+                                           const typename Vec16<T>::type* __restrict__ Vv, int nvec, int vc,
+                                           typename Vec16<T>::type& acc) {
+  for (int e = e0; e < e1; e += KC) {
+    int c[KC];
+    T a[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const bool have = e + k < e1;
+      c[k] = ci[have ? e + k : e1 - 1];
+      a[k] = have ? va[e + k] : T(0);
+    }
+    typename Vec16<T>::type x[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) x[k] = Vv[(int64_t)c[k] * nvec + vc];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) axpy(a[k], x[k], acc);
+  }
+}
+
+template <class T, bool HAS_B, int KC, bool DIRECT>
 __global__ __launch_bounds__(256) void k_spmm_rows(int n, int rows_xcd, int rbx, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const T* __restrict__ va,
                                                    const int* __restrict__ brp, const int* __restrict__ bci,
@@ -265,11 +288,19 @@ __global__ __launch_bounds__(256) void k_spmm_rows(int n, int rows_xcd, int rbx,
   const int s = (li * C) / m0;
   const V16* __restrict__ Vv = reinterpret_cast<const V16*>(V);
   V16 acc = vzero<V16>(), self = vzero<V16>();
-  group_gather<T, HAS_B, KC>(rp[row], rp[row + 1], g0, li, ci, va, Vv, nvec, li, acc);
-  if (HAS_B)
-    group_gather<T, HAS_B, KC>(brp[row], brp[row + 1], g0, li, bci, bva, Vv, nvec, li, self);
+  if (DIRECT)
+    group_gather_direct<T, KC>(rp[row], rp[row + 1], ci, va, Vv, nvec, li, acc);
   else
-    self = Vv[(int64_t)row * nvec + li];
+    group_gather<T, HAS_B, KC>(rp[row], rp[row + 1], g0, li, ci, va, Vv, nvec, li, acc);
+  const bool shifted = zs[2 * s] != T(0) || zs[2 * s + 1] != T(0);
+  if (HAS_B) {
+    if (DIRECT)
+      group_gather_direct<T, KC>(brp[row], brp[row + 1], bci, bva, Vv, nvec, li, self);
+    else
+      group_gather<T, HAS_B, KC>(brp[row], brp[row + 1], g0, li, bci, bva, Vv, nvec, li, self);
+  } else if (shifted) {
+    self = Vv[(int64_t)row * nvec + li];  // a zero shift (W = -A V) needs no self term
+  }
   if (active == nullptr || active[s] != 0)
     nt_store(zs_minus(zs[2 * s], zs[2 * s + 1], self, acc), reinterpret_cast<V16*>(W) + (int64_t)row * nvec + li);
 }
@@ -302,7 +333,8 @@ struct Sched {
 };
 constexpr Sched kSched[] = {{false, 1, 8, "row-U1-K8"}, {false, 2, 4, "row-U2-K4"}, {false, 3, 4, "row-U3-K4"},
                             {true, 8, 8, "slab8-K8"},   {true, 16, 8, "slab16-K8"}, {true, 32, 8, "slab32-K8"},
-                            {true, 16, 16, "slab16-K16"}, {true, 8, 4, "slab8-K4"},  {true, 0, 8, "rows-K8"}};
+                            {true, 16, 16, "slab16-K16"}, {true, 8, 4, "slab8-K4"},  {true, 0, 8, "rows-K8"},
+                            {true, 0, 7, "rows-K7"},    {true, 0, 7, "rows-K7-direct"}, {true, 0, 4, "rows-K4-direct"}};
 constexpr int kNSched = sizeof(kSched) / sizeof(kSched[0]);
 
 struct SpmmOperands {
@@ -341,7 +373,7 @@ void launch_slab(hipStream_t st, const SpmmOperands& o) {
                      (const T*)o.zs, o.active, (const T*)o.V, (T*)o.W);
 }
 
-template <class T, bool HAS_B, int KC>
+template <class T, bool HAS_B, int KC, bool DIRECT>
 void launch_rows(hipStream_t st, const SpmmOperands& o) {
   constexpr int C = Vec16<T>::C;
   const int nvec = o.ns * o.m0 / C;
@@ -349,13 +381,13 @@ void launch_rows(hipStream_t st, const SpmmOperands& o) {
   const int rpb = 4 * (64 / nvec);  // rows per workgroup
   const int rows_xcd = (o.n + kXcds - 1) / kXcds;
   const int rbx = (rows_xcd + rpb - 1) / rpb;
-  hipLaunchKernelGGL((k_spmm_rows<T, HAS_B, KC>), dim3((unsigned)((int64_t)kXcds * rbx)), dim3(256), 0, st, o.n,
+  hipLaunchKernelGGL((k_spmm_rows<T, HAS_B, KC, DIRECT>), dim3((unsigned)((int64_t)kXcds * rbx)), dim3(256), 0, st, o.n,
                      rows_xcd, rbx, o.rp, o.ci, (const T*)o.va, o.brp, o.bci, (const T*)o.bva, o.ns, o.m0,
                      (const T*)o.zs, o.active, (const T*)o.V, (T*)o.W);
 }
 
 // whether schedule idx can run a block of nvec 16-byte vectors per row
-bool sched_fits(int idx, int nvec) { return idx != 8 || (nvec >= 8 && nvec <= 64); }
+bool sched_fits(int idx, int nvec) { return idx < 8 || (nvec >= 8 && nvec <= 64); }
 
 template <class T, bool HAS_B>
 void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
@@ -368,7 +400,10 @@ void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
     case 5: launch_slab<T, HAS_B, 32, 8>(st, o); break;
     case 6: launch_slab<T, HAS_B, 16, 16>(st, o); break;
     case 7: launch_slab<T, HAS_B, 8, 4>(st, o); break;
-    case 8: launch_rows<T, HAS_B, 8>(st, o); break;
+    case 8: launch_rows<T, HAS_B, 8, false>(st, o); break;
+    case 9: launch_rows<T, HAS_B, 7, false>(st, o); break;
+    case 10: launch_rows<T, HAS_B, 7, true>(st, o); break;
+    case 11: launch_rows<T, HAS_B, 4, true>(st, o); break;
     default: throw Error{IFEAST_ERR_INVALID_ARG, "unknown SpMM schedule"};
   }
 }

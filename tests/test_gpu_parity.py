@@ -75,11 +75,13 @@ def test_spmm_shifted_parity(ctx, torch_cuda, prec, case):
         assert np.abs(got[:, sl] - want).max() <= tol * scale * 10, (s, np.abs(got[:, sl] - want).max() / scale)
 
 
-@pytest.mark.parametrize("sched", range(9))
+@pytest.mark.parametrize("sched", range(12))
 def test_spmm_every_schedule(torch_cuda, sched, monkeypatch):
     """Each autotuner candidate (forced through IFEAST_SPMM_SCHED on a fresh matrix) against the oracle,
     on widths that leave partial passes: 3 x 18 complex columns (FP32: 27 vectors, FP64: 54) and B present.
-    Schedule 8 (whole rows per lane group) only takes rows of at most 64 vectors."""
+    Schedules 8 and up (whole rows per lane group) only take rows of 8 to 64 vectors.  The last
+    case has one shift at zero (W = -A V, the shared basis's product), where the row's own term is
+    not read."""
     import paper_1706_00692_amd as pk
 
     torch = torch_cuda
@@ -87,12 +89,16 @@ def test_spmm_every_schedule(torch_cuda, sched, monkeypatch):
     c = pk.Context(0)
     try:
         for prec, dt, tol in [(pk.PREC_MIXED, torch.complex64, 2e-5), (pk.PREC_FP64, torch.complex128, 1e-13)]:
-            for A, B, m0, ns in [(W.spd27(7, 31), W.mass27(7, 32), 18, 3), (W.laplacian_2d(19), None, 80, 5),
-                                 (W.laplacian_3d(9, W.random_potential(729, 4)), None, 40, 1)]:
+            for A, B, m0, ns, zero in [(W.spd27(7, 31), W.mass27(7, 32), 18, 3, False),
+                                       (W.laplacian_2d(19), None, 80, 5, False),
+                                       (W.laplacian_3d(9, W.random_potential(729, 4)), None, 40, 1, False),
+                                       (W.laplacian_3d(9, W.random_potential(729, 5)), None, 40, 1, True)]:
                 nvec = ns * m0 // (2 if prec == pk.PREC_MIXED else 1)
-                if sched == 8 and nvec > 64:
+                if sched >= 8 and not 8 <= nvec <= 64:
                     continue
                 z = np.array([0.3 + 0.2j, 1.1 + 0.05j, -0.4 + 1.5j, 0.7 + 0.01j, 2 + 3j])[:ns]
+                if zero:
+                    z = np.zeros(ns, dtype=complex)
                 V = _rand_block(A.n, ns * m0, 17)
                 Vd = _cplx(torch, V, dt)
                 Wd = torch.zeros_like(Vd)

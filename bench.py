@@ -263,6 +263,62 @@ def extra_solve(pk, torch, name):
     return out
 
 
+def matvec_experiment(pk, N=24, want=50, m0s=(64, 80, 96, 128), ncs=(4, 10, 24), alpha=0.2):
+    """Matrix-vector product counts of IFEAST against m0 and against the number of nodes, on a
+    stand-in for the paper's real-space Hamiltonians (3-D Laplacian + potential), with ARPACK
+    (scipy eigsh, Lanczos with implicit restarts) for the same eigenpairs as the Krylov comparison.
+
+    IFEAST: the lowest ``want`` eigenpairs to residual 1e-10, the upper half of a trapezoidal rule
+    on the circle through the interval ends, inner tolerance factor alpha.  Counted: outer
+    iterations; matvecs of the shared basis (Arnoldi steps x m0: what the GPU multiplies); the
+    per-shift total (sum over shifts of their own block iterations x m0: what the method costs
+    when every shifted system has its own Krylov space, the paper's 'total'); and the sequential
+    count (sum over outer iterations of the longest shift's block iterations, one product per
+    step with the block's columns in parallel, the paper's 'sequential')."""
+    import scipy.sparse.linalg as spla
+    import workloads as W
+
+    A = W.config2(N, 0.0, 1.0).A
+    As = A.to_scipy()
+    ncount = [0]
+
+    def mv(x):
+        ncount[0] += 1 if x.ndim == 1 else x.shape[1]
+        return As @ x
+
+    op = spla.LinearOperator(As.shape, matvec=mv, matmat=mv, dtype=np.float64)
+    ref = np.sort(spla.eigsh(As, k=want + 8, which="SA", tol=1e-12)[0])
+    emin, emax = ref[0] - 0.5 * (ref[1] - ref[0]), 0.5 * (ref[want - 1] + ref[want])
+    rows = []
+    ctx = pk.Context(0)
+    Am = ctx.matrix(A)
+    for m0, nc in [(m, 4) for m in m0s] + [(80, c) for c in ncs if c != 4]:
+        prob = W.config2_small(N, m0, emin, emax)
+        prob.contour = {"kind": "half", "emin": emin, "emax": emax, "rule": "trap", "nc": nc}
+        prob.alpha, prob.tol, prob.max_outer = alpha, 1e-10, 40
+        r = ctx.solve_resident(Am, None, prob.contour, pk.problem_params(prob, pk.PREC_FP64), prob.x0())
+        ok = bool(r.converged and r.m == want and np.allclose(np.sort(r.lam_in), ref[:want], rtol=1e-9))
+        rows.append({"m0": m0, "nc": nc, "converged": ok, "outer_iters": r.outer_iters,
+                     "shared_basis_matvec": int(r.total_matvec),
+                     "per_shift_total_matvec": int(r.inner_hist.sum()) * m0,
+                     "sequential_matvec": int(r.seq_matvec),
+                     "sequential_per_outer": r.seq_matvec / max(1, r.outer_iters),
+                     "seconds": r.solve_seconds})
+        log(f"matvec table: {rows[-1]}")
+    Am.close()
+    ctx.close()
+    arpack = []
+    for m0 in m0s:
+        ncount[0] = 0
+        vals = np.sort(spla.eigsh(op, k=want, which="SA", ncv=m0, tol=1e-10, maxiter=20000)[0])
+        arpack.append({"ncv": m0, "matvec": ncount[0], "max_rel_err": float(np.max(np.abs(vals - ref[:want]) /
+                                                                                   np.abs(ref[:want])))})
+        log(f"arpack: {arpack[-1]}")
+    return {"matrix": f"lap3d_pot_{N}^3 (n={A.n})", "eigenpairs": want, "interval": [emin, emax],
+            "alpha": alpha, "tol": 1e-10, "rule": "trapezoid, upper half of the circle", "ifeast": rows,
+            "arpack": arpack}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +336,8 @@ def main():
     ap.add_argument("--max-outer", type=int, default=0, help="cap outer iterations (profiling runs only)")
     ap.add_argument("--reorth-eta", type=float, default=0.0,
                     help="orthogonality threshold of the shared basis (0: the library's default)")
+    ap.add_argument("--experiment", default="", choices=["", "matvec"],
+                    help="matvec: print the matrix-vector product counts against m0 and nc instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); see the design notes for how the "
@@ -290,6 +348,9 @@ def main():
     import paper_1706_00692_amd as pk
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.experiment == "matvec":
+        print(json.dumps({"experiment": "matvec counts", **matvec_experiment(pk)}), flush=True)
+        return
     prob, wname, want = workload(args.workload)
     general = prob.kind == "general"
     if args.max_outer:

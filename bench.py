@@ -319,6 +319,83 @@ def matvec_experiment(pk, N=24, want=50, m0s=(64, 80, 96, 128), ncs=(4, 10, 24),
             "arpack": arpack}
 
 
+def serve_request(W, req, spectra):
+    """A request of the serving stream: the 3-D Laplacian + potential (the 64^3 problem's
+    generator and seed) on a grid of the drawn side, the interval from below the spectrum to the
+    widest gap within two places of the (m0/2)-th eigenvalue.  spectra caches the low spectrum of
+    each side (scipy's Lanczos on the host, input preparation outside the stream)."""
+    import scipy.sparse.linalg as spla
+
+    N, m0 = req["side"], req["m0"]
+    A = W.config2(N, 0.0, 1.0).A
+    if N not in spectra:
+        spectra[N] = np.sort(spla.eigsh(A.to_scipy(), k=36, which="SA", tol=1e-6)[0])
+    ev = spectra[N]
+    k = m0 // 2
+    i = k - 2 + int(np.argmax(np.diff(ev)[k - 3:k + 2]))  # gap between ev[i] and ev[i + 1]
+    prob = W.Problem(name=f"serve_{N}_{m0}", A=A, B=None,
+                     contour={"kind": "half", "emin": 0.5, "emax": float(0.5 * (ev[i] + ev[i + 1])),
+                              "rule": "gl", "nc": 8},
+                     m0=m0, max_inner=8, alpha=1e-2, tol=1e-9, max_outer=40, x0_seed=req["x0_seed"])
+    return prob
+
+
+def serve_experiment(pk, count=24, sides=(32, 48, 64), m0s=(16, 32, 64), rate=20.0, alone=3):
+    """Serving: a seeded Poisson stream of eigen-solve requests submitted at their arrival times to
+    one context (continuous batching: requests are admitted by device footprint and run on a pool
+    of workers with their own streams and workspaces), once in each precision.  Reports completed
+    requests, throughput, p50/p99 latency (completion minus submission) and, for a sample, the
+    difference between the result in the stream and the result alone."""
+    import workloads as W
+
+    reqs = W.serving_requests(count, seed=3000, rate=rate, sides=sides, m0s=m0s)
+    spectra = {}
+    probs = [serve_request(W, r, spectra) for r in reqs]
+    out = {"requests": count, "rate_per_s": rate, "sides": list(sides), "m0s": list(m0s),
+           "mix": [f"{r['side']}^3/m0={r['m0']}" for r in reqs]}
+    for prec_name, prec in (("mixed", pk.PREC_MIXED), ("fp64", pk.PREC_FP64)):
+        ctx = pk.Context(0)
+        params = [pk.problem_params(p, prec) for p in probs]
+        # one warm request per shape outside the stream (SpMM autotune, code paths)
+        for p, pr in {(p.n, p.m0): (p, pr) for p, pr in zip(probs, params)}.values():
+            ctx.wait(ctx.submit(p.A, None, p.contour, pr, p.x0()), p.n, p.m0, p.max_outer, p.contour["nc"])
+        t0 = time.perf_counter()
+        tickets = []
+        for req, p, pr in zip(reqs, probs, params):
+            delay = req["arrival"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(ctx.submit(p.A, None, p.contour, pr, p.x0()))
+        results = []
+        for t, p in zip(tickets, probs):
+            try:
+                results.append(ctx.wait(t, p.n, p.m0, p.max_outer, p.contour["nc"]))
+            except pk.IFeastError as e:
+                results.append(e.status)
+        span = time.perf_counter() - t0
+        good = [r for r, p in zip(results, probs) if not isinstance(r, int) and r.converged and r.m > 0
+                and r.resid[: r.m].max() <= p.tol]
+        lat = [r.latency for r in good]
+        rec = {"completed": len(good), "failed_or_unconverged": count - len(good), "span_s": span,
+               "requests_per_s": len(good) / span, "eigenpairs_per_s": sum(r.m for r in good) / span,
+               "latency_p50_s": float(np.percentile(lat, 50)) if lat else None,
+               "latency_p99_s": float(np.percentile(lat, 99)) if lat else None}
+        if prec_name == "mixed":
+            diffs = []
+            for i in range(min(alone, count)):
+                r = results[i]
+                if isinstance(r, int):
+                    continue
+                a = ctx.solve_problem(probs[i], precision=prec)
+                if a.m == r.m and a.m > 0:
+                    diffs.append(float(np.max(np.abs(np.sort(a.lam_in) - np.sort(r.lam_in)) / np.abs(a.lam_in))))
+            rec["alone_vs_stream_max_rel_eig_diff"] = max(diffs) if diffs else None
+        ctx.close()
+        out[prec_name] = rec
+        log(f"serve {prec_name}: {rec}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,12 +409,14 @@ def main():
                     help="also time one complete oracle inner solve at full size (minutes of host time)")
     ap.add_argument("--extras", default="c4",
                     help="comma-separated extra configurations solved once each ('' for none)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--basis", default="auto", choices=["auto", "shared", "per_shift"])
     ap.add_argument("--max-outer", type=int, default=0, help="cap outer iterations (profiling runs only)")
     ap.add_argument("--reorth-eta", type=float, default=0.0,
                     help="orthogonality threshold of the shared basis (0: the library's default)")
-    ap.add_argument("--experiment", default="", choices=["", "matvec"],
-                    help="matvec: print the matrix-vector product counts against m0 and nc instead")
+    ap.add_argument("--experiment", default="", choices=["", "matvec", "serve"],
+                    help="matvec: matrix-vector product counts against m0 and nc; serve: a seeded "
+                         "Poisson stream of requests (throughput, p50/p99 latency); printed instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); see the design notes for how the "
@@ -350,6 +429,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.experiment == "matvec":
         print(json.dumps({"experiment": "matvec counts", **matvec_experiment(pk)}), flush=True)
+        return
+    if args.experiment == "serve":
+        print(json.dumps({"experiment": "serving stream", **serve_experiment(pk)}), flush=True)
         return
     prob, wname, want = workload(args.workload)
     general = prob.kind == "general"
@@ -419,8 +501,8 @@ def main():
                       "tol": prob.tol, "eigenpairs": res[0].m, "outer_iters": res[0].outer_iters,
                       "seq_matvec": res[0].seq_matvec, "total_matvec": res[0].total_matvec,
                       "max_outer_cap": args.max_outer or None},
-           "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                         "note": "back-to-back solves of one request; the served stream is bench_serve.py"},
+           "solve_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                               "note": "back-to-back solves of the benchmark problem"},
            "converged": ok}
     if want is not None and res[0].m == len(want):
         out["max_rel_eig_err_vs_closed_form"] = float(np.max(np.abs(np.sort(res[0].lam_in.real) - want) /
@@ -490,6 +572,13 @@ def main():
     ctx.close()
     for name in [e for e in args.extras.split(",") if e and e != args.workload]:
         out[f"extra_{name}"] = extra_solve(pk, torch, name)
+    if not args.no_serve:
+        sv = serve_experiment(pk)
+        out["serving"] = sv
+        out["latency_s"] = {"p50": sv["mixed"]["latency_p50_s"], "p99": sv["mixed"]["latency_p99_s"],
+                            "fp64_p50": sv["fp64"]["latency_p50_s"], "fp64_p99": sv["fp64"]["latency_p99_s"],
+                            "note": "completion minus submission over a seeded Poisson stream (20 requests/s) "
+                                    "of 3-D Laplacian + potential solves, sides 32-64, m0 16-64"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, res[0], full_shift=args.cpu_full_shift)
         log(f"cpu baseline: {out['cpu_baseline']}")

@@ -239,14 +239,21 @@ def cpu_baseline(prob, gpu_res, steps=8, full_shift=False):
 
 def extra_solve(pk, torch, name):
     """One mixed-precision solve of another configuration, timed on its own context (an extra
-    key of the JSON line, never `value`)."""
-    prob, wname, want = workload(name)
+    key of the JSON line, never `value`).  A name ending in "_minres" solves that configuration
+    with MINRES inner solves (one solve to warm the workspace, then the timed one)."""
+    minres = name.endswith("_minres")
+    prob, wname, want = workload(name[: -len("_minres")] if minres else name)
+    if minres:
+        wname += "_minres_inner"
     ctx = pk.Context(0)
     try:
         A = ctx.matrix(prob.A)
         B = None if prob.B is None else ctx.matrix(prob.B)
+        params = pk.problem_params(prob, pk.PREC_MIXED, **({"basis": pk.BASIS_MINRES} if minres else {}))
+        if minres:
+            ctx.solve_resident(A, B, prob.contour, params, prob.x0())
         t = time.perf_counter()
-        r = ctx.solve_resident(A, B, prob.contour, pk.problem_params(prob, pk.PREC_MIXED), prob.x0())
+        r = ctx.solve_resident(A, B, prob.contour, params, prob.x0())
         wall = time.perf_counter() - t
     finally:
         ctx.close()
@@ -407,10 +414,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-full-shift", action="store_true",
                     help="also time one complete oracle inner solve at full size (minutes of host time)")
-    ap.add_argument("--extras", default="c4",
+    ap.add_argument("--extras", default="c4,c2_minres",
                     help="comma-separated extra configurations solved once each ('' for none)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
-    ap.add_argument("--basis", default="auto", choices=["auto", "shared", "per_shift"])
+    ap.add_argument("--basis", default="auto", choices=["auto", "shared", "per_shift", "minres"])
     ap.add_argument("--max-outer", type=int, default=0, help="cap outer iterations (profiling runs only)")
     ap.add_argument("--reorth-eta", type=float, default=0.0,
                     help="orthogonality threshold of the shared basis (0: the library's default)")
@@ -437,7 +444,8 @@ def main():
     general = prob.kind == "general"
     if args.max_outer:
         prob.max_outer = args.max_outer
-    basis = {"auto": pk.BASIS_AUTO, "shared": pk.BASIS_SHARED, "per_shift": pk.BASIS_PER_SHIFT}[args.basis]
+    basis = {"auto": pk.BASIS_AUTO, "shared": pk.BASIS_SHARED, "per_shift": pk.BASIS_PER_SHIFT,
+             "minres": pk.BASIS_MINRES}[args.basis]
     shared = args.basis != "per_shift" and prob.B is None
     log(f"workload {wname}: n={prob.A.n} nnz={prob.A.nnz} m0={prob.m0} nc={prob.contour['nc']} "
         f"k={prob.max_inner} contour={prob.contour} basis={args.basis}")

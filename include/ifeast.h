@@ -101,7 +101,11 @@ enum { IFEAST_BASIS_AUTO = 0,      /* shared for B = I, per shift otherwise */
                                       block Krylov spaces from R (z_s - Lambda)^{-1} coincide, so up to
                                       max_inner * max_cycles block steps run without restarts and only the
                                       small least-squares problems are per shift */
-       IFEAST_BASIS_PER_SHIFT = 2 };/* per shift complex block GMRES(max_inner), restarted up to max_cycles */
+       IFEAST_BASIS_PER_SHIFT = 2, /* per shift complex block GMRES(max_inner), restarted up to max_cycles */
+       IFEAST_BASIS_MINRES = 3 };  /* B = I, symmetric A: MINRES per column (the paper's inner solver, Sec. 2), one
+                                      Lanczos recurrence per column of R serving every shift, directions by
+                                      three-term recurrences added straight into Q, no Krylov basis stored; at
+                                      most max_inner * max_cycles steps */
 enum { IFEAST_INNER_GLOBAL = 0,/* stop when every column residual <= alpha ||R_F|| (Algorithm 2, step 1) */
        IFEAST_INNER_COLUMN = 1 };/* column j stops when its residual fell by alpha (Eq. alpha with alpha_j = alpha) */
 

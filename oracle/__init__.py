@@ -32,6 +32,7 @@ from .feast import (
     inside_contour,
     dense_reference,
     quad_accumulate,
+    minres_columns,
 )
 
 __all__ = [
@@ -50,5 +51,6 @@ __all__ = [
     "inside_contour",
     "dense_reference",
     "quad_accumulate",
+    "minres_columns",
     "lowest_eigenvalues_lap3d",
 ]

@@ -171,10 +171,31 @@ def classify(lam, r, eta, contour, z, w, half, tau):
     return ins, geo & ~ok, float(rf)
 
 
+def minres_columns(M, rhs, steps: int, tol):
+    """MINRES iterates of M y = rhs, column by column (Sec. 2: the paper's inner solver).
+
+    MINRES's iterate after k steps is the vector of the Krylov space K_k(M, b) that minimises
+    ||b - M y||, which is what one GMRES cycle with block size 1 computes; each column stops on
+    its own when its residual is <= tol (scalar or per column), after at most ``steps`` steps.
+    Returns (D, steps per column).
+    """
+    rhs = np.asarray(rhs, dtype=complex)
+    tol = np.broadcast_to(np.asarray(tol, dtype=float), (rhs.shape[1],))
+    cols, its = [], []
+    for c in range(rhs.shape[1]):
+        d, info = block_gmres(M, rhs[:, [c]], steps, tol[c])
+        cols.append(d)
+        its.append(info["iters"])
+    return np.hstack(cols), its
+
+
 def ifeast(A, B, contour: dict, m0: int, max_inner: int, alpha: float, tol: float, X0: np.ndarray,
            max_outer: int = 50, mode: str = "ritz", kind: str = "symmetric", max_cycles: int = 1,
-           inner_rule: str = "global", tau: float = 0.5, callback=None) -> IFeastResult:
+           inner_rule: str = "global", tau: float = 0.5, callback=None, inner: str = "gmres") -> IFeastResult:
     """IFEAST with block-GMRES(k) inner solves (Algorithm 2), k = max_inner.
+
+    ``inner="minres"``: each column of each shifted system is solved by MINRES (minres_columns)
+    for at most max_inner * max_cycles steps instead.
 
     ``mode``: "ritz" (Y0 = X (z - Lambda)^{-1}) or "literal" (Y0 = 0).
     ``inner_rule``: "global" stops a shift when every column residual is
@@ -213,6 +234,11 @@ def ifeast(A, B, contour: dict, m0: int, max_inner: int, alpha: float, tol: floa
             M = shifted_operator(A, B, zk)
             rhs = R / (zk - lam)[None, :] if mode == "ritz" else BX
             tol_in = alpha * rf if inner_rule == "global" else alpha * np.linalg.norm(rhs, axis=0)
+            if inner == "minres":
+                Dk, its = minres_columns(M, rhs, max_inner * max_cycles, tol_in)
+                D.append(Dk)
+                iters.append(max(its))
+                continue
             Dk, info = block_gmres_restarted(M, rhs, max_inner, tol_in, max_cycles)
             D.append(Dk)
             iters.append(info["iters"])

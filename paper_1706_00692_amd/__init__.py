@@ -24,6 +24,7 @@ from ._binding import (
     BASIS_AUTO,
     BASIS_SHARED,
     BASIS_PER_SHIFT,
+    BASIS_MINRES,
     FLAG_INSIDE,
     FLAG_SPURIOUS,
     STATUS,
@@ -46,6 +47,7 @@ __all__ = [
     "BASIS_AUTO",
     "BASIS_SHARED",
     "BASIS_PER_SHIFT",
+    "BASIS_MINRES",
     "FLAG_INSIDE",
     "FLAG_SPURIOUS",
     "STATUS",

@@ -62,7 +62,7 @@ class KernelStatStruct(C.Structure):
     _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
 
-BASIS_AUTO, BASIS_SHARED, BASIS_PER_SHIFT = 0, 1, 2
+BASIS_AUTO, BASIS_SHARED, BASIS_PER_SHIFT, BASIS_MINRES = 0, 1, 2, 3
 KERNEL_SPMM, KERNEL_GRAM, KERNEL_UPDATE, KERNEL_QACC, KERNEL_OUTER = 0, 1, 2, 3, 4
 KERNEL_NAMES = {KERNEL_SPMM: "spmm", KERNEL_GRAM: "gram", KERNEL_UPDATE: "update", KERNEL_QACC: "qacc",
                 KERNEL_OUTER: "outer"}

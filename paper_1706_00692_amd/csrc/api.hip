@@ -96,16 +96,17 @@ Shape make_shape(int64_t n, bool hasB, const ifeast_contour* C, const ifeast_par
   s.k = p->max_inner;
   s.hasB = hasB;
   s.precision = p->precision;
-  if (p->basis == IFEAST_BASIS_SHARED && hasB)
-    throw Error{IFEAST_ERR_UNSUPPORTED, "a shared Krylov basis needs B = I"};
-  s.shared = !hasB && p->basis != IFEAST_BASIS_PER_SHIFT;
+  if ((p->basis == IFEAST_BASIS_SHARED || p->basis == IFEAST_BASIS_MINRES) && hasB)
+    throw Error{IFEAST_ERR_UNSUPPORTED, "a shared Krylov basis or MINRES inner solves need B = I"};
+  s.minres = p->basis == IFEAST_BASIS_MINRES;
+  s.shared = !hasB && p->basis != IFEAST_BASIS_PER_SHIFT && !s.minres;
   if (p->problem == IFEAST_PROBLEM_GENERAL) {
     if (hasB) throw Error{IFEAST_ERR_UNSUPPORTED, "non-Hermitian problems take B = I"};
     // the upper half of a conjugate-symmetric rule is solved (see validate_params)
     s.general = true;
     s.ns = nsys(C) / 2;
   }
-  s.kb = s.shared ? p->max_inner * p->max_cycles : p->max_inner;
+  s.kb = (s.shared || s.minres) ? p->max_inner * p->max_cycles : p->max_inner;
   return s;
 }
 
@@ -123,7 +124,7 @@ static std::map<ifeast_ctx*, EngineCache> g_cache;
 namespace {
 bool same(const Shape& a, const Shape& b) {
   return a.n == b.n && a.m0 == b.m0 && a.ns == b.ns && a.k == b.k && a.hasB == b.hasB && a.precision == b.precision &&
-         a.shared == b.shared && a.kb == b.kb && a.general == b.general;
+         a.shared == b.shared && a.kb == b.kb && a.general == b.general && a.minres == b.minres;
 }
 Engine& engine_for(ifeast_ctx* ctx, const Shape& s) {
   std::lock_guard<std::mutex> lk(g_cache_mu);

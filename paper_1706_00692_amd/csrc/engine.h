@@ -25,6 +25,7 @@ struct Shape {
   bool shared = false;  // one real Krylov basis for all shifts (B = I)
   int kb = 0;           // basis capacity in blocks: k (per shift) or k * max_cycles (shared)
   bool general = false; // non-Hermitian A (real, B = I): Ritz block in pair format, full Arnoldi
+  bool minres = false;  // batched shifted MINRES (B = I, symmetric): kb = the step cap
 };
 uint64_t workspace_bytes(const Shape& s);
 

@@ -132,8 +132,11 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
   IF_REQUIRE(p.alpha >= 0.0 && p.alpha < 1.0, "alpha must be in [0, 1)");
   IF_REQUIRE(p.tol > 0.0, "tol must be positive");
   IF_REQUIRE(p.reorth_eta >= 0.0, "reorth_eta must be >= 0");
-  IF_REQUIRE(p.basis == IFEAST_BASIS_AUTO || p.basis == IFEAST_BASIS_SHARED || p.basis == IFEAST_BASIS_PER_SHIFT,
+  IF_REQUIRE(p.basis == IFEAST_BASIS_AUTO || p.basis == IFEAST_BASIS_SHARED || p.basis == IFEAST_BASIS_PER_SHIFT ||
+                 p.basis == IFEAST_BASIS_MINRES,
              "unknown basis mode");
+  if (p.basis == IFEAST_BASIS_MINRES && p.problem != IFEAST_PROBLEM_SYMMETRIC)
+    throw Error{IFEAST_ERR_UNSUPPORTED, "MINRES inner solves take symmetric problems"};
   IF_REQUIRE(p.precision == IFEAST_PREC_FP64 || p.precision == IFEAST_PREC_MIXED, "unknown precision");
   IF_REQUIRE(p.inner_rule == IFEAST_INNER_GLOBAL || p.inner_rule == IFEAST_INNER_COLUMN, "unknown inner rule");
   IF_REQUIRE(p.problem == IFEAST_PROBLEM_SYMMETRIC || p.problem == IFEAST_PROBLEM_GENERAL, "unknown problem kind");
@@ -181,6 +184,7 @@ struct Layout {
   size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gw, Hr, Tinv, Racc, chol, Yq, Uc, zs;
   size_t Hm, Ss;  // shared basis: real block Hessenberg, per-shift start blocks
   size_t Us, Om;  // shared basis: sketch of the older blocks (n x kSketch), its random factors
+  size_t mrv, mrd, mrp, mrs;  // MINRES: three n x m0 blocks, two direction sets, partials, state
 };
 
 Layout layout(const Shape& s) {
@@ -207,6 +211,18 @@ Layout layout(const Shape& s) {
   L.Racc = ns * m0 * m0 * 16;
   L.chol = ns * 3 * m0 * m0 * 16;
   L.zs = 4 * 64 * 8;
+  if (s.minres) {
+    // no Krylov basis and no least squares: three Lanczos blocks and two sets of direction vectors
+    L.H = L.Vh = L.tauh = L.g = L.y = L.u = L.Racc = L.chol = 0;
+    L.V = L.T1 = L.gpart = L.gred = L.gw = L.Hr = L.Tinv = L.Yq = L.Uc = L.Hm = L.Ss = L.Us = L.Om = 0;
+    L.gpart = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
+    L.mrv = 3 * n * m0 * ts;
+    L.mrd = 2 * ns * n * m0 * 2 * ts;
+    L.mrp = 2 * minres_partial_bytes(s.n, (int)m0);
+    L.mrs = minres_state_bytes((int)m0, (int)ns);
+    return L;
+  }
+  L.mrv = L.mrd = L.mrp = L.mrs = 0;
   if (s.shared) {
     // one real basis of k + 1 blocks (n x m0), real products of width m0
     L.V = (k + 1) * n * m0 * ts;
@@ -256,7 +272,7 @@ Layout layout(const Shape& s) {
 size_t total(const Layout& L) {
   return 3 * L.X + L.AQ + L.BQ + L.R + 10 * L.vec + 6 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
          L.tauh + L.g + L.u + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq +
-         L.Uc + 3 * L.zs + L.Hm + L.Ss + L.Us + L.Om;
+         L.Uc + 3 * L.zs + L.Hm + L.Ss + L.Us + L.Om + L.mrv + L.mrd + L.mrp + L.mrs;
 }
 
 }  // namespace
@@ -351,6 +367,7 @@ struct Engine::Impl {
   DevBuf X, Q, Xn, AQ, BQ, R, lam, resid, eta, rho, C, GA, GB, rrwork, colpart, clsout;
   DevBuf lamI, rhoI, GX;  // non-Hermitian path: imaginary parts (pair format), Gram of the filtered block
   DevBuf TS, TA;          // non-Hermitian path: SVQB transform of a pass, accumulated transform
+  DevBuf mrV, mrD, mrP, mrS, mrN;  // MINRES: Lanczos blocks, directions, partials, state, start norms
   // inner
   DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gwb, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
   DevBuf Hm, Ss;             // shared basis
@@ -457,6 +474,13 @@ struct Engine::Impl {
     zsD = DevBuf(L.zs);
     wsD = DevBuf(L.zs);
     if (L.Hm) Hm = DevBuf(L.Hm);
+    if (L.mrv) {
+      mrV = DevBuf(L.mrv);
+      mrD = DevBuf(L.mrd);
+      mrP = DevBuf(L.mrp);
+      mrS = DevBuf(L.mrs);
+      mrN = DevBuf(L.vec);
+    }
     if (L.Ss) Ss = DevBuf(L.Ss);
     if (L.Us) Us = DevBuf(L.Us);
     if (L.Om) {
@@ -714,6 +738,69 @@ struct Engine::Impl {
     ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
     launch_apply<T, T>(st, a2);
     launch_copy_if<T>(st, d_two_sh, n * m0, tmp, dst);
+  }
+
+  // Inner solves by batched shifted MINRES (B = I, symmetric A): one Lanczos recurrence per
+  // column of R shared by every shift, minimal-residual iterates by Givens rotations of each
+  // shift's complex tridiagonal, directions by three-term recurrences, Q += Re(wf_s x_s) as they
+  // go.  Each (column, shift) stops by the stopping rule on its minimal residual; at most
+  // k * max_cycles steps.  Returns the steps per shift.
+  template <class T>
+  std::vector<int> inner_minres(const ifeast_matrix* A, const Nodes& nd, const ifeast_params& p, const double* Xd,
+                                const double* lamd, const double* Rd, const double* rhod,
+                                const std::vector<double>& tolh, double* Qd) {
+    const int64_t n = sh.n;
+    const int m0 = sh.m0, ns = sh.ns, K = sh.kb;
+    IF_REQUIRE(m0 % 2 == 0 && m0 <= 128, "MINRES: m0 must be even and at most 128");
+    std::vector<double> zdv(2 * ns), wf(2 * ns);
+    for (int s = 0; s < ns; ++s) {
+      zdv[2 * s] = nd.z[s].real();
+      zdv[2 * s + 1] = nd.z[s].imag();
+      const cd f = nd.half ? 2.0 * nd.w[s] : nd.w[s];
+      wf[2 * s] = f.real();
+      wf[2 * s + 1] = f.imag();
+    }
+    side_stream();  // pinned host flags
+    stage_off = 0;
+    const std::vector<T> zero(4, (T)0);
+    h2d_staged(zsT.p, zero.data(), zero.size() * sizeof(T));
+    h2d_staged(zsD.p, zdv.data(), zdv.size() * sizeof(double));
+    h2d_staged(wsD.p, wf.data(), wf.size() * sizeof(double));
+    h2d_staged(tol.p, tolh.data(), tolh.size() * sizeof(double));
+    const int64_t bs = n * m0;
+    T* vb = mrV.as<T>();
+    MinresRun<T> mr;
+    mr.n = n;
+    mr.m0 = m0;
+    mr.ns = ns;
+    mr.V = vb;
+    mr.Vp = vb + bs;
+    mr.W = vb + 2 * bs;
+    mr.D1 = mrD.as<T>();
+    mr.D2 = mrD.as<T>() + 2 * ns * bs;
+    mr.pa = mrP.as<double>();
+    mr.pb = mrP.as<double>() + minres_partial_bytes(n, m0) / sizeof(double);
+    mr.state = mrS.p;
+    // Q = X rho_hat(Lambda); v_1 = r / ||r|| per column
+    launch_scale_cols(st, n, m0, Xd, rhod, Qd);
+    launch_col_sumsq(st, n, m0, Rd, mrN.as<double>(), colpart.as<double>());
+    mr.start(st, Rd, mrN.as<double>(), lamd, zsD.as<double>());
+    int steps = 0;
+    for (int k = 0; k < K; ++k) {
+      mr.step(st, A, zsT.as<T>(), zsD.as<double>(), wsD.as<double>(), tol.as<double>(), Qd);
+      steps = k + 1;
+      // the pairs still iterating after step k, read one step later (the device runs on)
+      IF_HIP(hipMemcpyAsync(h_flags + (k & 1) * 128, mr.column_active(), m0 * sizeof(int), hipMemcpyDeviceToHost,
+                            st));
+      IF_HIP(hipEventRecord(ev_lsq[k & 1], st));
+      if (k >= 1) {
+        IF_HIP(hipEventSynchronize(ev_lsq[(k - 1) & 1]));
+        const int* hf = h_flags + ((k - 1) & 1) * 128;
+        if (std::all_of(hf, hf + m0, [](int a) { return a == 0; })) break;
+      }
+    }
+    shared_steps = steps;
+    return d2h_ints(mr.shift_steps(), ns);
   }
 
   // Inner solves of all shifts on one real block Arnoldi of M = -A (B = I):
@@ -1258,7 +1345,11 @@ void Engine::filter(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast
   IF_REQUIRE(!shape_.general, "the step-level filter takes symmetric problems");
   const std::vector<double> tolh = inner_tolerances(nd, p, lamh, std::vector<double>(m0, 0.0), residh, rf, m0);
   std::vector<int> it;
-  if (shape_.shared)
+  if (shape_.minres)
+    it = shape_.precision == IFEAST_PREC_MIXED
+             ? I.inner_minres<float>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+             : I.inner_minres<double>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+  else if (shape_.shared)
     it = shape_.precision == IFEAST_PREC_MIXED
              ? I.inner_shared<float>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q)
              : I.inner_shared<double>(A, nd, p, X, lam, R, I.rho.as<double>(), tolh, Q);
@@ -1367,7 +1458,11 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     std::vector<int> iters;
     const double* lamId = gen ? lamI : nullptr;
     const double* rhoId = gen ? I.rhoI.as<double>() : nullptr;
-    if (shape_.shared)
+    if (shape_.minres)
+      iters = shape_.precision == IFEAST_PREC_MIXED
+                  ? I.inner_minres<float>(A, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q)
+                  : I.inner_minres<double>(A, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q);
+    else if (shape_.shared)
       iters = shape_.precision == IFEAST_PREC_MIXED
                   ? I.inner_shared<float>(A, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q, lamId, rhoId)
                   : I.inner_shared<double>(A, nd_in, p, X, lam, R, I.rho.as<double>(), tolh, Q, lamId, rhoId);
@@ -1387,10 +1482,10 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
     int mx = 0;
     for (int s = 0; s < shape_.ns; ++s) {
       stats.inner_hist.push_back(iters[s]);
-      if (!shape_.shared) stats.total_matvec += (int64_t)iters[s] * m0;
+      if (!shape_.shared && !shape_.minres) stats.total_matvec += (int64_t)iters[s] * m0;
       mx = std::max(mx, iters[s]);
     }
-    if (shape_.shared) {
+    if (shape_.shared || shape_.minres) {
       stats.total_matvec += (int64_t)I.shared_steps * m0;
       mx = I.shared_steps;
     }

@@ -335,6 +335,33 @@ struct ClassifyArgs {
 void launch_classify(hipStream_t st, const ClassifyArgs& a, const double* lam, const double* lam_im,
                      const double* resid, const double* eta, int* flags, double* out);
 
+// ---- batched shifted MINRES (minres.hip): one Lanczos recurrence per column of R shared by all
+// shifts, minimal-residual iterates by Givens rotations of each shift's tridiagonal, direction
+// vectors by a three-term recurrence accumulated straight into Q.  Buffers belong to the caller:
+// V, Vp, W: n x m0 (T); D1, D2: ns x n x m0 complex (T, interleaved); pa, pb: partial sums
+// (minres_partial_bytes each); state: minres_state_bytes.
+size_t minres_state_bytes(int m0, int ns);
+size_t minres_partial_bytes(int64_t n, int m0);
+template <class T>
+struct MinresRun {
+  int64_t n;
+  int m0, ns;
+  T *V, *Vp, *W, *D1, *D2;
+  double *pa, *pb;
+  void* state;
+  int k = 0;
+  // v_1 = R / rnorm per column (R: n x m0 FP64, rnorm its column norms), zero directions, and
+  // g_1 = rnorm / (z_s - lambda_c) per (column, shift); z: device 2 ns doubles
+  int start(hipStream_t st, const double* R, const double* rnorm, const double* lam, const double* z);
+  // one Lanczos step for every column and one MINRES update for every active (column, shift):
+  // zeroshift: device complex 0 of type T; z, wf: device 2 ns doubles (nodes, quadrature factors
+  // of Q += Re(wf x)); tol: device ns x m0 stopping thresholds on the minimal residual
+  void step(hipStream_t st, const ifeast_matrix* A, const T* zeroshift, const double* z, const double* wf,
+            const double* tol, double* Q);
+  const int* column_active() const;  // device m0: pairs of each column still iterating
+  const int* shift_steps() const;    // device ns: steps in which each shift iterated
+};
+
 // ---- allocation-free Rayleigh-Ritz (noalloc.hip)
 // Size of the per-device scratch array the allocation-free entry point draws every buffer from.
 constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;

@@ -773,3 +773,55 @@ def test_solve_generalized_random_vs_dense(ctx):
     Xg, Xr = res.X_in, V[:, 2:11]
     sines = np.linalg.norm(Xr - Xg @ (Xg.T @ (B @ Xr)), axis=0)
     assert sines.max() <= 1e-7, sines.max()
+
+
+# ------------------------------------------------------------- MINRES inner solves
+def test_filter_parity_minres_fp64(ctx, torch_cuda):
+    """Batched shifted MINRES (one Lanczos recurrence per column serving every shift, three-term
+    direction updates) against the oracle's column-by-column minimal-residual iterates: 16 steps
+    on every (column, shift), FP64, configuration 1."""
+    import paper_1706_00692_amd as pk
+
+    torch = torch_cuda
+    prob = W.config1()
+    lam, X, R, r = _first_iterate(prob)
+    A = prob.A.to_scipy()
+    z, w, half = contour_nodes(prob.contour)
+    D = [O.minres_columns(O.shifted_operator(A, None, zk), R / (zk - lam)[None, :], 16, 0.0)[0] for zk in z]
+    want = O.quad_accumulate(X, lam, D, z, w, half)
+    Am = ctx.matrix(prob.A)
+    p = pk.params_struct(prob.m0, max_outer=1, max_inner=4, max_cycles=4, alpha=0.0, tol=1e-9,
+                         precision=pk.PREC_FP64, basis=pk.BASIS_MINRES)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    Qd = torch.zeros_like(Xd)
+    iters = ctx.filter(Am, None, prob.contour, p, Xd, torch.from_numpy(lam).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(R)).cuda(), 1.0, Qd)
+    torch.cuda.synchronize()
+    assert list(iters) == [16] * 8
+    err = np.abs(Qd.cpu().numpy() - want).max() / np.abs(want).max()
+    assert err <= 1e-8, err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_minres_inner(ctx, prec):
+    """Whole solves with MINRES inner solves: configuration 1 against its closed form and the
+    oracle (MINRES inner solves too), a ragged 9^3 Laplacian + potential against dense eigh."""
+    import paper_1706_00692_amd as pk
+
+    pr = pk.PREC_FP64 if prec == "fp64" else pk.PREC_MIXED
+    prob = W.config1()
+    res = ctx.solve_problem(prob, precision=pr, basis=pk.BASIS_MINRES)
+    ref = O.ifeast(prob.A, None, prob.contour, prob.m0, prob.max_inner, prob.alpha, prob.tol, prob.x0(),
+                   prob.max_outer, max_cycles=prob.max_cycles, inner_rule=prob.inner_rule, tau=prob.tau,
+                   inner="minres")
+    _check_against_oracle(prob, res, ref)
+    mu = 2 - 2 * np.cos(np.arange(1, 21) * np.pi / 21)
+    exact = np.sort((mu[:, None] + mu[None, :]).ravel())
+    assert np.allclose(np.sort(res.lam_in), exact[(exact > 0.5) & (exact < 0.8)], rtol=1e-10, atol=0)
+    N = 9
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    prob = W.config2_small(N=N, m0=32, emin=0.5 * (lam_all[3] + lam_all[4]), emax=0.5 * (lam_all[15] + lam_all[16]))
+    res = ctx.solve_problem(prob, precision=pr, basis=pk.BASIS_MINRES)
+    assert res.status == 0 and res.m == 12
+    assert np.allclose(np.sort(res.lam_in), lam_all[4:16], rtol=1e-10, atol=0)
+    assert res.resid[: res.m].max() <= prob.tol

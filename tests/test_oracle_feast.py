@@ -222,3 +222,15 @@ def test_ifeast_status_m0_too_small_and_no_eig():
     res = O.ifeast(p.A, None, p.contour, p.m0, p.max_inner, p.alpha, p.tol, p.x0(), p.max_outer,
                    max_cycles=p.max_cycles, inner_rule=p.inner_rule, tau=p.tau)
     assert res.status == "ok" and res.m == 11
+
+
+def test_ifeast_minres_inner_closed_form():
+    """IFEAST with MINRES inner solves (the paper's experiments) reaches configuration 1's
+    closed-form eigenvalues."""
+    p = W.config1()
+    res = O.ifeast(p.A, None, p.contour, p.m0, p.max_inner, p.alpha, p.tol, p.x0(), p.max_outer,
+                   max_cycles=p.max_cycles, inner_rule=p.inner_rule, tau=p.tau, inner="minres")
+    exact = _lap_exact(20)
+    want = exact[(exact > 0.5) & (exact < 0.8)]
+    assert res.converged and res.m == 11 and res.status == "ok"
+    assert np.allclose(np.sort(res.lam_in), want, rtol=1e-10, atol=0)

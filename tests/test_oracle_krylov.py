@@ -93,3 +93,34 @@ def test_generalized_operator():
     D, info = block_gmres(shifted_operator(A, B, z), R, 14, 0.0)
     exact = np.linalg.solve(z * B.toarray() - A.toarray(), R)
     assert np.allclose(D, exact, atol=1e-8)
+
+
+def test_minres_columns_are_minimal_residual_iterates():
+    """MINRES's k-step iterate minimises ||b - M y|| over K_k(M, b): for a complex-shifted symmetric
+    matrix it equals the projection solution computed from an explicit Krylov matrix (normal
+    equations of the minimisation), column by column, and the residual does not grow with k."""
+    import oracle as O
+
+    rng = np.random.default_rng(7)
+    n = 60
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    z = 0.3 + 0.7j
+    M = lambda V: z * V - A @ V
+    B = rng.standard_normal((n, 3))
+    prev = np.full(3, np.inf)
+    for k in (1, 3, 6):
+        D, its = O.minres_columns(M, B, k, 0.0)
+        assert its == [k, k, k]
+        for c in range(3):
+            b = B[:, c].astype(complex)
+            K = np.column_stack([np.linalg.matrix_power(z * np.eye(n) - A, i) @ b for i in range(k)])
+            MK = (z * np.eye(n) - A) @ K
+            coef = np.linalg.lstsq(MK, b, rcond=None)[0]
+            assert np.allclose(D[:, c], K @ coef, rtol=1e-8, atol=1e-10 * np.abs(b).max())
+        r = np.linalg.norm(B - M(D), axis=0)
+        assert np.all(r <= prev * (1 + 1e-12))
+        prev = r
+    # a full-dimension space solves exactly
+    D, _ = O.minres_columns(M, B, n, 0.0)
+    assert np.allclose(D, np.linalg.solve(z * np.eye(n) - A, B), rtol=1e-8, atol=1e-10)

@@ -165,6 +165,10 @@ typedef struct {
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
  * device memory of resident requests in the serving loop (0 = 90% of free). */
 int ifeast_create(ifeast_ctx **ctx, int device, uint64_t hbm_budget_bytes);
+/* Free the context.  Serving requests still queued end with
+ * IFEAST_ERR_DEVICE (a thread blocked in ifeast_wait on one returns that
+ * status); running ones finish first.  No other call may start on the
+ * context once destroy has begun (such a call races with the free). */
 int ifeast_destroy(ifeast_ctx *ctx);
 /* Order the context's later work on a caller stream (a hipStream_t passed as
  * void*; NULL is the default (null) stream).  Until this is called a context

@@ -539,11 +539,14 @@ def test_serving_destroy_fails_queued_requests(torch_cuda):
 
     import paper_1706_00692_amd as pk
 
-    probs = _small_serving_problems()
-    p = probs[1]
+    import time
+
+    N = 20
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    p = W.config2_small(N=N, m0=32, emin=0.5 * (lam_all[3] + lam_all[4]), emax=0.5 * (lam_all[15] + lam_all[16]))
     fp = pk.footprint(p.n, p.A.nnz, 0, p.contour, _serving_params(pk, p))
-    c = pk.Context(0, budget=fp)
-    tickets = [c.submit(p.A, None, p.contour, _serving_params(pk, p), p.x0()) for _ in range(4)]
+    c = pk.Context(0, budget=fp)  # one request at a time: the later ones queue
+    tickets = [c.submit(p.A, None, p.contour, _serving_params(pk, p), p.x0()) for _ in range(8)]
     got = {}
 
     import ctypes
@@ -562,6 +565,7 @@ def test_serving_destroy_fails_queued_requests(torch_cuda):
 
     th = threading.Thread(target=waiter)
     th.start()
+    time.sleep(0.2)  # the waiter is blocked in wait() by now (the context must outlive its entry)
     c.close()
     th.join(timeout=120)
     assert not th.is_alive()

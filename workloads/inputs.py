@@ -230,7 +230,7 @@ def config4(N: int = 512, target: float | None = None, count: int = 40) -> Probl
     """2-D upwind convection-diffusion, beta = (20, 10), h^2-scaled, on an N x N grid (n = N^2,
     262,144 at N = 512), B = I: a full circle on the real axis around about 40 eigenvalues (the
     lowest ones by default), 16 trapezoidal nodes, m0 = 64, block GMRES with 10 iterations per
-    cycle."""
+    cycle and at most 30 cycles (300 iterations) per shifted solve."""
     c, r, inside = config4_circle(N, target, count)
     return Problem(
         name=f"convdiff_{N}",
@@ -244,6 +244,7 @@ def config4(N: int = 512, target: float | None = None, count: int = 40) -> Probl
         max_outer=30,
         x0_seed=2004,
         kind="general",
+        max_cycles=30,
         meta={"inside": inside},
     )
 

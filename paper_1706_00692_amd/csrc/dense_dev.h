@@ -48,6 +48,28 @@ __device__ inline double block_max(double v, double* sh) {
   return t;
 }
 
+// ---- 16-lane groups: lanes 16 q .. 16 q + 15 of a wave form one DPP row.
+// v of another lane of the same row (CTRL: a DPP row permutation), one 32-bit half at a time.
+template <int CTRL>
+__device__ inline double row_perm(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Sum over the 16 lanes of the row, in every lane of it: two quad butterflies (lane ^ 1,
+// lane ^ 2), then the half-row and row mirrors, each adding the other half's partial sum.
+// Every stage adds two operands that are swapped in the partner lane, so all 16 lanes end with
+// the same bits.  All 16 lanes of the row must be active.
+__device__ inline double row16_sum(double v) {
+  v += row_perm<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += row_perm<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += row_perm<0x141>(v);  // row_half_mirror
+  v += row_perm<0x140>(v);  // row_mirror
+  return v;
+}
+__device__ inline c2 row16_csum(c2 v) { return cmk(row16_sum(v.x), row16_sum(v.y)); }
+
 // Lane l's value of v in every lane (l wave-uniform; the whole wave active): two scalar reads
 // of the register halves instead of a lane permute through the LDS unit.
 __device__ inline double lane_bcast(double v, int l) {

@@ -184,6 +184,7 @@ struct Layout {
   size_t V, T1, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gw, Hr, Tinv, Racc, chol, Yq, Uc, zs;
   size_t Hm, Ss;  // shared basis: real block Hessenberg, per-shift start blocks
   size_t Us, Om;  // shared basis: sketch of the older blocks (n x kSketch), its random factors
+  size_t Cf;      // shared basis: coefficients of the folded second pass (5 m0 x m0)
   size_t mrv, mrd, mrp, mrs;  // MINRES: three n x m0 blocks, two direction sets, partials, state
 };
 
@@ -214,7 +215,7 @@ Layout layout(const Shape& s) {
   if (s.minres) {
     // no Krylov basis and no least squares: three Lanczos blocks and two sets of direction vectors
     L.H = L.Vh = L.tauh = L.g = L.y = L.u = L.Racc = L.chol = 0;
-    L.V = L.T1 = L.gpart = L.gred = L.gw = L.Hr = L.Tinv = L.Yq = L.Uc = L.Hm = L.Ss = L.Us = L.Om = 0;
+    L.V = L.T1 = L.gpart = L.gred = L.gw = L.Hr = L.Tinv = L.Yq = L.Uc = L.Hm = L.Ss = L.Us = L.Om = L.Cf = 0;
     L.gpart = gram_partial_bytes<double>(s.n, (int)m0, (int)m0, 1);
     L.mrv = 3 * n * m0 * ts;
     L.mrd = 2 * ns * n * m0 * 2 * ts;
@@ -235,9 +236,10 @@ Layout layout(const Shape& s) {
       gp = std::max(gp, ts == 4 ? gram_partial_bytes<float>(s.n, (int)m0, (int)m0, (int)items)
                                 : gram_partial_bytes<double>(s.n, (int)m0, (int)m0, (int)items));
     L.gpart = gp;
-    L.gred = std::max(k * m0 * m0, 2 * m0 * m0) * 8;
+    L.gred = std::max(k, (size_t)4) * m0 * m0 * 8;
     L.gw = m0 * m0 * 8;
     L.Hr = k * m0 * m0 * ts;
+    L.Cf = 5 * m0 * m0 * ts;
     L.Tinv = m0 * m0 * ts;
     L.Yq = k * m0 * m0 * ts;
     L.Uc = 16;
@@ -266,13 +268,14 @@ Layout layout(const Shape& s) {
   L.Ss = 0;
   L.Us = 0;
   L.Om = 0;
+  L.Cf = 0;
   return L;
 }
 
 size_t total(const Layout& L) {
   return 3 * L.X + L.AQ + L.BQ + L.R + 10 * L.vec + 6 * L.mm + L.rrwork + L.colpart + L.V + 2 * L.T1 + L.H + L.Vh +
          L.tauh + L.g + L.u + L.y + L.flags + L.tol + L.gpart + L.gred + L.gw + L.Hr + L.Tinv + L.Racc + L.chol + L.Yq +
-         L.Uc + 3 * L.zs + L.Hm + L.Ss + L.Us + L.Om + L.mrv + L.mrd + L.mrp + L.mrs;
+         L.Uc + 3 * L.zs + L.Hm + L.Ss + L.Us + L.Om + L.Cf + L.mrv + L.mrd + L.mrp + L.mrs;
 }
 
 }  // namespace
@@ -372,6 +375,7 @@ struct Engine::Impl {
   DevBuf V, T1, T2, H, Vh, tauh, g, y, u, flags, tol, gpart, gred, gwb, Hr, Tinv, Racc, chol, Yq, Uc, zsT, zsD, wsD;
   DevBuf Hm, Ss;             // shared basis
   DevBuf Us, Om;             // shared basis: sketch of the older blocks, its random factors
+  DevBuf Cf;                 // shared basis: folded second-pass coefficients
   int* d_one = nullptr;      // a single 1 (the shared block's activity flag)
   int shared_steps = 0;      // Arnoldi steps of the last shared inner solve
   int* d_active = nullptr;  // ns
@@ -483,6 +487,7 @@ struct Engine::Impl {
     }
     if (L.Ss) Ss = DevBuf(L.Ss);
     if (L.Us) Us = DevBuf(L.Us);
+    if (L.Cf) Cf = DevBuf(L.Cf);
     if (L.Om) {
       // fixed Gaussian factors, variance 1 / kSketch: E ||Om^T x||^2 = ||x||^2
       Om = DevBuf(L.Om);
@@ -899,7 +904,6 @@ struct Engine::Impl {
     T* U = Us.as<T>();
     if (!always || nonsym_sel) launch_fill_zero(st, Us.p, Us.bytes);
     bool force_next = false;  // the step after a triggered third pass takes one too
-    static const bool debug_reorth = getenv("IFEAST_DEBUG_REORTH") != nullptr;
     int skip_checks = 0;      // steps left before the next orthogonality estimate
     const int zero_cnt = 0;
     h2d_staged(d_cnt, &zero_cnt, sizeof(int));
@@ -956,9 +960,11 @@ struct Engine::Impl {
         project(lo, nl);
         bool full = always || lo == 0;
         int certified = -1;
+        bool folded = false;  // V_{j+1} already formed (the second pass folded into the normalisation)
         if (!full) {
           const int64_t mm0 = (int64_t)m0 * m0;
-          double* gsk = gred.as<double>() + 2 * mm0;  // beside the local pass's two items
+          double* gwf = gred.as<double>() + nl * mm0;        // W^T W: the combined Gram's last item
+          double* gsk = gred.as<double>() + (nl + 1) * mm0;  // the sketch product, beside it
           // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
           ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
                        Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
@@ -973,20 +979,38 @@ struct Engine::Impl {
           } else {
             --skip_checks;
           }
-          launch_gram<T>(st, gw, gpart.p, gpart.bytes);
-          if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwb.as<double>(), d_loss);
+          // the second pass's coefficients G2 = [V_{j-1}, V_j]^T W and the block's own Gram
+          // W^T W in one sweep over W: items 0..nl of [V_{j-1}, V_j, W]^T W
+          GramArgs g3{n, m0, m0, 1, nl + 1, Vb + (int64_t)lo * bs, m0, 0, bs, t1, m0, 0, 0, nullptr, gred.as<double>()};
+          g3.A_last = t1;
+          launch_gram<T>(st, g3, gpart.p, gpart.bytes);
+          if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwf, d_loss);
           // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass
           // changes the block by rounding only, or (a full pass) by at most reorth_eta per
           // column, which the margin on the Gershgorin bound covers
-          launch_gersh_flags(st, m0, gwb.as<double>(), single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh,
-                             d_cnt);
+          launch_gersh_flags(st, m0, gwf, single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh, d_cnt);
           // the estimate and the flags in one copy
           double* hchk = reinterpret_cast<double*>(h_flags + 128);
           IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 2 * sizeof(int), hipMemcpyDeviceToHost, st));
           IF_HIP(hipEventRecord(ev_chk, st));
-          // the local second pass is needed in either case: it runs while the host waits
-          gram(j, lo, nl, 1);
-          project(lo, nl);
+          // the common case (no pass against the older blocks) runs while the host waits: the
+          // second pass folded into the normalisation, V_{j+1} = (W - V G2) R^{-1} from the
+          // Gram W^T W - G2^T G2 (the pass removed little, so the downdate loses nothing to
+          // cancellation) as one product over [V_{j-1}, V_j, W]
+          launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwf);
+          const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
+          T* hr_next = j + 1 < K ? Hr.as<T>() : nullptr;
+          launch_cholqr_real_ctl<T>(st, m0, gwf, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single_sh, 0,
+                                    Hm.as<double>(), ldh, j, hr_next);
+          T* cf = Cf.as<T>();
+          T* g2t = cf + (nl + 1) * mm0;
+          launch_fold_second_pass<T>(st, m0, nl, gred.as<double>(), Tinv.as<T>(), cf, g2t, Hm.as<double>(), ldh, j,
+                                     lo);
+          T* dst = Vb + (int64_t)(j + 1) * bs;
+          ApplyArgs af{n, m0, m0, 1, nl + 1, nl + 1, Vb + (int64_t)lo * bs, m0, 0, 0, bs, cf, 0, dst, m0, 0, 1.0, 0.0,
+                       nullptr, nullptr};
+          af.A_last = t1;
+          launch_apply<T, T>(st, af);
           IF_HIP(hipEventSynchronize(ev_chk));
           // a third pass cleans the new block, but the block before it still carries the loss
           // into the next step's product: that step takes a third pass too, after which both
@@ -1005,31 +1029,28 @@ struct Engine::Impl {
           if (full) skip_checks = 0;
           certified = h_flags[130] != 0 ? 1 : 0;
           if (full) {
-            // a third pass against every block (the local blocks again: their coefficients are
-            // rounding-sized), and the block's Gram afresh
+            // the folded block is discarded: the second pass as a projection, then a third pass
+            // against every block (the local blocks again: their coefficients are rounding-sized),
+            // the block's Gram afresh and its normalisation
+            ApplyArgs ap{n, m0, m0, 1, nl, nl, Vb + (int64_t)lo * bs, m0, 0, 0, bs, g2t, 0, t1, m0, 0, -1.0, 1.0,
+                         nullptr, nullptr};
+            launch_apply<T, T>(st, ap);
             gram(j, 0, j + 1, 1);
-            if (debug_reorth) {
-              std::vector<double> gh((size_t)(j + 1) * m0 * m0), wh((size_t)m0 * m0);
-              IF_HIP(hipMemcpyAsync(gh.data(), gred.p, gh.size() * 8, hipMemcpyDeviceToHost, st));
-              IF_HIP(hipMemcpyAsync(wh.data(), gwb.p, wh.size() * 8, hipMemcpyDeviceToHost, st));
-              IF_HIP(hipStreamSynchronize(st));
-              fprintf(stderr, "[reorth] j=%d est=%.1e per-block max|c|/|w|:", j, hchk[0]);
-              for (int i = 0; i <= j; ++i) {
-                double mx = 0.0;
-                for (int a = 0; a < m0; ++a)
-                  for (int b = 0; b < m0; ++b)
-                    mx = std::max(mx, std::fabs(gh[(size_t)i * m0 * m0 + a * m0 + b]) / std::sqrt(wh[b * m0 + b]));
-                fprintf(stderr, " %.0e", mx);
-              }
-              fprintf(stderr, "\n");
-            }
             project(0, j + 1);
             launch_gram<T>(st, gw, gpart.p, gpart.bytes);
             ++reorth_steps;
-          } else {
-            // W^T W - C^T C: the pass removed little, so this loses nothing to cancellation
-            launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwb.as<double>());
+            cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified, j, ldh, hr_next);
+          } else if (certified == 0) {
+            // the second Cholesky-QR pass (the first ran shifted)
+            GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two_sh, gred.as<double>(), -1};
+            launch_gram<T>(st, g2, gpart.p, gpart.bytes);
+            launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1,
+                                      Hm.as<double>(), ldh, j, hr_next, chol.as<double>());
+            ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, t2, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
+            launch_apply<T, T>(st, a2);
+            launch_copy_if<T>(st, d_two_sh, n * m0, t2, dst);
           }
+          folded = true;
         } else {
           gram(j, lo, nl, 1);
           project(lo, nl);
@@ -1039,7 +1060,7 @@ struct Engine::Impl {
         if (always) {
           cholqr2_real<T>(t1, t2, dst, gwb.as<double>());
           launch_subdiag_real(st, m0, j, ldh, Racc.as<cd>(), Hm.as<double>());
-        } else {
+        } else if (!folded) {
           cholqr_adaptive_real<T>(t1, t2, dst, gwb.as<double>(), certified, j, ldh,
                                   j + 1 < K ? Hr.as<T>() : nullptr);
         }

@@ -93,7 +93,9 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
   if (r0 >= r1) {
     // an empty split still owns its slot of partial sums
   }
-  const T* __restrict__ A = static_cast<const T*>(g.A) + s * g.a_s + i * g.a_i + p0;
+  const T* __restrict__ A = (g.A_last != nullptr && i == g.ni - 1 ? static_cast<const T*>(g.A_last) + s * g.a_s
+                                                                    : static_cast<const T*>(g.A) + s * g.a_s + i * g.a_i) +
+                            p0;
   const T* __restrict__ B = static_cast<const T*>(g.B) + s * g.b_s + i * g.b_i + q0;
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -227,6 +229,10 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
   const int64_t r1 = min(g.n, r0 + rows_per_split);
   const T* __restrict__ A0 = static_cast<const T*>(g.A) + s * g.a_s + i0 * g.a_i;
   const T* __restrict__ B = static_cast<const T*>(g.B) + s * g.b_s;
+  const T* Aq[4];  // the group's blocks (the shift's last one possibly from A_last)
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    Aq[q] = (g.A_last != nullptr && i0 + q == g.ni - 1) ? static_cast<const T*>(g.A_last) + s * g.a_s : A0 + q * g.a_i;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   // waves per block: with fewer than four blocks in the group, several waves share a block,
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
       rb[t] = ok ? *reinterpret_cast<const V*>(B + row * g.ldb + c) : zero16<T>();
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        ra[q][t] = (ok && q < nil) ? *reinterpret_cast<const V*>(A0 + q * g.a_i + row * g.lda + c) : zero16<T>();
+        ra[q][t] = (ok && q < nil) ? *reinterpret_cast<const V*>(Aq[q] + row * g.lda + c) : zero16<T>();
     }
   };
   if (r0 < r1) fetch(r0);
@@ -367,7 +373,9 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
   V ra[PERA], rb[PERB];
   auto fetch = [&](int b, int k0) {
     const int sb = b / a.nbi, ib = b % a.nbi;
-    const T* __restrict__ Ab = Abase + sb * a.a_s + ib * a.a_i;
+    const T* __restrict__ Ab = (a.A_last != nullptr && b == a.nb - 1)
+                                   ? static_cast<const T*>(a.A_last) + item * a.a_item
+                                   : Abase + sb * a.a_s + ib * a.a_i;
     const T* __restrict__ Bb = Bbase + (int64_t)b * a.KW * a.OW;
 #pragma unroll
     for (int t = 0; t < PERA; ++t) {
@@ -626,8 +634,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     if (kt) {
       const int nact = kt->count(g.active, g.ns);
       const double eff = (double)nact * g.ni;
-      // the self Gram (A == B, one block) reads one block
-      const double rb = (g.A == g.B && g.ni == 1) ? 0.0 : (double)g.n * g.QW * sizeof(T) * nact;
+      // the self Gram (A == B, one block, or B as the last block) reads B once, as an A block
+      const double rb = ((g.A == g.B && g.ni == 1) || g.A_last == g.B) ? 0.0 : (double)g.n * g.QW * sizeof(T) * nact;
       kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, (double)g.n * g.PW * sizeof(T) * eff + rb);
     }
     const int64_t total = (int64_t)items * g.PW * g.QW * 8;
@@ -667,11 +675,14 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   IF_HIP(hipGetLastError());
   if (kt) {
     // algorithmic: every active item's A block once; B once per item, or once per shift when the
-    // blocks of a shift share it (b_i == 0); the self Gram (A == B, one block) reads one block
+    // blocks of a shift share it (b_i == 0); the self Gram (A == B, one block, or B as the last
+    // block) reads B once, as an A block
     const int nact = kt->count(g.active, g.ns);
     const double eff = (double)nact * g.ni;
     const double ra = (double)g.n * g.PW * sizeof(T) * eff;
-    const double rb = (g.A == g.B && g.ni == 1) ? 0.0 : (double)g.n * g.QW * sizeof(T) * (g.b_i == 0 ? nact : eff);
+    const double rb = ((g.A == g.B && g.ni == 1) || g.A_last == g.B)
+                          ? 0.0
+                          : (double)g.n * g.QW * sizeof(T) * (g.b_i == 0 ? nact : eff);
     kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, ra + rb);
   }
   const int64_t total = (int64_t)items * g.PW * g.QW * 8;

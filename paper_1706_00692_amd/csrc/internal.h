@@ -173,6 +173,7 @@ struct GramArgs {
   int kclass = KC_GRAM;  // timing class (KC_GRAM or KC_OUTER; < 0: not timed)
   int tb_cap = 0;        // > 0: largest square tile, in 16-column blocks (narrow-by-wide products)
   GramCombine cmb;       // optional (cmb.Hm != null): Hm and Hr written by the reduction
+  const void* A_last = nullptr;  // optional: block ni - 1 of each shift read from A_last + s * a_s instead
 };
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes);
@@ -198,6 +199,7 @@ struct ApplyArgs {
   const int* active_item;  // per item, may be null
   const int* active_sb;    // per sb, may be null
   int kclass = KC_UPDATE;  // timing class (KC_UPDATE or KC_QACC; < 0: not timed)
+  const void* A_last = nullptr;  // optional: block nb - 1 read from A_last + item * a_item instead
 };
 template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a);
@@ -270,6 +272,12 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 // gw -= C^T C (C: rows x m0): the Gram of a block after projecting out orthonormal directions
 void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw);
+// The second Gram-Schmidt pass folded into the Cholesky-QR product: from G2 (nl blocks m0 x m0,
+// FP64) and Tinv, Cf = [-G2_0 Tinv; ..; -G2_{nl-1} Tinv; Tinv], G2T = G2 in type T, and
+// Hm(lo + b, j) += G2_b.
+template <class T>
+void launch_fold_second_pass(hipStream_t st, int m0, int nl, const double* G2, const T* Tinv, T* Cf, T* G2T,
+                             double* Hm, int ldh, int j, int lo);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
 // block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
 void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,

@@ -139,6 +139,34 @@ __global__ void k_sum_y(int ns, int m0, int kcap, int jmax, const c2* __restrict
   Yr[idx] = (T)acc;
 }
 
+// The second Gram-Schmidt pass folded into the normalisation.  With G2 = [V_lo..V_{lo+nl-1}]^T W
+// the second pass's coefficients and R^{-1} = Tinv the Cholesky-QR factor of
+// (W - V G2)^T (W - V G2) = W^T W - G2^T G2, the next block is
+//     V_{j+1} = (W - V G2) Tinv = V (-G2 Tinv) + W Tinv,
+// one product over [V_lo.., W] with the stacked coefficients written here:
+// Cf[b] = -G2_b Tinv (b < nl) and Cf[nl] = Tinv; also G2T = G2 in type T and Hm += G2 (block rows
+// lo.. of block column j, as the second pass accumulates its coefficients).
+// G2: nl blocks m0 x m0 row-major (FP64); Tinv: m0 x m0 row-major, upper triangular.
+template <class T>
+__global__ void k_fold_second_pass(int m0, int nl, const double* __restrict__ G2, const T* __restrict__ Tinv,
+                                   T* __restrict__ Cf, T* __restrict__ G2T, double* __restrict__ Hm, int ldh, int j,
+                                   int lo) {
+  const int64_t mm = (int64_t)m0 * m0;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (nl + 1) * mm) return;
+  const int b = (int)(idx / mm), a = (int)((idx % mm) / m0), q = (int)(idx % m0);
+  if (b == nl) {
+    Cf[idx] = Tinv[a * m0 + q];
+    return;
+  }
+  const double* g = G2 + b * mm + (int64_t)a * m0;
+  double acc = 0.0;
+  for (int k = 0; k <= q; ++k) acc += g[k] * (double)Tinv[k * m0 + q];
+  Cf[idx] = (T)(-acc);
+  G2T[idx] = (T)g[q];
+  Hm[(int64_t)(j * m0 + q) * ldh + (int64_t)(lo + b) * m0 + a] += g[q];
+}
+
 }  // namespace
 
 template <class T>
@@ -178,6 +206,18 @@ void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* 
   IF_HIP(hipGetLastError());
 }
 
+template <class T>
+void launch_fold_second_pass(hipStream_t st, int m0, int nl, const double* G2, const T* Tinv, T* Cf, T* G2T,
+                             double* Hm, int ldh, int j, int lo) {
+  hipLaunchKernelGGL((k_fold_second_pass<T>), dim3(nblk((int64_t)(nl + 1) * m0 * m0)), dim3(256), 0, st, m0, nl, G2,
+                     Tinv, Cf, G2T, Hm, ldh, j, lo);
+  IF_HIP(hipGetLastError());
+}
+
+template void launch_fold_second_pass<float>(hipStream_t, int, int, const double*, const float*, float*, float*,
+                                             double*, int, int, int);
+template void launch_fold_second_pass<double>(hipStream_t, int, int, const double*, const double*, double*, double*,
+                                              double*, int, int, int);
 template void launch_to_T<float>(hipStream_t, int64_t, const double*, float*);
 template void launch_to_T<double>(hipStream_t, int64_t, const double*, double*);
 template void launch_sum_y<float>(hipStream_t, int, int, int, int, const cd*, const double*, float*);

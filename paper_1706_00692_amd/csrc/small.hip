@@ -703,40 +703,10 @@ __global__ __launch_bounds__(256) void k_lsq_init(LsqArgs a, const c2* __restric
   }
 }
 
-// Step j, part 1: the reflectors of steps i0..j-1 on the new block column j of Hbar
-// (i0 = 0, or j - band - 1 for a banded Hbar).  Reflector block i acts on rows
-// [i m0, (i+2) m0) only, and once it has acted rows [i m0, (i+1) m0) are final, so each wave
-// (one column, 4y + w of grid row y) slides a 2 m0-row window through LDS: load the next m0
-// rows, apply block i, write back the first m0.  grid (ns, ceil(m0/4)).
-__global__ __launch_bounds__(256) void k_lsq_prev(LsqArgs a, int j) {
-  __shared__ c2 winbuf[4 * 256];  // 4 waves x 2 m0 (m0 <= 128)
-  const int s = blockIdx.x;
-  if (a.active[s] == 0 || j == 0) return;
-  const LsqView v = lsq_view(a, s);
-  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = blockIdx.y * 4 + wave;
-  if (col >= m0) return;
-  const int i0 = a.band > 0 ? max(0, j - a.band - 1) : 0;
-  c2* h = v.H + (int64_t)(j * m0 + col) * ldh;  // h[r] is row r of the column
-  c2* win = winbuf + wave * m2;                 // rows [i m0, (i+2) m0) of the column
-  for (int r = lane; r < m0; r += 64) win[r] = h[i0 * m0 + r];
-  for (int i = i0; i < j; ++i) {
-    for (int r = lane; r < m0; r += 64) win[m0 + r] = h[(i + 1) * m0 + r];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    wave_reflect_run(v.Vh + (int64_t)i * m2 * m0, v.tau + i * m0, m0, m2, win, lane, false);
-    for (int r = lane; r < m0; r += 64) {
-      h[i * m0 + r] = win[r];
-      win[r] = win[m0 + r];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  }
-  for (int r = lane; r < m0; r += 64) h[j * m0 + r] = win[r];
-}
-
-// Step j, part 2: Householder QR of the slab rows [j m0, (j+2) m0) of block column j
-// (its lower half is upper triangular), the same reflectors on the right-hand side,
-// per-column residual norms and the stopping rule.  One workgroup per shift.
+// Step j for m0 > 96, after the earlier reflectors (k_lsq_reflect): Householder QR of the slab
+// rows [j m0, (j+2) m0) of block column j (its lower half is upper triangular) in global memory,
+// the same reflectors on the right-hand side, per-column residual norms and the stopping rule.
+// One workgroup per shift, one wave per column.
 __global__ __launch_bounds__(256) void k_lsq_qr(LsqArgs a, int j) {
   const int s = blockIdx.x;
   if (a.active[s] == 0) return;
@@ -820,113 +790,6 @@ __global__ __launch_bounds__(256) void k_lsq_qr(LsqArgs a, int j) {
   }
 }
 
-// The same factorisation with the slab held in LDS, packed: column c keeps its rows
-// 0..m0+c (the rest of the slab is zero), 1.5 m0^2 complex numbers in all.  16 waves:
-// wave 0 forms reflector c while the others wait, then all waves apply it to the
-// columns to its right.  The right-hand side is left to k_lsq_rhs.
-__global__ __launch_bounds__(1024) void k_lsq_qr_lds(LsqArgs a, int j) {
-  extern __shared__ c2 lds[];
-  constexpr int NW = 16;
-  const int s = blockIdx.x;
-  if (a.active[s] == 0) return;
-  const LsqView v = lsq_view(a, s);
-  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int base = j * m0;
-  const int P = m0 * m0 + m0 * (m0 + 1) / 2;
-  c2* sl = lds;           // packed slab
-  c2* vb = lds + P;       // current reflector (2 m0)
-  auto off = [&](int col) { return col * (m0 + 1) + col * (col - 1) / 2; };  // start of column col
-  c2* h = v.H + (int64_t)j * m0 * ldh + base;
-  c2* Vj = v.Vh + (int64_t)j * m2 * m0;
-  double* tj = v.tau + j * m0;
-  __shared__ double sh_tau;
-  for (int col = wave; col < m0; col += NW) {
-    c2* dst = sl + off(col);
-    const c2* src = h + (int64_t)col * ldh;
-    for (int r = lane; r <= m0 + col; r += 64) dst[r] = src[r];
-  }
-  __syncthreads();
-  for (int c = 0; c < m0; ++c) {
-    c2* xc = sl + off(c);
-    const int r0 = c, r1 = m0 + c + 1;
-    if (wave == 0) {
-      double ss = 0.0;
-      for (int r = r0 + lane; r < r1; r += 64) ss += cabs2(xc[r]);
-      ss = wave_dsum(ss);
-      const double nrm = sqrt(ss);
-      const c2 x0 = xc[r0];
-      double tau = 0.0;
-      c2 beta = x0, v0 = cmk(0.0, 0.0);
-      if (nrm > 0.0) {
-        const double ax = sqrt(cabs2(x0));
-        const c2 ph = ax > 0.0 ? cscale(1.0 / ax, x0) : cmk(1.0, 0.0);
-        beta = cscale(-nrm, ph);
-        v0 = csub(x0, beta);
-        const double vn2 = ss - cabs2(x0) + cabs2(v0);
-        tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-      }
-      for (int r = lane; r < m2; r += 64) {
-        c2 val = cmk(0.0, 0.0);
-        if (tau != 0.0) val = (r == r0) ? v0 : ((r > r0 && r < r1) ? xc[r] : cmk(0.0, 0.0));
-        vb[r] = val;
-        Vj[(int64_t)c * m2 + r] = val;
-      }
-      if (lane == 0) {
-        tj[c] = tau;
-        sh_tau = tau;
-      }
-      if (tau != 0.0)
-        for (int r = r0 + lane; r < r1; r += 64) xc[r] = (r == r0) ? beta : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    const double tau = sh_tau;
-    if (tau != 0.0) {
-      for (int col = c + 1 + wave; col < m0; col += NW) {
-        c2* x = sl + off(col);
-        c2 d = cmk(0.0, 0.0);
-        for (int r = r0 + lane; r < r1; r += 64) d = cadd(d, cjmul(vb[r], x[r]));
-        d = wave_csum(d);
-        const c2 f = cscale(tau, d);
-        for (int r = r0 + lane; r < r1; r += 64) x[r] = csub(x[r], cmul(f, vb[r]));
-      }
-    }
-    __syncthreads();
-  }
-  // R block column back to global (rows 0..m0+col of each slab column)
-  for (int col = wave; col < m0; col += NW) {
-    const c2* src = sl + off(col);
-    c2* dst = h + (int64_t)col * ldh;
-    for (int r = lane; r <= m0 + col; r += 64) dst[r] = src[r];
-  }
-}
-
-// Step j, part 3: the reflectors of step j on the right-hand side slab, one wave per
-// column (staged in LDS), and that column's residual norm (the last m0 rows of the
-// transformed slab).  grid (ns, ceil(m0/4)).
-__global__ __launch_bounds__(256) void k_lsq_rhs(LsqArgs a, int j) {
-  __shared__ c2 colbuf[4 * 256];  // 4 x 2 m0
-  const int s = blockIdx.x;
-  if (a.active[s] == 0) return;
-  const LsqView v = lsq_view(a, s);
-  const int m0 = a.m0, ldh = a.ldh, m2 = 2 * m0;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = blockIdx.y * 4 + wave;
-  if (col >= m0) return;
-  c2* x = colbuf + wave * m2;
-  c2* gc = v.g + j * m0 + (int64_t)col * ldh;
-  for (int r = lane; r < m2; r += 64) x[r] = gc[r];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  wave_reflect_run(v.Vh + (int64_t)j * m2 * m0, v.tau + j * m0, m0, m2, x, lane, false);
-  double ss = 0.0;
-  for (int r = lane; r < m2; r += 64) {
-    gc[r] = x[r];
-    if (r >= m0) ss += cabs2(x[r]);
-  }
-  ss = wave_dsum(ss);
-  if (lane == 0) v.res[col] = sqrt(ss);
-}
-
 // Step j, part 4: the stopping rule of the shift (every column's residual at or below
 // its threshold ends the cycle).  One wave per shift.
 __global__ void k_lsq_stop(LsqArgs a, int j) {
@@ -942,6 +805,281 @@ __global__ void k_lsq_stop(LsqArgs a, int j) {
     if (!bad) {
       a.cycle_done[s] = 1;
       a.active[s] = 0;
+    }
+  }
+}
+
+// ---- step j with one 16-lane group per column (DPP row reductions instead of wave-wide lane
+// permutes, so a reflector's dot product costs four dependent stages): k_lsq_reflect for the
+// earlier reflectors, k_lsq_qr_regs for the new slab (m0 <= 96), k_lsq_reflect for the
+// right-hand side and its residual norms, k_lsq_stop.
+//
+// Reflectors of earlier steps on a block of columns.  grid (ns, ceil(m0/16)), 256 threads:
+// group g owns column 16 y + g.  RHS == false: the reflectors of steps i0..j-1 on block column
+// j of Hbar (i0 = 0, or j - band - 1 for a banded Hbar); RHS == true: those of step j on the
+// right-hand side slab rows [j m0, (j+2) m0), then the column's residual norm (the slab's last
+// m0 rows).  M0 > 0: m0 fixed at compile time (the lane masks fold away); 0: a.m0.
+// Reflector block i acts on rows [i m0, (i+2) m0) only and leaves rows [i m0, (i+1) m0) final, so the group keeps that window in registers: rows i m0 + 16 q + l
+// (top) and (i+1) m0 + 16 q + l (bottom) in lane l's slot q < SH = ceil(m0/16), the next
+// block's rows loading while the current block applies.  The reflectors pass through LDS in
+// chunks of rc columns (rc * 2 m0 <= kChunk), the next chunk's loads in flight meanwhile.
+constexpr int kChunk = 2560;  // complex entries of one reflector chunk (40 KiB)
+constexpr int kChunkPer = kChunk / 256;
+
+template <int SH, bool RHS, int M0>
+__global__ __launch_bounds__(256) void k_lsq_reflect(LsqArgs a, int j, int rc) {
+  extern __shared__ c2 vch[];  // rc x 2 m0 reflector entries, then rc taus
+  const int s = blockIdx.x;
+  if (a.active[s] == 0 || (!RHS && j == 0)) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = M0 > 0 ? M0 : a.m0, ldh = a.ldh, m2 = 2 * m0;
+  const int tid = threadIdx.x, l = tid & 15;
+  const int col = blockIdx.y * 16 + (tid >> 4);
+  const bool has = col < m0;  // the same for the 16 lanes of a group
+  double* tch = reinterpret_cast<double*>(vch + rc * m2);
+  const int i0 = RHS ? j : (a.band > 0 ? max(0, j - a.band - 1) : 0);
+  const int i1 = RHS ? j + 1 : j;  // reflector blocks [i0, i1)
+  c2* h = (RHS ? v.g : v.H + (int64_t)j * m0 * ldh) + (int64_t)(has ? col : 0) * ldh;  // row 0 of the column
+  auto load_rows = [&](int r0, c2* dst) {
+#pragma unroll
+    for (int q = 0; q < SH; ++q) {
+      const int rr = 16 * q + l;
+      dst[q] = (has && rr < m0) ? h[r0 + rr] : cmk(0.0, 0.0);
+    }
+  };
+  auto store_rows = [&](int r0, const c2* src) {
+#pragma unroll
+    for (int q = 0; q < SH; ++q) {
+      const int rr = 16 * q + l;
+      if (has && rr < m0) h[r0 + rr] = src[q];
+    }
+  };
+  c2 top[SH], bot[SH], nxt[SH];
+  load_rows(i0 * m0, top);
+  load_rows((i0 + 1) * m0, bot);
+  if (i0 + 1 < i1) load_rows((i0 + 2) * m0, nxt);
+  const int nch = (m0 + rc - 1) / rc, total = (i1 - i0) * nch;
+  c2 pre[kChunkPer];
+  double pre_tau = 0.0;
+  auto fetch = [&](int t) {
+    const int i = i0 + t / nch, c0 = (t % nch) * rc, cnt = min(rc, m0 - c0);
+    const c2* src = v.Vh + ((int64_t)i * m0 + c0) * m2;  // reflector c0 of step i
+#pragma unroll
+    for (int q = 0; q < kChunkPer; ++q) {
+      const int e = tid + 256 * q;
+      pre[q] = e < cnt * m2 ? src[e] : cmk(0.0, 0.0);
+    }
+    pre_tau = tid < cnt ? v.tau[i * m0 + c0 + tid] : 0.0;
+  };
+  fetch(0);
+  for (int t = 0; t < total; ++t) {
+    const int i = i0 + t / nch, c0 = (t % nch) * rc, cnt = min(rc, m0 - c0);
+    __syncthreads();  // the previous chunk is no longer read
+#pragma unroll
+    for (int q = 0; q < kChunkPer; ++q) {
+      const int e = tid + 256 * q;
+      if (e < cnt * m2) vch[e] = pre[q];
+    }
+    if (tid < cnt) tch[tid] = pre_tau;
+    __syncthreads();
+    if (t + 1 < total) fetch(t + 1);
+    if (has) {
+      for (int cc = 0; cc < cnt; ++cc) {
+        const double tv = tch[cc];
+        if (tv == 0.0) continue;
+        // the reflector's entries for this lane's rows, all loads first; it is zero off its
+        // support rows c .. m0 + c (padding lanes take zeros)
+        const c2* vc = vch + cc * m2;
+        c2 vt[SH], vu[SH];
+#pragma unroll
+        for (int q = 0; q < SH; ++q) {
+          const int rr = min(16 * q + l, m0 - 1);
+          vt[q] = vc[rr];
+          vu[q] = vc[m0 + rr];
+        }
+        c2 d = cmk(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < SH; ++q) {
+          if (16 * q + l >= m0) {
+            vt[q] = cmk(0.0, 0.0);
+            vu[q] = cmk(0.0, 0.0);
+          }
+          d = cadd(d, cjmul(vt[q], top[q]));
+          d = cadd(d, cjmul(vu[q], bot[q]));
+        }
+        const c2 f = cscale(tv, row16_csum(d));
+#pragma unroll
+        for (int q = 0; q < SH; ++q) {
+          top[q] = csub(top[q], cmul(f, vt[q]));
+          bot[q] = csub(bot[q], cmul(f, vu[q]));
+        }
+      }
+    }
+    if ((t + 1) % nch == 0) {
+      // block i done: rows [i m0, (i+1) m0) are final; the window moves down one block
+      store_rows(i * m0, top);
+      if (i + 1 < i1) {
+#pragma unroll
+        for (int q = 0; q < SH; ++q) {
+          top[q] = bot[q];
+          bot[q] = nxt[q];
+        }
+        if (i + 2 < i1) load_rows((i + 3) * m0, nxt);
+      } else {
+        store_rows((i + 1) * m0, bot);
+      }
+    }
+  }
+  if (RHS) {
+    double ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < SH; ++q) ss += cabs2(bot[q]);
+    ss = row16_sum(ss);
+    if (has && l == 0) v.res[col] = sqrt(ss);
+  }
+}
+
+// Householder QR of the slab rows [j m0, (j+2) m0) of block column j (its lower half upper
+// triangular), reflectors and taus to Vh / tauh, R in place, with the columns in registers:
+// one workgroup per shift, 512 threads in 32 groups of 16 lanes,
+// group g owning columns g, g + 32, ..  (MAXC at most).  Reflector c acts on rows c..m0+c, and the
+// owner of column c + 1 forms reflector c + 1 from rows c+1..m0+c+1, so every column a group
+// still updates keeps rows [b, b + 16 NW) in registers, b = 16 floor(c / 16) (NW slots of 16
+// rows, NW = floor((m0 + 32) / 16)): every 16 steps the top slot (final rows of R) goes to global
+// memory and the next 16 rows of the slab enter from it (loaded one window shift ahead).  A
+// finished column writes its window back.  Only the reflectors pass through LDS (two buffers
+// indexed by slab row, zero off the support), so the factorisation moves no column data
+// through LDS and needs little of it.  M0 > 0: m0 fixed at compile time; 0: a.m0.
+template <int NW, int MAXC, int M0>
+__global__ __launch_bounds__(512) void k_lsq_qr_regs(LsqArgs a, int j) {
+  constexpr int NG = 32;
+  __shared__ c2 vb[2][256 + 32];
+  __shared__ double tb[2];
+  const int s = blockIdx.x;
+  if (a.active[s] == 0) return;
+  const LsqView v = lsq_view(a, s);
+  const int m0 = M0 > 0 ? M0 : a.m0, ldh = a.ldh, m2 = 2 * m0;
+  const int tid = threadIdx.x, g = tid >> 4, l = tid & 15, gl0 = tid & 48;  // gl0: the group's first lane in its wave
+  c2* h = v.H + (int64_t)j * m0 * ldh + j * m0;  // slab (row r, col c) at h[r + c * ldh]
+  c2* Vj = v.Vh + (int64_t)j * m2 * m0;
+  double* tj = v.tau + j * m0;
+  // column i of the group: g + 32 i; rows 0..m0+col of it are stored
+  auto colof = [&](int i) { return g + NG * i; };
+  auto ld = [&](int col, int r) { return (col < m0 && r <= m0 + col) ? h[(int64_t)col * ldh + r] : cmk(0.0, 0.0); };
+  c2 x[MAXC][NW], pf[MAXC];
+#pragma unroll
+  for (int i = 0; i < MAXC; ++i) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) x[i][q] = ld(colof(i), 16 * q + l);
+    pf[i] = ld(colof(i), 16 * NW + l);
+  }
+  for (int r = tid; r < 2 * (256 + 32); r += 512) (&vb[0][0])[r] = cmk(0.0, 0.0);
+  __syncthreads();
+  int base = 0;
+  // reflector c from the window xv of column c (run by the owning group), rows c..m0+c
+  auto form = [&](int c, const c2* xv) {
+    double ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int r = base + 16 * q + l;
+      if (r >= c && r <= m0 + c) ss += cabs2(xv[q]);
+    }
+    ss = row16_sum(ss);
+    const int q0 = (c - base) >> 4, l0 = (c - base) & 15;
+    c2 x0 = cmk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < NW; ++q)
+      if (q == q0) x0 = cmk(lane_bcast(xv[q].x, gl0 + l0), lane_bcast(xv[q].y, gl0 + l0));
+    const double nrm = sqrt(ss);
+    double tau = 0.0;
+    c2 beta = x0, v0 = cmk(0.0, 0.0);
+    if (nrm > 0.0) {
+      const double ax = sqrt(cabs2(x0));
+      const c2 ph = ax > 0.0 ? cscale(1.0 / ax, x0) : cmk(1.0, 0.0);
+      beta = cscale(-nrm, ph);
+      v0 = csub(x0, beta);
+      const double vn2 = ss - cabs2(x0) + cabs2(v0);
+      tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    }
+    const int col = c;
+    c2* vbc = vb[c & 1];
+    c2* vg = Vj + (int64_t)c * m2;
+    c2* hc = h + (int64_t)col * ldh;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int r = base + 16 * q + l;
+      const bool sup = tau != 0.0 && r >= c && r <= m0 + c;
+      const c2 val = sup ? (r == c ? v0 : xv[q]) : cmk(0.0, 0.0);
+      vbc[r] = val;
+      if (r < m2) vg[r] = val;
+      // the finished column: beta on row c, zeros below it on the support
+      if (r <= m0 + col) hc[r] = (tau != 0.0 && r >= c) ? (r == c ? beta : cmk(0.0, 0.0)) : xv[q];
+    }
+    vbc[base + 16 * NW + l] = cmk(0.0, 0.0);  // the readers' window may reach one slot further
+    for (int r = l; r < base; r += 16) vg[r] = cmk(0.0, 0.0);
+    for (int r = base + 16 * NW + l; r < m2; r += 16) vg[r] = cmk(0.0, 0.0);
+    if (l == 0) {
+      tj[c] = tau;
+      tb[c & 1] = tau;
+    }
+  };
+  if (g == 0) form(0, x[0]);
+  __syncthreads();
+  // 16 steps per window position: the entering rows (loaded a window shift ahead) are consumed
+  // only at a shift, so the steps in between never wait on global memory (a wait on the loads
+  // would also wait on the reflectors' stores)
+  for (int cw = 0; cw < m0; cw += 16) {
+    if (cw > 0) {
+      // the window moves down 16 rows: the top slot is final (rows below cw) in the columns still
+      // updated (columns 0..cw are finished and written)
+#pragma unroll
+      for (int i = 0; i < MAXC; ++i) {
+        const int col = colof(i);
+        if (col > cw && col < m0) {
+          h[(int64_t)col * ldh + base + l] = x[i][0];
+#pragma unroll
+          for (int q = 0; q + 1 < NW; ++q) x[i][q] = x[i][q + 1];
+          x[i][NW - 1] = pf[i];
+          pf[i] = ld(col, base + 16 + 16 * NW + l);
+        }
+      }
+      base += 16;
+    }
+    const int cend = min(cw + 16, m0);
+    for (int c = cw; c < cend; ++c) {
+      const double tv = tb[c & 1];
+      const bool live = tv != 0.0;
+      // reflector c at this group's rows of the window (zero off its support)
+      c2 vv[NW];
+      const c2* vbc = vb[c & 1];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) vv[q] = vbc[base + 16 * q + l];
+#pragma unroll
+      for (int i = 0; i < MAXC; ++i) {
+        const int col = colof(i);
+        if (live && col > c && col < m0) {
+          c2 d = cmk(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < NW; ++q) d = cadd(d, cjmul(vv[q], x[i][q]));
+          const c2 f = cscale(tv, row16_csum(d));
+#pragma unroll
+          for (int q = 0; q < NW; ++q) x[i][q] = csub(x[i][q], cmul(f, vv[q]));
+        }
+      }
+      if (c + 1 < m0 && g == (c + 1) % NG) {
+        // the owner of column c + 1 (its slot (c + 1) / 32) forms reflector c + 1
+        const int io = (c + 1) / NG;
+        c2 xv[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) xv[q] = x[0][q];
+#pragma unroll
+        for (int i = 1; i < MAXC; ++i)
+          if (i == io)
+#pragma unroll
+            for (int q = 0; q < NW; ++q) xv[q] = x[i][q];
+        form(c + 1, xv);
+      }
+      __syncthreads();
     }
   }
 }
@@ -1604,32 +1742,63 @@ void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S) {
   hipLaunchKernelGGL(k_lsq_init, dim3(a.ns), dim3(256), 0, st, a, reinterpret_cast<const c2*>(S));
   IF_HIP(hipGetLastError());
 }
+namespace {
+template <int SH, bool RHS, int M0>
+void launch_reflect_inst(hipStream_t st, const LsqArgs& a, int j, int rc, size_t lds) {
+  hipLaunchKernelGGL((k_lsq_reflect<SH, RHS, M0>), dim3(a.ns, (a.m0 + 15) / 16), dim3(256), lds, st, a, j, rc);
+}
+// k_lsq_reflect for this m0: grid (ns, ceil(m0/16)), chunks of rc reflectors; the common block
+// sizes get kernels compiled for them
+template <bool RHS>
+void launch_lsq_reflect(hipStream_t st, const LsqArgs& a, int j) {
+  const int m2 = 2 * a.m0;
+  const int rc = std::max(1, std::min(16, kChunk / m2));
+  const size_t lds = (size_t)rc * m2 * sizeof(c2) + (size_t)rc * sizeof(double);
+  switch (a.m0) {
+    case 16: launch_reflect_inst<1, RHS, 16>(st, a, j, rc, lds); break;
+    case 32: launch_reflect_inst<2, RHS, 32>(st, a, j, rc, lds); break;
+    case 64: launch_reflect_inst<4, RHS, 64>(st, a, j, rc, lds); break;
+    case 80: launch_reflect_inst<5, RHS, 80>(st, a, j, rc, lds); break;
+    case 128: launch_reflect_inst<8, RHS, 128>(st, a, j, rc, lds); break;
+    default:
+      switch ((a.m0 + 15) / 16) {
+#define IF_LSQ_SH(SH) \
+  case SH: launch_reflect_inst<SH, RHS, 0>(st, a, j, rc, lds); break;
+        IF_LSQ_SH(1) IF_LSQ_SH(2) IF_LSQ_SH(3) IF_LSQ_SH(4) IF_LSQ_SH(5) IF_LSQ_SH(6) IF_LSQ_SH(7) IF_LSQ_SH(8)
+#undef IF_LSQ_SH
+        default: IF_REQUIRE(false, "least squares: m0 > 128");
+      }
+  }
+  IF_HIP(hipGetLastError());
+}
+template <int NW, int MAXC, int M0>
+void launch_lsq_qr_regs_inst(hipStream_t st, const LsqArgs& a, int j) {
+  hipLaunchKernelGGL((k_lsq_qr_regs<NW, MAXC, M0>), dim3(a.ns), dim3(512), 0, st, a, j);
+  IF_HIP(hipGetLastError());
+}
+// k_lsq_qr_regs for this m0 (m0 <= 96); false if it does not apply
+bool launch_lsq_qr_regs(hipStream_t st, const LsqArgs& a, int j) {
+  switch (a.m0) {
+    case 16: launch_lsq_qr_regs_inst<3, 1, 16>(st, a, j); return true;
+    case 32: launch_lsq_qr_regs_inst<4, 1, 32>(st, a, j); return true;
+    case 64: launch_lsq_qr_regs_inst<6, 2, 64>(st, a, j); return true;
+    case 80: launch_lsq_qr_regs_inst<7, 3, 80>(st, a, j); return true;
+    default:
+      if (a.m0 > 96) return false;
+      launch_lsq_qr_regs_inst<8, 3, 0>(st, a, j);
+      return true;
+  }
+}
+}  // namespace
+
 void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
-  static int max_lds = -1;
-  if (max_lds < 0) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
-  }
-  if (j > 0) {
-    IF_REQUIRE(a.m0 <= 128, "least squares: m0 > 128");
-    hipLaunchKernelGGL(k_lsq_prev, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a, j);
-    IF_HIP(hipGetLastError());
-  }
-  // packed slab in LDS when it fits the workgroup's LDS
-  const size_t P = (size_t)a.m0 * a.m0 + (size_t)a.m0 * (a.m0 + 1) / 2;
-  const size_t lds = (P + 2 * (size_t)a.m0) * sizeof(c2);
-  static const bool force_global = getenv("IFEAST_LSQ_GLOBAL") != nullptr;
-  if ((int64_t)lds + 1024 <= (int64_t)max_lds && !force_global) {
-    if (lds > 64 * 1024)
-      IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_qr_lds),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_lsq_qr_lds, dim3(a.ns), dim3(1024), lds, st, a, j);
-    IF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_lsq_rhs, dim3(a.ns, (a.m0 + 3) / 4), dim3(256), 0, st, a, j);
-    IF_HIP(hipGetLastError());
+  IF_REQUIRE(a.m0 <= 128, "least squares: m0 > 128");
+  if (j > 0) launch_lsq_reflect<false>(st, a, j);
+  if (launch_lsq_qr_regs(st, a, j)) {
+    launch_lsq_reflect<true>(st, a, j);
     hipLaunchKernelGGL(k_lsq_stop, dim3(a.ns), dim3(64), 0, st, a, j);
   } else {
+    // m0 > 96: the slab in global memory, one wave per column
     hipLaunchKernelGGL(k_lsq_qr, dim3(a.ns), dim3(256), 0, st, a, j);
   }
   IF_HIP(hipGetLastError());

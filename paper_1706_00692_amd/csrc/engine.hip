@@ -391,12 +391,14 @@ struct Engine::Impl {
                             // followed by that step's one-pass / two-pass Cholesky-QR flags
   int* d_single_sh = nullptr;
   int* d_two_sh = nullptr;
+  int* d_act3 = nullptr;    // second local pass needed (twice: the two local blocks), then 1 (W's own term)
   int* d_cnt = nullptr;     // blocks normalised with one Cholesky-QR pass (shared basis)
   double single_gersh = 0.5;
   double dead_thr = 1e-280;
   int64_t single_steps = 0; // shift-steps normalised with one Cholesky-QR pass
   double reorth_eta = 0.1;  // keep-fraction below which a second pass runs (>= 1: always)
   int64_t reorth_steps = 0; // shift-steps that ran a second pass
+  int64_t local_second = 0; // shared basis: steps whose first pass needed a second one against the local blocks
   double max_loss = 0.0;     // largest measured loss of orthogonality (shared basis, partial mode)
   int64_t ldc = 0, blk = 0;  // complex per row, reals per basis block
 
@@ -519,6 +521,7 @@ struct Engine::Impl {
     d_loss = reinterpret_cast<double*>(f + 704);
     d_single_sh = f + 706;
     d_two_sh = f + 707;
+    d_act3 = f + 708;
     d_cnt = f + 720;
     ldc = (int64_t)sh.ns * sh.m0;
     blk = sh.n * ldc * 2;
@@ -989,15 +992,19 @@ struct Engine::Impl {
           // changes the block by rounding only, or (a full pass) by at most reorth_eta per
           // column, which the margin on the Gershgorin bound covers
           launch_gersh_flags(st, m0, gwf, single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh, d_cnt);
+          // the loss of orthogonality the first pass left against the local blocks, measured: the
+          // second pass runs only when it exceeds a hundredth of the loss tolerated against the
+          // older blocks
+          launch_local_loss(st, nl * m0, m0, gred.as<double>(), gwf, 0.01 * thr, d_act3);
           // the estimate and the flags in one copy
           double* hchk = reinterpret_cast<double*>(h_flags + 128);
-          IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+          IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 3 * sizeof(int), hipMemcpyDeviceToHost, st));
           IF_HIP(hipEventRecord(ev_chk, st));
           // the common case (no pass against the older blocks) runs while the host waits: the
-          // second pass folded into the normalisation, V_{j+1} = (W - V G2) R^{-1} from the
-          // Gram W^T W - G2^T G2 (the pass removed little, so the downdate loses nothing to
-          // cancellation) as one product over [V_{j-1}, V_j, W]
-          launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwf);
+          // second pass, when needed, folded into the normalisation, V_{j+1} = (W - V G2) R^{-1}
+          // from the Gram W^T W - G2^T G2 (the pass removes little, so the downdate loses nothing
+          // to cancellation) as W R^{-1} + [V_{j-1}, V_j] (-G2 R^{-1})
+          launch_gram_downdate(st, nl * m0, m0, gred.as<double>(), gwf, d_act3);
           const double eps = sizeof(T) == 4 ? (double)FLT_EPSILON : DBL_EPSILON;
           T* hr_next = j + 1 < K ? Hr.as<T>() : nullptr;
           launch_cholqr_real_ctl<T>(st, m0, gwf, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single_sh, 0,
@@ -1005,13 +1012,18 @@ struct Engine::Impl {
           T* cf = Cf.as<T>();
           T* g2t = cf + (nl + 1) * mm0;
           launch_fold_second_pass<T>(st, m0, nl, gred.as<double>(), Tinv.as<T>(), cf, g2t, Hm.as<double>(), ldh, j,
-                                     lo);
+                                     lo, d_act3);
           T* dst = Vb + (int64_t)(j + 1) * bs;
-          ApplyArgs af{n, m0, m0, 1, nl + 1, nl + 1, Vb + (int64_t)lo * bs, m0, 0, 0, bs, cf, 0, dst, m0, 0, 1.0, 0.0,
-                       nullptr, nullptr};
-          af.A_last = t1;
-          launch_apply<T, T>(st, af);
+          ApplyArgs aw{n, m0, m0, 1, 1, 1, t1, m0, 0, 0, 0, cf + nl * mm0, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
+          launch_apply<T, T>(st, aw);
+          // the second pass's term (skipped on the device when not needed; left out of the timer,
+          // as whether it runs is known on the device only)
+          ApplyArgs av{n, m0, m0, 1, nl, nl, Vb + (int64_t)lo * bs, m0, 0, 0, bs, cf, 0, dst, m0, 0, 1.0, 1.0, d_act3,
+                       nullptr, -1};
+          launch_apply<T, T>(st, av);
           IF_HIP(hipEventSynchronize(ev_chk));
+          const bool second = h_flags[132] != 0;
+          if (second) ++local_second;
           // a third pass cleans the new block, but the block before it still carries the loss
           // into the next step's product: that step takes a third pass too, after which both
           // parents of the recurrence are clean (Simon's partial reorthogonalisation does the same)
@@ -1034,7 +1046,7 @@ struct Engine::Impl {
             // the block's Gram afresh and its normalisation
             ApplyArgs ap{n, m0, m0, 1, nl, nl, Vb + (int64_t)lo * bs, m0, 0, 0, bs, g2t, 0, t1, m0, 0, -1.0, 1.0,
                          nullptr, nullptr};
-            launch_apply<T, T>(st, ap);
+            if (second) launch_apply<T, T>(st, ap);
             gram(j, 0, j + 1, 1);
             project(0, j + 1);
             launch_gram<T>(st, gw, gpart.p, gpart.bytes);
@@ -1520,9 +1532,10 @@ int Engine::solve(const ifeast_matrix* A, const ifeast_matrix* B, const ifeast_c
         (void)hipEventElapsedTime(&ms_now, e0, en);
         (void)hipEventDestroy(en);
       }
-      fprintf(stderr, "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld single=%lld loss=%.1e t=%.2fs\n",
-              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.single_steps, I.max_loss,
-              ms_now * 1e-3);
+      fprintf(stderr,
+              "[ifeast] outer %d rf=%.3e m=%d max_inner=%d reorth=%lld local2=%lld single=%lld loss=%.1e t=%.2fs\n",
+              it + 1, stats.rf, stats.m, mx, (long long)I.reorth_steps, (long long)I.local_second,
+              (long long)I.single_steps, I.max_loss, ms_now * 1e-3);
       if (verbose2) {
         std::vector<double> etah(m0), rhoh(m0);
         IF_HIP(hipMemcpyAsync(etah.data(), eta, m0 * 8, hipMemcpyDeviceToHost, st_));

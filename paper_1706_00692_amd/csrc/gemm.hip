@@ -304,6 +304,104 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
     }
 }
 
+// The same products with eight waves: G[s, i] = A_{s,i}^T B_s for the nil <= NIL blocks
+// i = NIL y .. of a shift, each (16 TB) x (16 TB).  The nil * TB row blocks of 16 go round-robin
+// to the waves (wave w: row blocks w, w + 8, ..), each wave taking all TB column blocks of its
+// rows, so three blocks keep every wave busy and a wave holds at most ceil(NIL TB / 8) x TB
+// MFMA tiles.  The B tile and the nil A tiles of a K chunk are staged once for the workgroup.
+// grid: x = row split, y = group of NIL blocks, z = shift.
+template <class T, int TB, int NIL, int KC>
+__global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64_t rows_per_split,
+                                                   T* __restrict__ partial) {
+  using V = typename V16T<T>::t;
+  constexpr int VN = V16T<T>::N;
+  constexpr int TP = TB * 16;
+  constexpr int LD = lds_ld<T>(TP);
+  constexpr int NV = KC * TP / VN;  // 16-byte vectors per operand tile
+  constexpr int NT = NIL + 1;       // staged tiles: the A blocks, then B
+  constexpr int PER = (NT * NV + 511) / 512;
+  constexpr int MAXR = (NIL * TB + 7) / 8;
+  __shared__ T sT[NT * KC * LD];
+  const int s = blockIdx.z;
+  if (g.active != nullptr && g.active[s] == 0) return;
+  const int i0 = blockIdx.y * NIL;
+  const int nil = min(NIL, g.ni - i0);
+  const int split = blockIdx.x;
+  const int64_t r0 = (int64_t)split * rows_per_split;
+  const int64_t r1 = min(g.n, r0 + rows_per_split);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  // tile t < nil: A block i0 + t (the shift's last one possibly from A_last); t = NIL: B
+  const T* const Ab = static_cast<const T*>(g.A) + s * g.a_s;
+  const T* const Al = g.A_last != nullptr ? static_cast<const T*>(g.A_last) + s * g.a_s : nullptr;
+  const T* const Bb = static_cast<const T*>(g.B) + s * g.b_s;
+  typename Mfma<T>::acc acc[MAXR][TB];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r)
+#pragma unroll
+    for (int b = 0; b < TB; ++b) acc[r][b] = Mfma<T>::zero();
+  V pre[PER];
+  auto fetch = [&](int64_t rc) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 512 * u;
+      const int t = e / NV, v = e % NV;
+      const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
+      const int64_t row = rc + r;
+      pre[u] = zero16<T>();
+      if (t < NT && (t == NIL || t < nil) && row < r1) {
+        // the tile's source, computed (an indexed pointer array would live in scratch)
+        const T* p = t == NIL ? Bb : ((Al != nullptr && i0 + t == g.ni - 1) ? Al : Ab + (i0 + t) * g.a_i);
+        const int64_t ld = t == NIL ? g.ldb : g.lda;
+        pre[u] = *reinterpret_cast<const V*>(p + row * ld + c);
+      }
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t rc = r0; rc < r1; rc += KC) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 512 * u;
+      const int t = e / NV, v = e % NV;
+      if (t < NT) {
+        const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
+        put16<T>(sT + (t * KC + r) * LD + c, pre[u]);
+      }
+    }
+    __syncthreads();
+    if (rc + KC < r1) fetch(rc + KC);
+    const T* sB = sT + NIL * KC * LD;
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T bf[TB];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) bf[b] = sB[(kk + lk) * LD + b * 16 + li];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) {
+        const int rb = wave + 8 * r;
+        if (rb < nil * TB) {
+          const int blk = rb / TB, lr = rb % TB;
+          const T af = sT[(blk * KC + kk + lk) * LD + lr * 16 + li];
+#pragma unroll
+          for (int b = 0; b < TB; ++b) acc[r][b] = Mfma<T>::mma(af, bf[b], acc[r][b]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    const int rb = wave + 8 * r;
+    if (rb >= nil * TB) continue;
+    const int blk = rb / TB, lr = rb % TB;
+    T* out = partial + ((int64_t)(s * g.ni + i0 + blk) * nsplit + split) * TP * TP;
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(int64_t)(lr * 16 + Mfma<T>::row(lk, v)) * TP + b * 16 + li] = acc[r][b][v];
+  }
+}
+
 inline int gram_tb(int W) {
   // tile blocks per dimension: at most 10 (160 reals), as few tiles as possible
   const int nb = W / 16;
@@ -574,6 +672,8 @@ int gram_capacity(int tb) {
 int g_gram_variant = 0;
 // K chunk of the four-block Gram kernel (32, or 16).
 int g_gram4_kc = 32;
+// FP32 multi-block Grams: the eight-wave kernel (1) or the four-wave one (0).
+int g_gram_rows = 1;
 
 template <class T>
 size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
@@ -612,7 +712,29 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     KernelTimer* kt = g.kclass >= 0 ? current_timer() : nullptr;
     const int tok = kt ? kt->begin(st) : -1;
 #define IF_G4(TB_, KC_) hipLaunchKernelGGL((k_gram4<T, TB_, KC_>), grid, block, 0, st, g, nsplit, rps, part)
-    if (kc == 32) {
+#define IF_GR(TB_, NIL_) \
+  hipLaunchKernelGGL((k_gram_rows<T, TB_, NIL_, 32>), dim3(nsplit, (g.ni + NIL_ - 1) / NIL_, g.ns), dim3(512), 0, st, g, \
+                     nsplit, rps, part)
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (g_gram_rows) {
+        // eight waves, row blocks round-robin: groups of three blocks when there are exactly three
+        const int nil = g.ni == 2 ? 2 : (g.ni == 3 ? 3 : 4);
+#define IF_GR_TB(TB_) \
+  if (nil == 2) IF_GR(TB_, 2); else if (nil == 3) IF_GR(TB_, 3); else IF_GR(TB_, 4);
+        switch (tb) {
+          case 1: IF_GR_TB(1) break;
+          case 2: IF_GR_TB(2) break;
+          case 3: IF_GR_TB(3) break;
+          case 4: IF_GR_TB(4) break;
+          default: IF_GR_TB(5) break;
+        }
+#undef IF_GR_TB
+        done = true;
+      }
+    }
+    if (done) {
+    } else if (kc == 32) {
       switch (tb) {
         case 1: IF_G4(1, 32); break;
         case 2: IF_G4(2, 32); break;
@@ -630,6 +752,7 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
       }
     }
 #undef IF_G4
+#undef IF_GR
     IF_HIP(hipGetLastError());
     if (kt) {
       const int nact = kt->count(g.active, g.ns);

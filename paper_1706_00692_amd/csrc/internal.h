@@ -271,13 +271,18 @@ void launch_to_T(hipStream_t st, int64_t count, const double* X, T* Y);
 // out[0] = max over columns b of ||G[:, b]|| / ||w_b|| (G = U^T W, nk x m0; gw = W^T W)
 void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, const double* gw, double* out);
 // gw -= C^T C (C: rows x m0): the Gram of a block after projecting out orthonormal directions
-void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw);
+// active (may be null): skipped when active[0] == 0
+void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw,
+                          const int* active = nullptr);
+// act[0..1] = the loss of orthogonality max_b ||G2[:, b]|| / ||w_b|| a first Gram-Schmidt pass
+// left against the local blocks exceeds eta (G2: rows x m0, gw = W^T W); act[2] = 1
+void launch_local_loss(hipStream_t st, int rows, int m0, const double* G2, const double* gw, double eta, int* act);
 // The second Gram-Schmidt pass folded into the Cholesky-QR product: from G2 (nl blocks m0 x m0,
 // FP64) and Tinv, Cf = [-G2_0 Tinv; ..; -G2_{nl-1} Tinv; Tinv], G2T = G2 in type T, and
-// Hm(lo + b, j) += G2_b.
+// Hm(lo + b, j) += G2_b; with need[0] == 0 (no second pass) only Cf[nl] = Tinv.
 template <class T>
 void launch_fold_second_pass(hipStream_t st, int m0, int nl, const double* G2, const T* Tinv, T* Cf, T* G2T,
-                             double* Hm, int ldh, int j, int lo);
+                             double* Hm, int ldh, int j, int lo, const int* need);
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm);
 // block column j of Hbar_s = z_s I~ + Hm for every active shift (per-shift complex H, capacity kcap)
 void launch_shift_column(hipStream_t st, int ns, int m0, int j, int ldh, int kcap, const double* z, const int* active,

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(128) void k_sketch_check_real(int nk, int m0, const
 // W1^T W1 - C^T C.  gw (m0 x m0) holds W1^T W1 on entry; C has `rows` rows of m0.
 // One workgroup per 16 x 16 tile of gw; rows staged through LDS 160 at a time.
 __global__ __launch_bounds__(256) void k_gram_downdate(int rows, int m0, const double* __restrict__ C,
-                                                       double* __restrict__ gw) {
+                                                       double* __restrict__ gw, const int* __restrict__ active) {
+  if (active != nullptr && active[0] == 0) return;
   // chunks of KR rows: the two-block case (2 x 80 rows) is one chunk, so its loads overlap
   constexpr int KR = 160;
   __shared__ double ca[KR][17], cb[KR][17];
@@ -139,6 +140,40 @@ __global__ void k_sum_y(int ns, int m0, int kcap, int jmax, const c2* __restrict
   Yr[idx] = (T)acc;
 }
 
+// Loss of orthogonality a first Gram-Schmidt pass left in W against the local blocks:
+// max over columns b of ||G2[:, b]|| / ||w_b|| with G2 = [V_lo..]^T W (rows x m0) and
+// ||w_b||^2 the diagonal of gw = W^T W.  act[0] = act[1] = (that loss > eta, or not finite): the
+// second pass is needed; act[2] = 1 (W's own term).  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_local_loss(int rows, int m0, const double* __restrict__ G2,
+                                                     const double* __restrict__ gw, double eta, int* __restrict__ act) {
+  // column b's sum of squares in 1024 / m0 row slices (coalesced: consecutive threads, consecutive
+  // columns), combined in LDS; the slice sums are added in a fixed order
+  __shared__ double part[1024];
+  __shared__ double colr[128];
+  const int t = threadIdx.x, ns = 1024 / m0;
+  const int b = t % m0, sl = t / m0;
+  double g2 = 0.0;
+  if (sl < ns)
+    for (int a = sl; a < rows; a += ns) g2 += G2[(int64_t)a * m0 + b] * G2[(int64_t)a * m0 + b];
+  part[t] = g2;
+  __syncthreads();
+  if (t < m0) {
+    double sum = 0.0;
+    for (int k = 0; k < ns; ++k) sum += part[k * m0 + t];
+    const double w2 = gw[(int64_t)t * m0 + t];
+    colr[t] = w2 > 0.0 ? sum / w2 : (sum > 0.0 ? INFINITY : 0.0);
+  }
+  __syncthreads();
+  if (t == 0) {
+    double mx = 0.0;
+    for (int c = 0; c < m0; ++c) mx = (colr[c] > mx || colr[c] != colr[c]) ? colr[c] : mx;
+    const int need = mx <= eta * eta ? 0 : 1;
+    act[0] = need;
+    act[1] = need;
+    act[2] = 1;
+  }
+}
+
 // The second Gram-Schmidt pass folded into the normalisation.  With G2 = [V_lo..V_{lo+nl-1}]^T W
 // the second pass's coefficients and R^{-1} = Tinv the Cholesky-QR factor of
 // (W - V G2)^T (W - V G2) = W^T W - G2^T G2, the next block is
@@ -150,7 +185,7 @@ __global__ void k_sum_y(int ns, int m0, int kcap, int jmax, const c2* __restrict
 template <class T>
 __global__ void k_fold_second_pass(int m0, int nl, const double* __restrict__ G2, const T* __restrict__ Tinv,
                                    T* __restrict__ Cf, T* __restrict__ G2T, double* __restrict__ Hm, int ldh, int j,
-                                   int lo) {
+                                   int lo, const int* __restrict__ need) {
   const int64_t mm = (int64_t)m0 * m0;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (nl + 1) * mm) return;
@@ -159,6 +194,7 @@ __global__ void k_fold_second_pass(int m0, int nl, const double* __restrict__ G2
     Cf[idx] = Tinv[a * m0 + q];
     return;
   }
+  if (need != nullptr && need[0] == 0) return;  // no second pass: W itself is normalised
   const double* g = G2 + b * mm + (int64_t)a * m0;
   double acc = 0.0;
   for (int k = 0; k <= q; ++k) acc += g[k] * (double)Tinv[k * m0 + q];
@@ -178,9 +214,9 @@ void launch_sketch_check_real(hipStream_t st, int nk, int m0, const double* G, c
   hipLaunchKernelGGL(k_sketch_check_real, dim3(1), dim3(128), 0, st, nk, m0, G, gw, out);
   IF_HIP(hipGetLastError());
 }
-void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw) {
+void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, double* gw, const int* active) {
   const int nt = (m0 + 15) / 16;
-  hipLaunchKernelGGL(k_gram_downdate, dim3(nt * nt), dim3(256), 0, st, rows, m0, C, gw);
+  hipLaunchKernelGGL(k_gram_downdate, dim3(nt * nt), dim3(256), 0, st, rows, m0, C, gw, active);
   IF_HIP(hipGetLastError());
 }
 void launch_subdiag_real(hipStream_t st, int m0, int j, int ldh, const cd* Racc, double* Hm) {
@@ -208,16 +244,21 @@ void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* 
 
 template <class T>
 void launch_fold_second_pass(hipStream_t st, int m0, int nl, const double* G2, const T* Tinv, T* Cf, T* G2T,
-                             double* Hm, int ldh, int j, int lo) {
+                             double* Hm, int ldh, int j, int lo, const int* need) {
   hipLaunchKernelGGL((k_fold_second_pass<T>), dim3(nblk((int64_t)(nl + 1) * m0 * m0)), dim3(256), 0, st, m0, nl, G2,
-                     Tinv, Cf, G2T, Hm, ldh, j, lo);
+                     Tinv, Cf, G2T, Hm, ldh, j, lo, need);
+  IF_HIP(hipGetLastError());
+}
+void launch_local_loss(hipStream_t st, int rows, int m0, const double* G2, const double* gw, double eta, int* act) {
+  IF_REQUIRE(m0 <= 128, "local loss: m0 > 128");
+  hipLaunchKernelGGL(k_local_loss, dim3(1), dim3(1024), 0, st, rows, m0, G2, gw, eta, act);
   IF_HIP(hipGetLastError());
 }
 
 template void launch_fold_second_pass<float>(hipStream_t, int, int, const double*, const float*, float*, float*,
-                                             double*, int, int, int);
+                                             double*, int, int, int, const int*);
 template void launch_fold_second_pass<double>(hipStream_t, int, int, const double*, const double*, double*, double*,
-                                              double*, int, int, int);
+                                              double*, int, int, int, const int*);
 template void launch_to_T<float>(hipStream_t, int64_t, const double*, float*);
 template void launch_to_T<double>(hipStream_t, int64_t, const double*, double*);
 template void launch_sum_y<float>(hipStream_t, int, int, int, int, const cd*, const double*, float*);

@@ -176,6 +176,9 @@ constexpr size_t kStageBytes = 64 * 1024;
 
 // Columns of the random sketch that estimates the shared basis' loss of orthogonality.
 constexpr int kSketch = 16;
+// Workgroup slots (of the multi-block Gram kernel's two per compute unit) that the least squares
+// kernels on the side stream take while the basis kernels run
+constexpr int kLsqSlots = 48;
 
 
 struct Layout {
@@ -986,6 +989,9 @@ struct Engine::Impl {
           // W^T W in one sweep over W: items 0..nl of [V_{j-1}, V_j, W]^T W
           GramArgs g3{n, m0, m0, 1, nl + 1, Vb + (int64_t)lo * bs, m0, 0, bs, t1, m0, 0, 0, nullptr, gred.as<double>()};
           g3.A_last = t1;
+          // the least squares kernels of the previous step run beside it: its row split leaves
+          // their workgroup slots free
+          g3.reserve = kLsqSlots;
           launch_gram<T>(st, g3, gpart.p, gpart.bytes);
           if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwf, d_loss);
           // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass

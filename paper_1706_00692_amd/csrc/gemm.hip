@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
 // rows, so three blocks keep every wave busy and a wave holds at most ceil(NIL TB / 8) x TB
 // MFMA tiles.  The B tile and the nil A tiles of a K chunk are staged once for the workgroup.
 // grid: x = row split, y = group of NIL blocks, z = shift.
-template <class T, int TB, int NIL, int KC>
+template <class T, int TB, int NIL, int KC, bool DB>
 __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64_t rows_per_split,
                                                    T* __restrict__ partial) {
   using V = typename V16T<T>::t;
@@ -321,7 +321,8 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
   constexpr int NT = NIL + 1;       // staged tiles: the A blocks, then B
   constexpr int PER = (NT * NV + 511) / 512;
   constexpr int MAXR = (NIL * TB + 7) / 8;
-  __shared__ T sT[NT * KC * LD];
+  constexpr int NBUF = DB ? 2 : 1;  // DB: two LDS buffers, the next chunk stored while this one computes
+  __shared__ T sT[NBUF * NT * KC * LD];
   const int s = blockIdx.z;
   if (g.active != nullptr && g.active[s] == 0) return;
   const int i0 = blockIdx.y * NIL;
@@ -357,20 +358,19 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
       }
     }
   };
-  if (r0 < r1) fetch(r0);
-  for (int64_t rc = r0; rc < r1; rc += KC) {
+  auto stage = [&](T* buf) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + 512 * u;
       const int t = e / NV, v = e % NV;
       if (t < NT) {
         const int r = v / (TP / VN), c = (v % (TP / VN)) * VN;
-        put16<T>(sT + (t * KC + r) * LD + c, pre[u]);
+        put16<T>(buf + (t * KC + r) * LD + c, pre[u]);
       }
     }
-    __syncthreads();
-    if (rc + KC < r1) fetch(rc + KC);
-    const T* sB = sT + NIL * KC * LD;
+  };
+  auto compute = [&](const T* buf) {
+    const T* sB = buf + NIL * KC * LD;
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T bf[TB];
@@ -381,13 +381,36 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
         const int rb = wave + 8 * r;
         if (rb < nil * TB) {
           const int blk = rb / TB, lr = rb % TB;
-          const T af = sT[(blk * KC + kk + lk) * LD + lr * 16 + li];
+          const T af = buf[(blk * KC + kk + lk) * LD + lr * 16 + li];
 #pragma unroll
           for (int b = 0; b < TB; ++b) acc[r][b] = Mfma<T>::mma(af, bf[b], acc[r][b]);
         }
       }
     }
+  };
+  if (r0 < r1) fetch(r0);
+  if constexpr (DB) {
+    // one barrier per chunk: chunk c computes from buffer c & 1 while the loads of chunk c + 1
+    // are in flight, then stages them into the other buffer (last read in chunk c - 1)
+    if (r0 < r1) stage(sT);
     __syncthreads();
+    int cur = 0;
+    for (int64_t rc = r0; rc < r1; rc += KC) {
+      const bool more = rc + KC < r1;
+      if (more) fetch(rc + KC);
+      compute(sT + cur * NT * KC * LD);
+      if (more) stage(sT + (cur ^ 1) * NT * KC * LD);
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    for (int64_t rc = r0; rc < r1; rc += KC) {
+      stage(sT);
+      __syncthreads();
+      if (rc + KC < r1) fetch(rc + KC);
+      compute(sT);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
@@ -701,7 +724,10 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     const int tb = g.PW / 16;
     const int groups = (g.ni + 3) / 4;
     const int items = g.ns * g.ni;
-    const int nsplit = gram_nsplit(g.n, g.ns * groups, 1, gram4_capacity<T>(tb), 512);
+    int nsplit = gram_nsplit(g.n, g.ns * groups, 1, gram4_capacity<T>(tb), 512);
+    // with slots held by concurrent work, one round on the rest (a second, nearly empty round
+    // would cost as much as the first)
+    if (g.reserve > 0) nsplit = std::min(nsplit, std::max(1, gram4_capacity<T>(tb) / (g.ns * groups) - g.reserve));
     IF_REQUIRE((size_t)items * nsplit * g.PW * g.QW * sizeof(T) <= partial_bytes, "gram: partial buffer too small");
     // K chunk (rows per staged tile): 32 (measured fastest, two waves per SIMD still fit) or 16
     const int kc = g_gram4_kc == 16 ? 16 : 32;
@@ -712,9 +738,9 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     KernelTimer* kt = g.kclass >= 0 ? current_timer() : nullptr;
     const int tok = kt ? kt->begin(st) : -1;
 #define IF_G4(TB_, KC_) hipLaunchKernelGGL((k_gram4<T, TB_, KC_>), grid, block, 0, st, g, nsplit, rps, part)
-#define IF_GR(TB_, NIL_) \
-  hipLaunchKernelGGL((k_gram_rows<T, TB_, NIL_, 32>), dim3(nsplit, (g.ni + NIL_ - 1) / NIL_, g.ns), dim3(512), 0, st, g, \
-                     nsplit, rps, part)
+#define IF_GR(TB_, NIL_)                                                                                        \
+  hipLaunchKernelGGL((k_gram_rows<T, TB_, NIL_, 32, (NIL_ < 4)>), dim3(nsplit, (g.ni + NIL_ - 1) / NIL_, g.ns),   \
+                     dim3(512), 0, st, g, nsplit, rps, part)
     bool done = false;
     if constexpr (sizeof(T) == 4) {
       if (g_gram_rows) {

@@ -174,6 +174,7 @@ struct GramArgs {
   int tb_cap = 0;        // > 0: largest square tile, in 16-column blocks (narrow-by-wide products)
   GramCombine cmb;       // optional (cmb.Hm != null): Hm and Hr written by the reduction
   const void* A_last = nullptr;  // optional: block ni - 1 of each shift read from A_last + s * a_s instead
+  int reserve = 0;  // multi-block kernel: workgroup slots left to concurrent work when sizing the row split
 };
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes);

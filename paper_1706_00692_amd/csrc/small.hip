@@ -347,15 +347,28 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     const bool dd = !(g > dead_thr);
     dead[a] = dd ? 1 : 0;
     dsc[a] = dd ? 1.0 : sqrt(g);
+    dinv[a] = 1.0 / dsc[a];  // scaling reciprocals (reset to the Cholesky pivots' below)
   }
   __syncthreads();
-  for (int idx = tid; idx < m0 * m0; idx += nth) {
-    const int a = idx / m0, b = idx % m0;
-    double g;
-    if (dead[a] || dead[b]) g = a == b ? 1.0 : 0.0;
-    else g = G[idx] / (dsc[a] * dsc[b]) + (a == b ? shift_rel : 0.0);
-    L[a * ldl + b] = g;
-    if (accumulate) Rs[idx] = Racc[idx].x;
+  // eight loads in flight per thread, then the scaling (by reciprocals of the column norms)
+  for (int i0 = tid; i0 < m0 * m0; i0 += 8 * nth) {
+    double gv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = i0 + u * nth;
+      gv[u] = idx < m0 * m0 ? G[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = i0 + u * nth;
+      if (idx >= m0 * m0) break;
+      const int a = idx / m0, b = idx % m0;
+      double g;
+      if (dead[a] || dead[b]) g = a == b ? 1.0 : 0.0;
+      else g = gv[u] * (dinv[a] * dinv[b]) + (a == b ? shift_rel : 0.0);
+      L[a * ldl + b] = g;
+      if (accumulate) Rs[idx] = Racc[idx].x;
+    }
   }
   __syncthreads();
   // ---- 2. blocked Cholesky (lower triangle of L)
@@ -434,8 +447,7 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
   }
   // ---- 3. R factor (global writes; the previous R was staged in LDS)
   RR_MARK(18);
-  for (int idx = tid; idx < m0 * m0; idx += nth) {
-    const int a = idx / m0, b = idx % m0;
+  auto rfac = [&](int a, int b) {
     double v = 0.0;
     if (b >= a && !dead[a]) {
       if (accumulate)
@@ -443,13 +455,23 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       else
         v = dsc[b] * L[b * ldl + a];
     }
+    return v;
+  };
+  // R row-major into Racc and (transposed) block column jstep + 1 of Hm: consecutive threads,
+  // consecutive b
+  for (int idx = tid; idx < m0 * m0; idx += nth) {
+    const int a = idx / m0, b = idx % m0;
+    const double v = rfac(a, b);
     Racc[idx] = make_double2(v, 0.0);
-    if (lanczos_out) {
+    if (lanczos_out && Hr_next != nullptr) Hm[(int64_t)((jstep + 1) * m0 + a) * ldh + jstep * m0 + b] = v;
+  }
+  // R into block column jstep of Hm (column-major) and Hr_next: consecutive threads, consecutive a
+  if (lanczos_out) {
+    for (int idx = tid; idx < m0 * m0; idx += nth) {
+      const int b = idx / m0, a = idx % m0;
+      const double v = rfac(a, b);
       Hm[(int64_t)(jstep * m0 + b) * ldh + (jstep + 1) * m0 + a] = v;
-      if (Hr_next != nullptr) {
-        Hm[(int64_t)((jstep + 1) * m0 + a) * ldh + jstep * m0 + b] = v;
-        Hr_next[b * m0 + a] = (T)v;
-      }
+      if (Hr_next != nullptr) Hr_next[b * m0 + a] = (T)v;
     }
   }
   __syncthreads();

@@ -87,8 +87,9 @@ typedef struct {
   int half;                /* EXPLICIT: 1 if the nodes are the upper half of a conjugate-symmetric rule */
 } ifeast_contour;
 
-enum { IFEAST_PREC_FP64 = 0,   /* complex FP64 inner solves */
-       IFEAST_PREC_MIXED = 1 };/* complex FP32 inner solves, FP64 outer iteration */
+enum { IFEAST_PREC_FP64 = 0,   /* FP64 inner solves and outer iteration */
+       IFEAST_PREC_MIXED = 1 };/* FP32 inner solves (the shared basis: one real FP32 Krylov basis; the
+                                  per-shift basis: complex FP32 blocks), FP64 outer iteration */
 enum { IFEAST_PROBLEM_SYMMETRIC = 0, /* A symmetric, B SPD or NULL: HALF or EXPLICIT contours */
        IFEAST_PROBLEM_GENERAL = 1 };  /* A nonsymmetric, B NULL, a CIRCLE contour with c_im = 0 and an
                                          even nc (the rule is symmetric about the real axis, so the

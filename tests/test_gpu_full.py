@@ -1,9 +1,10 @@
 """Full-size parity: the 64^3 Laplacian + potential solve (m0 80, 8 Gauss-Legendre nodes on the
-upper half circle, block GMRES(8)) against the stored oracle spectrum of tests/golden.
+upper half circle, k = 8) against the stored oracle spectrum of tests/golden.
 
-The mixed path (complex FP32 inner solves, FP64 outer iteration) must find exactly the 54
-eigenvalues inside the interval, each within 1e-10 relative of the oracle's, with residual
-<= 1e-9.  About two and a half minutes on one MI355X.
+The mixed path (inner solves by block GMRES on one real FP32 Krylov basis shared by the 8 shifts,
+FP64 outer iteration) must find exactly the 54 eigenvalues inside the interval, each within 1e-10
+relative of the oracle's, with residual <= 1e-9.  The solve takes well under a second on one
+MI355X; the first import and the workspace allocation dominate the test's time.
 """
 
 import os

@@ -1111,7 +1111,7 @@ struct Engine::Impl {
     IF_HIP(hipStreamWaitEvent(st, ev_lsq[0], 0));
     shared_steps = jdone;
     single_steps += d2h_ints(d_cnt, 1)[0];
-    launch_lsq_finish(st, la);
+    launch_lsq_finish(st, la, jdone);
     launch_sum_y<T>(st, ns, m0, K, jdone, y.as<cd>(), wsD.as<double>(), Yq.as<T>());
     ApplyArgs aq{n, m0, m0, 1, jdone, jdone, Vb, m0, 0, 0, bs, Yq.p, 0, Qd, m0, 0, 1.0, 1.0, nullptr, nullptr,
                  KC_QACC};

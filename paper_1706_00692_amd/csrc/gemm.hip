@@ -450,9 +450,9 @@ inline int gram_nsplit(int64_t n, int items, int tiles, int cap, int64_t min_row
 }
 
 // ------------------------------------------------------------------ apply
-// O_item = beta O_item + alpha sum_b A_b Bm_b.  grid: x = 128-row tile (XCD
+// O_item = beta O_item + alpha sum_b A_b Bm_b.  grid: x = 64 RB-row tile (XCD
 // renumbered), y = output column tile, z = item.  Wave w owns rows
-// [32w, 32w+32) of the tile (two MFMA row blocks) and TBQ column blocks.
+// [16 RB w, 16 RB (w+1)) of the tile (RB MFMA row blocks) and TBQ column blocks.
 template <class T> struct ApplyCfg { static constexpr int KC = 32; };
 template <> struct ApplyCfg<double> { static constexpr int KC = 16; };
 
@@ -840,10 +840,14 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
   IF_HIP(hipGetLastError());
 }
 
-// Row blocks per wave and K chunk of the FP32 update kernel (FP64 uses 2 x 16); -1 selects the
-// built-in choice measured fastest: one row block per wave for 160-column outputs (the most
-// resident waves), two with a 16-row K chunk for 80-column outputs.
+// Row blocks per wave and K chunk of the FP32 update kernel (FP64: g_apply_rb64); -1 selects the
+// built-in choice measured fastest: one row block per wave for 144- and 160-column tiles (the most
+// resident waves), two row blocks with a 32-row K chunk for 96- to 128-column tiles (one row block
+// there is unrolled into more than 256 registers and runs one wave per SIMD: 14x slower at 128
+// columns), two with a 16-row K chunk up to 80 columns.
 int g_apply_variant = -1;
+// Row blocks per wave of the FP64 update kernel (1 or 2); <= 0 selects the built-in choice (1).
+int g_apply_rb64 = 0;
 
 template <class T, class TO, int RB, int KC>
 void launch_apply_rt(hipStream_t st, const ApplyArgs& a, int tbq, int ntq, KernelTimer* kt, int& tok) {
@@ -878,7 +882,7 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   constexpr int KC0 = ApplyCfg<T>::KC;
   if (sizeof(T) == 4) {
     int var = g_apply_variant;
-    if (var < 0) var = tbq >= 8 ? 3 : 6;
+    if (var < 0) var = tbq >= 9 ? 3 : (tbq >= 6 ? 0 : 6);
     switch (var) {
       case 0: launch_apply_rt<T, TO, 2, 32>(st, a, tbq, ntq, kt, tok); break;
       case 1: launch_apply_rt<T, TO, 1, 64>(st, a, tbq, ntq, kt, tok); break;
@@ -889,7 +893,15 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
       default: launch_apply_rt<T, TO, 2, 16>(st, a, tbq, ntq, kt, tok); break;
     }
   } else {
-    launch_apply_rt<T, TO, 2, KC0>(st, a, tbq, ntq, kt, tok);
+    // FP64: one row block per wave (measured faster than two at every tile width: 7 % at 80
+    // columns, 15 % at 160, 35 % at 128 of a complex 256-column output, where two hold more than
+    // 256 registers)
+    int rb = g_apply_rb64;
+    if (rb < 1) rb = 1;
+    if (rb == 1)
+      launch_apply_rt<T, TO, 1, KC0>(st, a, tbq, ntq, kt, tok);
+    else
+      launch_apply_rt<T, TO, 2, KC0>(st, a, tbq, ntq, kt, tok);
   }
   IF_HIP(hipGetLastError());
   if (kt) {

@@ -296,7 +296,8 @@ void launch_sum_y(hipStream_t st, int ns, int m0, int kcap, int jmax, const cd* 
 
 void launch_lsq_init(hipStream_t st, const LsqArgs& a, const cd* S /*ns x m0 x m0 row-major*/);
 void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j);
-void launch_lsq_finish(hipStream_t st, const LsqArgs& a);
+// jmax: host-known bound on the shifts' block iterations (-1: unknown)
+void launch_lsq_finish(hipStream_t st, const LsqArgs& a, int jmax = -1);
 // Real-ified coefficient blocks from y and u for the tall-skinny products:
 //   Yq[s][b] (2m0 x m0, T): Q += Re(V_b (wfac_s y_b))  (wfac = 2w for HALF contours, w otherwise)
 //   Uc[s][b] (2m0 x 2m0, T): T1_s = sum_b V_b u_b

@@ -845,6 +845,8 @@ __global__ void k_lsq_stop(LsqArgs a, int j) {
 // (top) and (i+1) m0 + 16 q + l (bottom) in lane l's slot q < SH = ceil(m0/16), the next
 // block's rows loading while the current block applies.  The reflectors pass through LDS in
 // chunks of rc columns (rc * 2 m0 <= kChunk), the next chunk's loads in flight meanwhile.
+// s_waitcnt operand (gfx9 encoding): vector memory count 0, the other counters unconstrained
+constexpr int kVmcntZero = 0x0F70;
 constexpr int kChunk = 2560;  // complex entries of one reflector chunk (40 KiB)
 constexpr int kChunkPer = kChunk / 256;
 
@@ -879,6 +881,9 @@ __global__ __launch_bounds__(256) void k_lsq_reflect(LsqArgs a, int j, int rc) {
   c2 top[SH], bot[SH], nxt[SH];
   load_rows(i0 * m0, top);
   load_rows((i0 + 1) * m0, bot);
+  // the window is complete before the loop: otherwise the reflector loop, unable to tell these
+  // loads from the chunk prefetches, waits on every prefetch at its first reflector
+  __builtin_amdgcn_s_waitcnt(kVmcntZero);
   if (i0 + 1 < i1) load_rows((i0 + 2) * m0, nxt);
   const int nch = (m0 + rc - 1) / rc, total = (i1 - i0) * nch;
   c2 pre[kChunkPer];
@@ -1230,6 +1235,151 @@ __global__ __launch_bounds__(256) void k_lsq_finish_band(LsqArgs a) {
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
+  }
+}
+
+// y = R^{-1} g_top for a full upper triangular R (the non-Hermitian Hessenberg keeps every block
+// above the diagonal), blocked and spread over the device, from the last block row up.  Per block
+// row b two launches: SOLVE takes y_{b+1} out of block row b (x_b -= R(b, b+1) y_{b+1}) and solves
+// R_bb y_b = x_b; the other takes y_{b+1} out of every block row rb < b.  Each workgroup handles one
+// block row, one shift and 16 right-hand sides (q): wave w holds right-hand sides 16 q + 4 w .. + 3,
+// lane l the rows l and l + 64 of the block in registers.  The products run on LDS chunks of 16
+// columns of R and 16 rows of y_{b+1}; the solve on R_bb's packed upper triangle in LDS.  The
+// working x lives in y itself (k_lsq_bsub_init copies g_top there).  grid (1 or b, ns, m0 / 16).
+constexpr int kBsubRows = 2;  // row slots per lane: m0 <= 128 rows per block
+
+__global__ void k_lsq_bsub_init(LsqArgs a) {
+  const int s = blockIdx.x, col = blockIdx.y;
+  const int J = a.iters[s];
+  const LsqView v = lsq_view(a, s);
+  const int n = J * a.m0, ldy = a.k * a.m0;
+  const c2* gc = v.g + (int64_t)col * a.ldh;
+  c2* yc = v.y + (int64_t)col * ldy;
+  for (int r = threadIdx.x; r < ldy; r += blockDim.x) yc[r] = r < n ? gc[r] : cmk(0.0, 0.0);
+}
+
+template <bool SOLVE>
+__global__ __launch_bounds__(256) void k_lsq_bsub(LsqArgs a, int b) {
+  extern __shared__ c2 bs_lds[];
+  const int rb = SOLVE ? b : blockIdx.x, s = blockIdx.y, q = blockIdx.z;
+  const int J = a.iters[s];
+  if (b >= J || (!SOLVE && b + 1 >= J)) return;  // this shift's solve starts lower down
+  const LsqView v = lsq_view(a, s);
+  const int m0 = a.m0, ldh = a.ldh, ldy = a.k * m0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  c2* Rc = bs_lds;            // 16 x m0: R(rows of block rb, 16 columns of block b + 1)
+  c2* Yc = Rc + 16 * m0;      // 16 x 16: the matching rows of y_{b+1}, this group's right-hand sides
+  c2* Rp = Yc + 16 * 16;      // packed upper triangle of R_bb, column c at c (c + 1) / 2
+  const int r0 = rb * m0;
+  const int rhs0 = 16 * q + 4 * wave;
+  c2 x[kBsubRows][4];
+#pragma unroll
+  for (int t = 0; t < kBsubRows; ++t) {
+    const int r = lane + 64 * t;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[t][u] = r < m0 ? v.y[(int64_t)(rhs0 + u) * ldy + r0 + r] : cmk(0.0, 0.0);
+  }
+  if (b + 1 < J) {
+    // x -= R(rb, b+1) y_{b+1}, 16 columns at a time
+    const int c0 = (b + 1) * m0;
+    c2 acc[kBsubRows][4];
+#pragma unroll
+    for (int t = 0; t < kBsubRows; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][u] = cmk(0.0, 0.0);
+    for (int kc = 0; kc < m0; kc += 16) {
+      __syncthreads();
+      for (int idx = tid; idx < 16 * m0; idx += 256) {
+        const int kk = idx / m0, r = idx % m0;
+        Rc[idx] = v.H[(int64_t)(c0 + kc + kk) * ldh + r0 + r];
+      }
+      {
+        const int kk = tid & 15, c = tid >> 4;
+        Yc[kk * 16 + c] = v.y[(int64_t)(16 * q + c) * ldy + c0 + kc + kk];
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < 16; ++kk) {
+        c2 yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yv[u] = Yc[kk * 16 + 4 * wave + u];
+#pragma unroll
+        for (int t = 0; t < kBsubRows; ++t) {
+          const int r = lane + 64 * t;
+          const c2 rv = r < m0 ? Rc[kk * m0 + r] : cmk(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[t][u] = cadd(acc[t][u], cmul(rv, yv[u]));
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kBsubRows; ++t)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[t][u] = csub(x[t][u], acc[t][u]);
+  }
+  if (!SOLVE) {
+#pragma unroll
+    for (int t = 0; t < kBsubRows; ++t) {
+      const int r = lane + 64 * t;
+      if (r < m0)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v.y[(int64_t)(rhs0 + u) * ldy + r0 + r] = x[t][u];
+    }
+    return;
+  }
+  // block row b: R_bb y_b = x_b.  R_bb's upper triangle to LDS; each lane keeps the reciprocal of
+  // its rows' diagonal (0 for a deflated column)
+  for (int idx = tid; idx < m0 * (m0 + 1) / 2; idx += 256) {
+    int c = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while (c * (c + 1) / 2 > idx) --c;
+    while ((c + 1) * (c + 2) / 2 <= idx) ++c;
+    const int r = idx - c * (c + 1) / 2;
+    Rp[idx] = v.H[(int64_t)(r0 + c) * ldh + r0 + r];
+  }
+  c2 rinv[kBsubRows];
+#pragma unroll
+  for (int t = 0; t < kBsubRows; ++t) {
+    const int r = lane + 64 * t;
+    const c2 d = r < m0 ? v.H[(int64_t)(r0 + r) * ldh + r0 + r] : cmk(0.0, 0.0);
+    rinv[t] = cabs2(d) > 1e-300 ? cdiv(cmk(1.0, 0.0), d) : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  // column-oriented back substitution on registers: row c's solution comes from its lane, the
+  // rows above take R(r, c) y_c
+  for (int c = m0 - 1; c >= 0; --c) {
+    const int slot = c >> 6, owner = c & 63;
+    const c2* col = Rp + c * (c + 1) / 2;
+    c2 rv[kBsubRows];
+#pragma unroll
+    for (int t = 0; t < kBsubRows; ++t) {
+      const int r = lane + 64 * t;
+      rv[t] = r < c ? col[r] : cmk(0.0, 0.0);
+    }
+    c2 yc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c2 mine = cmk(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < kBsubRows; ++t)
+        if (t == slot) mine = cmul(x[t][u], rinv[t]);
+      yc[u] = cmk(lane_bcast(mine.x, owner), lane_bcast(mine.y, owner));
+    }
+#pragma unroll
+    for (int t = 0; t < kBsubRows; ++t) {
+      const int r = lane + 64 * t;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (r < c) x[t][u] = csub(x[t][u], cmul(rv[t], yc[u]));
+        if (r == c) x[t][u] = yc[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kBsubRows; ++t) {
+    const int r = lane + 64 * t;
+    if (r < m0)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v.y[(int64_t)(rhs0 + u) * ldy + r0 + r] = x[t][u];
   }
 }
 
@@ -1825,12 +1975,29 @@ void launch_lsq_step(hipStream_t st, const LsqArgs& a, int j) {
   }
   IF_HIP(hipGetLastError());
 }
-void launch_lsq_finish(hipStream_t st, const LsqArgs& a) {
+void launch_lsq_finish(hipStream_t st, const LsqArgs& a, int jmax) {
   static int max_lds = -1;
   if (max_lds < 0) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) max_lds = 0;
+  }
+  if (a.band == 0 && !a.need_u && jmax > 0 && a.m0 % 16 == 0 && a.m0 <= 64 * kBsubRows) {
+    // full R: the blocked back substitution, one pair of launches per block row
+    const size_t lds_upd = ((size_t)16 * a.m0 + 256) * sizeof(c2);
+    const size_t lds_solve = lds_upd + (size_t)a.m0 * (a.m0 + 1) / 2 * sizeof(c2);
+    if ((int64_t)lds_solve + 1024 <= (int64_t)max_lds) {
+      if (lds_solve > 64 * 1024)
+        IF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lsq_bsub<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve));
+      hipLaunchKernelGGL(k_lsq_bsub_init, dim3(a.ns, a.m0), dim3(256), 0, st, a);
+      for (int b = jmax - 1; b >= 0; --b) {
+        hipLaunchKernelGGL(k_lsq_bsub<true>, dim3(1, a.ns, a.m0 / 16), dim3(256), lds_solve, st, a, b);
+        if (b > 0) hipLaunchKernelGGL(k_lsq_bsub<false>, dim3(b, a.ns, a.m0 / 16), dim3(256), lds_upd, st, a, b);
+      }
+      IF_HIP(hipGetLastError());
+      return;
+    }
   }
   if (a.band > 0 && !a.need_u && a.m0 <= 128) {
     const size_t lds = ((size_t)a.m0 * (a.m0 + 1) / 2 + (size_t)4 * (a.band + 2) * a.m0) * sizeof(c2);

@@ -171,36 +171,37 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
 }
 
 template <class T>
-__global__ void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni, const int* __restrict__ active,
-                              const T* __restrict__ partial, double* __restrict__ G, GramCombine cmb) {
-  // 8 consecutive lanes share one output element: each sums every 8th split, then the
-  // lanes' sums are added with shuffles (the order is fixed, so results are reproducible)
+__global__ __launch_bounds__(256) void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni,
+                                                     const int* __restrict__ active, const T* __restrict__ partial,
+                                                     double* __restrict__ G, GramCombine cmb) {
+  // 64 consecutive output elements per workgroup, one per lane, so every load of a wave reads 64
+  // consecutive partial sums; the four waves take every fourth split and their sums are added in
+  // wave order (a fixed order: results are reproducible)
+  __shared__ double red[4][64];
   const int64_t per_item = (int64_t)PW * QW;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t idx = gid >> 3;
-  const int part = (int)(gid & 7);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
   const bool live = idx < per_item * items;
   const int item = live ? (int)(idx / per_item) : 0;
   const bool on = live && !(active != nullptr && active[item / ni] == 0);
   double sum = 0.0;
   if (on) {
     const T* p = partial + (int64_t)item * nsplit * per_item + idx % per_item;
-    // unrolled so that sixteen loads are in flight before the (in-order) additions
-#pragma unroll 16
-    for (int sp = part; sp < nsplit; sp += 8) sum += (double)p[(int64_t)sp * per_item];
+    // unrolled so that eight loads are in flight before the (in-order) additions
+#pragma unroll 8
+    for (int sp = wave; sp < nsplit; sp += 4) sum += (double)p[(int64_t)sp * per_item];
   }
-  sum += __shfl_xor(sum, 1);
-  sum += __shfl_xor(sum, 2);
-  sum += __shfl_xor(sum, 4);
-  if (on && part == 0) {
-    G[idx] = sum;
-    if (cmb.Hm != nullptr) {
-      // block column j of Hm (block rows i0 + item) and the update factors, as k_combine_real
-      const int a = (int)((idx % per_item) / QW), b = (int)(idx % QW);
-      double* h = cmb.Hm + (int64_t)(cmb.j * QW + b) * cmb.ldh + (int64_t)(cmb.i0 + item) * PW + a;
-      *h = cmb.accumulate ? *h + sum : sum;
-      static_cast<T*>(cmb.Hr)[idx] = (T)sum;
-    }
+  red[wave][lane] = sum;
+  __syncthreads();
+  if (wave != 0 || !on) return;
+  sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  G[idx] = sum;
+  if (cmb.Hm != nullptr) {
+    // block column j of Hm (block rows i0 + item) and the update factors, as k_combine_real
+    const int a = (int)((idx % per_item) / QW), b = (int)(idx % QW);
+    double* h = cmb.Hm + (int64_t)(cmb.j * QW + b) * cmb.ldh + (int64_t)(cmb.i0 + item) * PW + a;
+    *h = cmb.accumulate ? *h + sum : sum;
+    static_cast<T*>(cmb.Hr)[idx] = (T)sum;
   }
 }
 
@@ -787,8 +788,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
       const double rb = ((g.A == g.B && g.ni == 1) || g.A_last == g.B) ? 0.0 : (double)g.n * g.QW * sizeof(T) * nact;
       kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, (double)g.n * g.PW * sizeof(T) * eff + rb);
     }
-    const int64_t total = (int64_t)items * g.PW * g.QW * 8;
-    hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
+    const int64_t total = (int64_t)items * g.PW * g.QW;
+    hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, items, nsplit,
                        g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
     IF_HIP(hipGetLastError());
     return;
@@ -834,8 +835,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
                           : (double)g.n * g.QW * sizeof(T) * (g.b_i == 0 ? nact : eff);
     kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, ra + rb);
   }
-  const int64_t total = (int64_t)items * g.PW * g.QW * 8;
-  hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, items, nsplit,
+  const int64_t total = (int64_t)items * g.PW * g.QW;
+  hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, items, nsplit,
                      g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
   IF_HIP(hipGetLastError());
 }

@@ -250,6 +250,28 @@ def test_filter_parity_shared_wide(ctx, torch_cuda, m0):
     assert err <= 1e-9, err
 
 
+@pytest.mark.parametrize("m0", [64, 80])
+def test_filter_parity_shared_mixed(ctx, torch_cuda, m0):
+    """Mixed precision on the shared basis at the benchmark's block widths (m0 = 64, 80): 8 Arnoldi
+    steps on a 10^3 Laplacian + potential, so steps 2..7 take the Lanczos path (sketched estimate,
+    local second pass folded into the normalisation, one-pass Cholesky-QR when certified), against
+    per-shift block GMRES in FP64; the FP32 part is the correction Q - X rho_hat(Lambda)."""
+    import paper_1706_00692_amd as pk
+    from oracle.quadrature import rho_hat
+
+    N = 10
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    prob = W.config2_small(N=N, m0=m0, emin=0.5 * (lam_all[5] + lam_all[6]), emax=0.5 * (lam_all[20] + lam_all[21]))
+    lam, X, R, r = _first_iterate(prob)
+    want = _oracle_filter(prob, lam, X, R, 4, 2, restarted=False)
+    got, iters = _gpu_filter(ctx, torch_cuda, prob, lam, X, R, pk.PREC_MIXED, 4, 2, 0.0, pk.BASIS_SHARED)
+    assert list(iters) == [8] * 8
+    z, w, half = contour_nodes(prob.contour)
+    base = X * rho_hat(lam, z, w, half)[None, :]
+    err = np.abs(got - want).max() / np.abs(want - base).max()
+    assert err <= 1e-4, err
+
+
 def test_solve_shared_m0_128_mixed(ctx):
     """A full mixed-precision solve with m0 = 128 on the shared basis (the widest block the
     serving mix draws), against the dense spectrum of a 12^3 Laplacian + potential."""

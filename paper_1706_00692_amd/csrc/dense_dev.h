@@ -72,6 +72,14 @@ __device__ inline c2 row16_csum(c2 v) { return cmk(row16_sum(v.x), row16_sum(v.y
 
 // Lane l's value of v in every lane (l wave-uniform; the whole wave active): two scalar reads
 // of the register halves instead of a lane permute through the LDS unit.
+// Workgroup barrier that orders LDS accesses only: global stores issued before it need not have
+// completed (__syncthreads would wait for them).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ inline double lane_bcast(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, l);

@@ -169,6 +169,10 @@ void validate_params(const ifeast_params& p, const ifeast_contour& C, int64_t n)
 }
 
 // ------------------------------------------------------------ workspace
+// Workgroup slots (of the multi-block Gram kernel's two per compute unit) that the least squares
+// kernels on the side stream take while the basis kernels run
+int g_lsq_slots = 48;
+
 namespace {
 
 // Pinned staging bytes for the small uploads of one shared inner solve.
@@ -176,9 +180,6 @@ constexpr size_t kStageBytes = 64 * 1024;
 
 // Columns of the random sketch that estimates the shared basis' loss of orthogonality.
 constexpr int kSketch = 16;
-// Workgroup slots (of the multi-block Gram kernel's two per compute unit) that the least squares
-// kernels on the side stream take while the basis kernels run
-constexpr int kLsqSlots = 48;
 
 
 struct Layout {
@@ -991,7 +992,7 @@ struct Engine::Impl {
           g3.A_last = t1;
           // the least squares kernels of the previous step run beside it: its row split leaves
           // their workgroup slots free
-          g3.reserve = kLsqSlots;
+          g3.reserve = g_lsq_slots;
           launch_gram<T>(st, g3, gpart.p, gpart.bytes);
           if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwf, d_loss);
           // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass

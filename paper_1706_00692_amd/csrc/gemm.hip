@@ -310,6 +310,8 @@ __global__ __launch_bounds__(256, 2) void k_gram4(GramArgs g, int nsplit, int64_
 // to the waves (wave w: row blocks w, w + 8, ..), each wave taking all TB column blocks of its
 // rows, so three blocks keep every wave busy and a wave holds at most ceil(NIL TB / 8) x TB
 // MFMA tiles.  The B tile and the nil A tiles of a K chunk are staged once for the workgroup.
+// NIL = 1 (one block against B) deals the TB x TB output tiles round-robin to the waves
+// instead, so that all eight waves compute.
 // grid: x = row split, y = group of NIL blocks, z = shift.
 template <class T, int TB, int NIL, int KC, bool DB>
 __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64_t rows_per_split,
@@ -337,11 +339,16 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
   const T* const Ab = static_cast<const T*>(g.A) + s * g.a_s;
   const T* const Al = g.A_last != nullptr ? static_cast<const T*>(g.A_last) + s * g.a_s : nullptr;
   const T* const Bb = static_cast<const T*>(g.B) + s * g.b_s;
-  typename Mfma<T>::acc acc[MAXR][TB];
+  constexpr bool TILES = NIL == 1;
+  constexpr int MAXT = (TB * TB + 7) / 8;  // tiles per wave (NIL = 1)
+  typename Mfma<T>::acc acc[TILES ? 1 : MAXR][TB];
+  typename Mfma<T>::acc acct[TILES ? MAXT : 1];
 #pragma unroll
-  for (int r = 0; r < MAXR; ++r)
+  for (int r = 0; r < (TILES ? 1 : MAXR); ++r)
 #pragma unroll
     for (int b = 0; b < TB; ++b) acc[r][b] = Mfma<T>::zero();
+#pragma unroll
+  for (int t = 0; t < (TILES ? MAXT : 1); ++t) acct[t] = Mfma<T>::zero();
   V pre[PER];
   auto fetch = [&](int64_t rc) {
 #pragma unroll
@@ -372,6 +379,22 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
   };
   auto compute = [&](const T* buf) {
     const T* sB = buf + NIL * KC * LD;
+    if constexpr (TILES) {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+          const int tile = wave + 8 * t;
+          if (tile < TB * TB) {
+            const int rb = tile / TB, cb = tile % TB;
+            const T af = buf[(kk + lk) * LD + rb * 16 + li];
+            const T bf = sB[(kk + lk) * LD + cb * 16 + li];
+            acct[t] = Mfma<T>::mma(af, bf, acct[t]);
+          }
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T bf[TB];
@@ -412,6 +435,18 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
       compute(sT);
       __syncthreads();
     }
+  }
+  if constexpr (TILES) {
+    T* out = partial + ((int64_t)(s * g.ni + i0) * nsplit + split) * TP * TP;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      const int tile = wave + 8 * t;
+      if (tile >= TB * TB) continue;
+      const int rb = tile / TB, cb = tile % TB;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(int64_t)(rb * 16 + Mfma<T>::row(lk, v)) * TP + cb * 16 + li] = acct[t][v];
+    }
+    return;
   }
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
@@ -666,6 +701,33 @@ int gram4_capacity(int tb) {
   }
 }
 
+// Workgroups of the eight-wave single-block Gram resident on the whole device at once.
+template <class T, int TB>
+int gram_rows1_capacity_of() {
+  static int cap = -1;
+  if (cap < 0) {
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_gram_rows<T, TB, 1, 32, true>),
+                                                     512, 0) != hipSuccess ||
+        occ < 1 || cus < 1)
+      return 1024;
+    cap = occ * cus;
+  }
+  return cap;
+}
+template <class T>
+int gram_rows1_capacity(int tb) {
+  switch (tb) {
+    case 1: return gram_rows1_capacity_of<T, 1>();
+    case 2: return gram_rows1_capacity_of<T, 2>();
+    case 3: return gram_rows1_capacity_of<T, 3>();
+    case 4: return gram_rows1_capacity_of<T, 4>();
+    default: return gram_rows1_capacity_of<T, 5>();
+  }
+}
+
 // k_gram4 applies to square products of at most 80 columns whose right operand is shared by
 // the blocks of a shift
 // (FP64 at 80 columns would spill at two waves per SIMD: it keeps the one-block kernel)
@@ -698,6 +760,9 @@ int g_gram_variant = 0;
 int g_gram4_kc = 32;
 // FP32 multi-block Grams: the eight-wave kernel (1) or the four-wave one (0).
 int g_gram_rows = 1;
+// FP32 single-block square Grams: the eight-wave kernel with the tiles dealt to the waves (1) or
+// the four-wave tile kernel (0).
+int g_gram_rows1 = 1;
 
 template <class T>
 size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
@@ -721,6 +786,39 @@ size_t gram_partial_bytes(int64_t n, int PW, int QW, int items) {
 template <class T>
 void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partial_bytes) {
   IF_REQUIRE(g.PW % 16 == 0 && g.QW % 16 == 0, "gram: widths must be multiples of 16");
+  if constexpr (sizeof(T) == 4) {
+    // one square block per shift (FP32, at most 80 columns): the eight-wave kernel with the output
+    // tiles dealt to the waves
+    if (g_gram_rows1 && g_gram_variant >= 0 && g.ni == 1 && g.PW == g.QW && g.PW <= 80 && g.b_i == 0) {
+      const int tb = g.PW / 16;
+      int nsplit = gram_nsplit(g.n, g.ns, 1, gram_rows1_capacity<T>(tb), 512);
+      nsplit = (int)std::max<size_t>(1, std::min<size_t>(nsplit, partial_bytes / ((size_t)g.ns * g.PW * g.QW * sizeof(T))));
+      int64_t rps = (g.n + nsplit - 1) / nsplit;
+      rps = (rps + 31) / 32 * 32;
+      T* part = static_cast<T*>(partial);
+      KernelTimer* kt = g.kclass >= 0 ? current_timer() : nullptr;
+      const int tok = kt ? kt->begin(st) : -1;
+      const dim3 grid(nsplit, 1, g.ns), block(512);
+      switch (tb) {
+        case 1: hipLaunchKernelGGL((k_gram_rows<T, 1, 1, 32, true>), grid, block, 0, st, g, nsplit, rps, part); break;
+        case 2: hipLaunchKernelGGL((k_gram_rows<T, 2, 1, 32, true>), grid, block, 0, st, g, nsplit, rps, part); break;
+        case 3: hipLaunchKernelGGL((k_gram_rows<T, 3, 1, 32, true>), grid, block, 0, st, g, nsplit, rps, part); break;
+        case 4: hipLaunchKernelGGL((k_gram_rows<T, 4, 1, 32, true>), grid, block, 0, st, g, nsplit, rps, part); break;
+        default: hipLaunchKernelGGL((k_gram_rows<T, 5, 1, 32, true>), grid, block, 0, st, g, nsplit, rps, part); break;
+      }
+      IF_HIP(hipGetLastError());
+      if (kt) {
+        const int nact = kt->count(g.active, g.ns);
+        const double rb = g.A == g.B ? 0.0 : (double)g.n * g.QW * sizeof(T) * nact;
+        kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * nact, (double)g.n * g.PW * sizeof(T) * nact + rb);
+      }
+      const int64_t total = (int64_t)g.ns * g.PW * g.QW;
+      hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, g.ns, nsplit,
+                         g.PW, g.QW, 1, g.active, part, g.G, g.cmb);
+      IF_HIP(hipGetLastError());
+      return;
+    }
+  }
   if (gram4_fits<T>(g) && g_gram_variant >= 0) {
     const int tb = g.PW / 16;
     const int groups = (g.ni + 3) / 4;

@@ -341,7 +341,18 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
   const int tid = threadIdx.x, nth = blockDim.x, wave = tid >> 6, lane = tid & 63;
   const int P = m0 / NB;
   RR_MARK(16);
-  // ---- 1.
+  // ---- 1.  The Gram's entries are loaded (sixteen per thread in flight, the first round together
+  // with the diagonal), then scaled by the reciprocals of the column norms.
+  constexpr int kGU = 16;
+  double gv[kGU];
+  auto gload = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+      const int idx = i0 + u * nth;
+      gv[u] = idx < m0 * m0 ? G[idx] : 0.0;
+    }
+  };
+  gload(tid);
   for (int a = tid; a < m0; a += nth) {
     const double g = G[a * m0 + a];
     const bool dd = !(g > dead_thr);
@@ -350,16 +361,10 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     dinv[a] = 1.0 / dsc[a];  // scaling reciprocals (reset to the Cholesky pivots' below)
   }
   __syncthreads();
-  // eight loads in flight per thread, then the scaling (by reciprocals of the column norms)
-  for (int i0 = tid; i0 < m0 * m0; i0 += 8 * nth) {
-    double gv[8];
+  for (int i0 = tid; i0 < m0 * m0; i0 += kGU * nth) {
+    if (i0 != tid) gload(i0);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int idx = i0 + u * nth;
-      gv[u] = idx < m0 * m0 ? G[idx] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kGU; ++u) {
       const int idx = i0 + u * nth;
       if (idx >= m0 * m0) break;
       const int a = idx / m0, b = idx % m0;
@@ -388,8 +393,14 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       for (int c = 0; c < NB; ++c) {
         const double pv0 = lane_bcast(arow[c], c);
         const bool dc = dead[c0 + c] != 0 || !(pv0 > tau_dep);
-        const double pv = dc ? 1.0 : sqrt(pv0);
-        const double rpv = 1.0 / pv;
+        // 1/sqrt(p) from the hardware estimate and two Newton steps (each doubles the correct
+        // bits), sqrt(p) = p / sqrt(p): a shorter dependent chain than a rounded square root
+        // and division
+        const double pp = dc ? 1.0 : pv0;
+        double rpv = __builtin_amdgcn_rsq(pp);
+        rpv = rpv * (1.5 - 0.5 * pp * rpv * rpv);
+        rpv = rpv * (1.5 - 0.5 * pp * rpv * rpv);
+        const double pv = pp * rpv;
         if (i > c) arow[c] = dc ? 0.0 : arow[c] * rpv;
         if (i == c) {
           arow[c] = pv;
@@ -474,7 +485,9 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
       if (Hr_next != nullptr) Hr_next[b * m0 + a] = (T)v;
     }
   }
-  __syncthreads();
+  // the inversion overwrites L's diagonal blocks, which the R entries above read; the R stores
+  // themselves need not complete before it
+  lds_barrier();
   // ---- 4a. invert the diagonal blocks, one wave each (in place)
   RR_MARK(19);
   for (int p = wave; p < P; p += nth / 64) {
@@ -511,9 +524,14 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     // S_j = sum_{k=j..bi-1} L_{bi,k} X_{k,j}  (X: the inverse so far), into tmp[16][w]
     for (int idx = tid; idx < NB * w; idx += nth) {
       const int r = idx / w, c = idx % w;
-      // X is lower triangular (rows k >= c); L's storage above the diagonal is not part of it
+      // X is lower triangular (rows k >= c); L's storage above the diagonal is not part of it.
+      // The same trip count on every lane (the rows above c masked), so the loads pipeline.
       double v = 0.0;
-      for (int k = c; k < r0; ++k) v += L[(r0 + r) * ldl + k] * L[k * ldl + c];
+#pragma unroll 8
+      for (int k = 0; k < r0; ++k) {
+        const double p = L[(r0 + r) * ldl + k] * L[k * ldl + c];
+        v += k >= c ? p : 0.0;
+      }
       tmp[r * m0 + c] = v;
     }
     __syncthreads();
@@ -521,7 +539,11 @@ __global__ __launch_bounds__(512) void k_cholqr_real(int m0, const double* __res
     for (int idx = tid; idx < NB * w; idx += nth) {
       const int r = idx / w, c = idx % w;
       double v = 0.0;
-      for (int m = 0; m <= r; ++m) v += L[(r0 + r) * ldl + r0 + m] * tmp[m * m0 + c];
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        const double p = L[(r0 + r) * ldl + r0 + m] * tmp[m * m0 + c];
+        v += m <= r ? p : 0.0;
+      }
       L[(r0 + r) * ldl + c] = -v;
     }
     __syncthreads();

@@ -305,6 +305,81 @@ __global__ __launch_bounds__(256) void k_spmm_rows(int n, int rows_xcd, int rbx,
     nt_store(zs_minus(zs[2 * s], zs[2 * s + 1], self, acc), reinterpret_cast<V16*>(W) + (int64_t)row * nvec + li);
 }
 
+// Whole rows as in k_spmm_rows (B = I only), each wavefront taking G consecutive sets of
+// floor(64 / nvec) rows and software-pipelining them: the row pointers of all G sets are loaded
+// first, and the CSR entries of set s + 1 are loaded before the gathers of set s, so a set waits
+// for one memory round trip (its gathers) instead of three (row pointers, entries, gathers).
+// Rows with more than KC entries take their further rounds unpipelined.
+template <class T, int KC, int G>
+__global__ __launch_bounds__(256) void k_spmm_rows_pipe(int n, int rows_xcd, int rbx, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci, const T* __restrict__ va,
+                                                        int ns, int m0, const T* __restrict__ zs,
+                                                        const int* __restrict__ active, const T* __restrict__ V,
+                                                        T* __restrict__ W) {
+  using V16 = typename Vec16<T>::type;
+  constexpr int C = Vec16<T>::C;
+  const int nvec = ns * m0 / C;
+  const int gpw = 64 / nvec;  // row groups per set
+  const int xcd = blockIdx.x % kXcds, rb = blockIdx.x / kXcds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane / nvec, li = lane % nvec, g0 = grp * nvec;
+  const int rlo = xcd * rows_xcd;
+  const int rhi = min(n, rlo + rows_xcd);
+  const int row0 = rlo + (rb * 4 + wave) * G * gpw + grp;  // set s: row0 + s gpw
+  if (grp >= gpw || row0 >= rhi) return;  // whole groups leave together
+  // every lane of a group takes part in the group's shuffles; a stopped shift only skips its stores
+  const int s_ = (li * C) / m0;
+  const bool live = active == nullptr || active[s_] != 0;
+  const bool shifted = zs[2 * s_] != T(0) || zs[2 * s_ + 1] != T(0);
+  const V16* __restrict__ Vv = reinterpret_cast<const V16*>(V);
+  int e0[G], e1[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int row = row0 + q * gpw;
+    e0[q] = row < rhi ? rp[row] : 0;
+    e1[q] = row < rhi ? rp[row + 1] : 0;
+  }
+  int cl = 0;
+  T al = T(0);
+  auto entries = [&](int q, int& c, T& a) {
+    const int my = e0[q] + li;
+    const bool have = li < KC && my < e1[q];
+    c = have ? ci[my] : 0;
+    a = have ? va[my] : T(0);
+  };
+  entries(0, cl, al);
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int row = row0 + q * gpw;
+    int cn = 0;
+    T an = T(0);
+    if (q + 1 < G) entries(q + 1, cn, an);
+    if (row < rhi) {
+      V16 acc = vzero<V16>();
+      int c[KC];
+      T a[KC];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        c[k] = __shfl(cl, g0 + k);
+        a[k] = __shfl(al, g0 + k);
+      }
+      V16 x[KC];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) x[k] = Vv[(int64_t)c[k] * nvec + li];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) axpy(a[k], x[k], acc);
+      if (e1[q] - e0[q] > KC)
+        group_gather<T, false, KC>(e0[q] + KC, e1[q], g0, li, ci, va, Vv, nvec, li, acc);
+      V16 self = vzero<V16>();
+      if (shifted) self = Vv[(int64_t)row * nvec + li];
+      if (live)
+        nt_store(zs_minus(zs[2 * s_], zs[2 * s_ + 1], self, acc), reinterpret_cast<V16*>(W) + (int64_t)row * nvec + li);
+    }
+    cl = cn;
+    al = an;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_spmm_real(int n, int per, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const double* __restrict__ va, int m,
                                                    const double* __restrict__ X, double* __restrict__ Y) {
@@ -334,7 +409,8 @@ struct Sched {
 constexpr Sched kSched[] = {{false, 1, 8, "row-U1-K8"}, {false, 2, 4, "row-U2-K4"}, {false, 3, 4, "row-U3-K4"},
                             {true, 8, 8, "slab8-K8"},   {true, 16, 8, "slab16-K8"}, {true, 32, 8, "slab32-K8"},
                             {true, 16, 16, "slab16-K16"}, {true, 8, 4, "slab8-K4"},  {true, 0, 8, "rows-K8"},
-                            {true, 0, 7, "rows-K7"},    {true, 0, 7, "rows-K7-direct"}, {true, 0, 4, "rows-K4-direct"}};
+                            {true, 0, 7, "rows-K7"},    {true, 0, 7, "rows-K7-direct"}, {true, 0, 4, "rows-K4-direct"},
+                            {true, 0, 7, "rows-K7-pipe2"}, {true, 0, 7, "rows-K7-pipe4"}, {true, 0, 8, "rows-K8-pipe4"}};
 constexpr int kNSched = sizeof(kSched) / sizeof(kSched[0]);
 
 struct SpmmOperands {
@@ -386,8 +462,25 @@ void launch_rows(hipStream_t st, const SpmmOperands& o) {
                      (const T*)o.zs, o.active, (const T*)o.V, (T*)o.W);
 }
 
-// whether schedule idx can run a block of nvec 16-byte vectors per row
-bool sched_fits(int idx, int nvec) { return idx < 8 || (nvec >= 8 && nvec <= 64); }
+template <class T, int KC, int G>
+void launch_rows_pipe(hipStream_t st, const SpmmOperands& o) {
+  constexpr int C = Vec16<T>::C;
+  const int nvec = o.ns * o.m0 / C;
+  IF_REQUIRE(nvec >= KC && nvec <= 64 && o.brp == nullptr, "SpMM pipelined rows schedule: 8..64 vectors per row, B = I");
+  const int rpb = 4 * G * (64 / nvec);  // rows per workgroup
+  const int rows_xcd = (o.n + kXcds - 1) / kXcds;
+  const int rbx = (rows_xcd + rpb - 1) / rpb;
+  hipLaunchKernelGGL((k_spmm_rows_pipe<T, KC, G>), dim3((unsigned)((int64_t)kXcds * rbx)), dim3(256), 0, st, o.n,
+                     rows_xcd, rbx, o.rp, o.ci, (const T*)o.va, o.ns, o.m0, (const T*)o.zs, o.active, (const T*)o.V,
+                     (T*)o.W);
+}
+
+// whether schedule idx can run a block of nvec 16-byte vectors per row (with B: has_b)
+bool sched_fits(int idx, int nvec, bool has_b) {
+  if (idx < 8) return true;
+  if (idx >= 12 && has_b) return false;
+  return nvec >= 8 && nvec <= 64;
+}
 
 template <class T, bool HAS_B>
 void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
@@ -404,6 +497,9 @@ void launch_sched(int idx, hipStream_t st, const SpmmOperands& o) {
     case 9: launch_rows<T, HAS_B, 7, false>(st, o); break;
     case 10: launch_rows<T, HAS_B, 7, true>(st, o); break;
     case 11: launch_rows<T, HAS_B, 4, true>(st, o); break;
+    case 12: launch_rows_pipe<T, 7, 2>(st, o); break;
+    case 13: launch_rows_pipe<T, 7, 4>(st, o); break;
+    case 14: launch_rows_pipe<T, 8, 4>(st, o); break;
     default: throw Error{IFEAST_ERR_INVALID_ARG, "unknown SpMM schedule"};
   }
 }
@@ -459,7 +555,7 @@ void launch_spmm_shifted(hipStream_t st, const ifeast_matrix* A, const ifeast_ma
       std::vector<float> times(kNSched, 0.f);
       const int nvec = ns * m0 / (sizeof(T) == 4 ? 2 : 1);
       for (int c = 0; c < kNSched; ++c) {
-        if (!sched_fits(c, nvec)) {
+        if (!sched_fits(c, nvec, B != nullptr)) {
           times[c] = 0.f;
           continue;
         }

@@ -75,13 +75,13 @@ def test_spmm_shifted_parity(ctx, torch_cuda, prec, case):
         assert np.abs(got[:, sl] - want).max() <= tol * scale * 10, (s, np.abs(got[:, sl] - want).max() / scale)
 
 
-@pytest.mark.parametrize("sched", range(12))
+@pytest.mark.parametrize("sched", range(15))
 def test_spmm_every_schedule(torch_cuda, sched, monkeypatch):
     """Each autotuner candidate (forced through IFEAST_SPMM_SCHED on a fresh matrix) against the oracle,
     on widths that leave partial passes: 3 x 18 complex columns (FP32: 27 vectors, FP64: 54) and B present.
-    Schedules 8 and up (whole rows per lane group) only take rows of 8 to 64 vectors.  The last
-    case has one shift at zero (W = -A V, the shared basis's product), where the row's own term is
-    not read."""
+    Schedules 8 and up (whole rows per lane group) only take rows of 8 to 64 vectors, and the
+    pipelined ones (12 and up) only B = I.  The last case has one shift at zero (W = -A V, the shared
+    basis's product), where the row's own term is not read."""
     import paper_1706_00692_amd as pk
 
     torch = torch_cuda
@@ -95,6 +95,8 @@ def test_spmm_every_schedule(torch_cuda, sched, monkeypatch):
                                        (W.laplacian_3d(9, W.random_potential(729, 5)), None, 40, 1, True)]:
                 nvec = ns * m0 // (2 if prec == pk.PREC_MIXED else 1)
                 if sched >= 8 and not 8 <= nvec <= 64:
+                    continue
+                if sched >= 12 and B is not None:
                     continue
                 z = np.array([0.3 + 0.2j, 1.1 + 0.05j, -0.4 + 1.5j, 0.7 + 0.01j, 2 + 3j])[:ns]
                 if zero:

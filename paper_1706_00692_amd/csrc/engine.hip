@@ -901,10 +901,11 @@ struct Engine::Impl {
       gg.cmb = GramCombine{Hm.as<double>(), ldh, j, lo, accumulate, Hr.as<T>() + (int64_t)off * m0 * m0};
       launch_gram<T>(st, gg, gpart.p, gpart.bytes);
     };
-    // W -= [V_lo..V_{lo+nb-1}] Hr
-    auto project = [&](int lo, int nb) {
+    // W -= [V_lo..V_{lo+nb-1}] Hr (lower0: Hr's first block is the recurrence's R^T, lower triangular)
+    auto project = [&](int lo, int nb, int lower0 = 0) {
       ApplyArgs ap{n, m0, m0, 1, nb, nb, Vb + (int64_t)lo * bs, m0, 0, 0, bs, Hr.p, 0, t1, m0, 0, -1.0, 1.0, nullptr,
                    nullptr};
+      ap.lower0 = lower0;
       launch_apply<T, T>(st, ap);
     };
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
@@ -964,7 +965,7 @@ struct Engine::Impl {
         } else {
           gram(j, lo, nl, 0);
         }
-        project(lo, nl);
+        project(lo, nl, !always && j >= 1 ? 1 : 0);
         bool full = always || lo == 0;
         int certified = -1;
         bool folded = false;  // V_{j+1} already formed (the second pass folded into the normalisation)

@@ -584,6 +584,8 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
       while (nb_ < a.nb && skip(nb_)) ++nb_;
     }
     if (nb_ < a.nb) fetch(nb_, nk * KC);
+    // block 0 with a lower triangular coefficient: output column tiles right of this K chunk are zero
+    const int tri_from = (a.lower0 && b == 0) ? kc * KC + KC - 1 : (1 << 30);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T af[RB];
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
       for (int r = 0; r < RB; ++r) af[r] = sA[(wave * 16 * RB + r * 16 + li) * LDA_S + kk + lk];
 #pragma unroll
       for (int t = 0; t < TBQ; ++t) {
-        if (t * 16 < vq) {
+        if (t * 16 < vq && q0 + t * 16 <= tri_from) {
           const T bv = sB[(kk + lk) * LDB_S + t * 16 + li];
           // transposed product: the MFMA computes (A Bm)^T blocks, so a lane ends up holding
           // consecutive output columns of one row

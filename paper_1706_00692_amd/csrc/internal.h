@@ -201,6 +201,7 @@ struct ApplyArgs {
   const int* active_sb;    // per sb, may be null
   int kclass = KC_UPDATE;  // timing class (KC_UPDATE or KC_QACC; < 0: not timed)
   const void* A_last = nullptr;  // optional: block nb - 1 read from A_last + item * a_item instead
+  int lower0 = 0;  // 1: block 0's coefficient (KW x OW) is lower triangular; its zero tiles are skipped
 };
 template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a);

@@ -741,6 +741,7 @@ struct Engine::Impl {
     launch_cholqr_real_ctl<T>(st, m0, G0, 4.0 * m0 * eps, Tinv.as<T>(), Racc.as<cd>(), 0, d_single_sh, 0, hm, ldh,
                               jstep, Hr_next);
     ApplyArgs a1{n, m0, m0, 1, 1, 1, src, m0, 0, 0, 0, Tinv.p, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
+    a1.upper0 = 1;
     launch_apply<T, T>(st, a1);
     if (certified == 1) return;
     GramArgs g2{n, m0, m0, 1, 1, dst, m0, 0, 0, dst, m0, 0, 0, d_two_sh, gred.as<double>(), -1};
@@ -748,6 +749,7 @@ struct Engine::Impl {
     launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1, hm,
                               ldh, jstep, Hr_next, chol.as<double>());
     ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, tmp, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
+    a2.upper0 = 1;
     launch_apply<T, T>(st, a2);
     launch_copy_if<T>(st, d_two_sh, n * m0, tmp, dst);
   }
@@ -995,15 +997,14 @@ struct Engine::Impl {
           // their workgroup slots free
           g3.reserve = g_lsq_slots;
           launch_gram<T>(st, g3, gpart.p, gpart.bytes);
-          if (check) launch_sketch_check_real(st, kSketch, m0, gsk, gwf, d_loss);
-          // one Cholesky-QR pass is certified from this Gram: the second Gram-Schmidt pass
-          // changes the block by rounding only, or (a full pass) by at most reorth_eta per
-          // column, which the margin on the Gershgorin bound covers
-          launch_gersh_flags(st, m0, gwf, single_gersh - 4.0 * thr, dead_thr, d_single_sh, d_two_sh, d_cnt);
-          // the loss of orthogonality the first pass left against the local blocks, measured: the
+          // in one launch: the sketched estimate; the Gershgorin certificate for one Cholesky-QR
+          // pass (the second Gram-Schmidt pass changes the block by rounding only, or (a full
+          // pass) by at most reorth_eta per column, which the margin on the bound covers); the
+          // measured loss of orthogonality the first pass left against the local blocks (the
           // second pass runs only when it exceeds a hundredth of the loss tolerated against the
-          // older blocks
-          launch_local_loss(st, nl * m0, m0, gred.as<double>(), gwf, 0.01 * thr, d_act3);
+          // older blocks)
+          launch_step_checks(st, kSketch, m0, check ? gsk : nullptr, gwf, single_gersh - 4.0 * thr, dead_thr,
+                             d_single_sh, d_two_sh, d_cnt, nl * m0, gred.as<double>(), 0.01 * thr, d_act3, d_loss);
           // the estimate and the flags in one copy
           double* hchk = reinterpret_cast<double*>(h_flags + 128);
           IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1023,6 +1024,7 @@ struct Engine::Impl {
                                      lo, d_act3);
           T* dst = Vb + (int64_t)(j + 1) * bs;
           ApplyArgs aw{n, m0, m0, 1, 1, 1, t1, m0, 0, 0, 0, cf + nl * mm0, 0, dst, m0, 0, 1.0, 0.0, nullptr, nullptr};
+          aw.upper0 = 1;  // R^{-1}
           launch_apply<T, T>(st, aw);
           // the second pass's term (skipped on the device when not needed; left out of the timer,
           // as whether it runs is known on the device only)
@@ -1067,6 +1069,7 @@ struct Engine::Impl {
             launch_cholqr_real_ctl<T>(st, m0, gred.as<double>(), 0.0, Tinv.as<T>(), Racc.as<cd>(), 1, d_single_sh, 1,
                                       Hm.as<double>(), ldh, j, hr_next, chol.as<double>());
             ApplyArgs a2{n, m0, m0, 1, 1, 1, dst, m0, 0, 0, 0, Tinv.p, 0, t2, m0, 0, 1.0, 0.0, d_two_sh, nullptr, -1};
+            a2.upper0 = 1;
             launch_apply<T, T>(st, a2);
             launch_copy_if<T>(st, d_two_sh, n * m0, t2, dst);
           }

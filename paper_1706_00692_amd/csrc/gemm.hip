@@ -339,6 +339,8 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
   const T* const Ab = static_cast<const T*>(g.A) + s * g.a_s;
   const T* const Al = g.A_last != nullptr ? static_cast<const T*>(g.A_last) + s * g.a_s : nullptr;
   const T* const Bb = static_cast<const T*>(g.B) + s * g.b_s;
+  // the group's last block is B itself (A_last == B, one shift): its Gram with B is symmetric
+  const bool sym = NIL != 1 && Al != nullptr && g.A_last == g.B && g.a_s == 0 && g.b_s == 0 && i0 + NIL >= g.ni;
   constexpr bool TILES = NIL == 1;
   constexpr int MAXT = (TB * TB + 7) / 8;  // tiles per wave (NIL = 1)
   typename Mfma<T>::acc acc[TILES ? 1 : MAXR][TB];
@@ -406,8 +408,11 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
         if (rb < nil * TB) {
           const int blk = rb / TB, lr = rb % TB;
           const T af = buf[(blk * KC + kk + lk) * LD + lr * 16 + li];
+          // the last block's self Gram is symmetric: only its tiles on and above the diagonal
+          const int bmin = (sym && blk == nil - 1) ? lr : 0;
 #pragma unroll
-          for (int b = 0; b < TB; ++b) acc[r][b] = Mfma<T>::mma(af, bf[b], acc[r][b]);
+          for (int b = 0; b < TB; ++b)
+            if (b >= bmin) acc[r][b] = Mfma<T>::mma(af, bf[b], acc[r][b]);
         }
       }
     }
@@ -454,10 +459,17 @@ __global__ __launch_bounds__(512) void k_gram_rows(GramArgs g, int nsplit, int64
     if (rb >= nil * TB) continue;
     const int blk = rb / TB, lr = rb % TB;
     T* out = partial + ((int64_t)(s * g.ni + i0 + blk) * nsplit + split) * TP * TP;
+    const bool sb = sym && blk == nil - 1;
 #pragma unroll
-    for (int b = 0; b < TB; ++b)
+    for (int b = 0; b < TB; ++b) {
+      if (sb && b < lr) continue;  // written below, as the transpose of tile (b, lr)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(int64_t)(lr * 16 + Mfma<T>::row(lk, v)) * TP + b * 16 + li] = acc[r][b][v];
+      for (int v = 0; v < 4; ++v) {
+        const int row = lr * 16 + Mfma<T>::row(lk, v), col = b * 16 + li;
+        out[(int64_t)row * TP + col] = acc[r][b][v];
+        if (sb && b > lr) out[(int64_t)col * TP + row] = acc[r][b][v];
+      }
+    }
   }
 }
 
@@ -584,8 +596,10 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
       while (nb_ < a.nb && skip(nb_)) ++nb_;
     }
     if (nb_ < a.nb) fetch(nb_, nk * KC);
-    // block 0 with a lower triangular coefficient: output column tiles right of this K chunk are zero
+    // block 0 with a lower (upper) triangular coefficient: the output column tiles right (left) of
+    // this K chunk get nothing from it
     const int tri_from = (a.lower0 && b == 0) ? kc * KC + KC - 1 : (1 << 30);
+    const int tri_to = (a.upper0 && b == 0) ? kc * KC - 15 : -(1 << 30);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T af[RB];
@@ -593,7 +607,7 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a, int per) {
       for (int r = 0; r < RB; ++r) af[r] = sA[(wave * 16 * RB + r * 16 + li) * LDA_S + kk + lk];
 #pragma unroll
       for (int t = 0; t < TBQ; ++t) {
-        if (t * 16 < vq && q0 + t * 16 <= tri_from) {
+        if (t * 16 < vq && q0 + t * 16 <= tri_from && q0 + t * 16 >= tri_to) {
           const T bv = sB[(kk + lk) * LDB_S + t * 16 + li];
           // transposed product: the MFMA computes (A Bm)^T blocks, so a lane ends up holding
           // consecutive output columns of one row
@@ -884,9 +898,14 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     if (kt) {
       const int nact = kt->count(g.active, g.ns);
       const double eff = (double)nact * g.ni;
-      // the self Gram (A == B, one block, or B as the last block) reads B once, as an A block
+      // the self Gram (A == B, one block, or B as the last block) reads B once, as an A block; the
+      // eight-wave kernel forms that last block's symmetric product from its upper triangle, which
+      // counts n m0 (m0 + 1) flops
       const double rb = ((g.A == g.B && g.ni == 1) || g.A_last == g.B) ? 0.0 : (double)g.n * g.QW * sizeof(T) * nact;
-      kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, (double)g.n * g.PW * sizeof(T) * eff + rb);
+      const bool symk = sizeof(T) == 4 && g_gram_rows && g.A_last == g.B && g.a_s == 0 && g.b_s == 0;
+      const double fl = symk ? 2.0 * g.n * g.PW * g.QW * (eff - 1) + (double)g.n * g.PW * (g.QW + 1)
+                             : 2.0 * g.n * g.PW * g.QW * eff;
+      kt->end(tok, g.kclass, fl, (double)g.n * g.PW * sizeof(T) * eff + rb);
     }
     const int64_t total = (int64_t)items * g.PW * g.QW;
     hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, items, nsplit,

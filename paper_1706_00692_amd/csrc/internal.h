@@ -202,6 +202,7 @@ struct ApplyArgs {
   int kclass = KC_UPDATE;  // timing class (KC_UPDATE or KC_QACC; < 0: not timed)
   const void* A_last = nullptr;  // optional: block nb - 1 read from A_last + item * a_item instead
   int lower0 = 0;  // 1: block 0's coefficient (KW x OW) is lower triangular; its zero tiles are skipped
+  int upper0 = 0;  // 1: block 0's coefficient is upper triangular (a triangular factor's inverse)
 };
 template <class T, class TO>
 void launch_apply(hipStream_t st, const ApplyArgs& a);
@@ -279,6 +280,11 @@ void launch_gram_downdate(hipStream_t st, int rows, int m0, const double* C, dou
 // act[0..1] = the loss of orthogonality max_b ||G2[:, b]|| / ||w_b|| a first Gram-Schmidt pass
 // left against the local blocks exceeds eta (G2: rows x m0, gw = W^T W); act[2] = 1
 void launch_local_loss(hipStream_t st, int rows, int m0, const double* G2, const double* gw, double eta, int* act);
+// The sketch estimate (Gsk may be null: skipped), the Gershgorin flags of gw and the local loss in
+// one launch (launch_sketch_check_real, launch_gersh_flags and launch_local_loss in turn)
+void launch_step_checks(hipStream_t st, int nk, int m0, const double* Gsk, const double* gw, double gersh,
+                        double dead_thr, int* single, int* two, int* count, int rows, const double* G2, double eta,
+                        int* act, double* out);
 // The second Gram-Schmidt pass folded into the Cholesky-QR product: from G2 (nl blocks m0 x m0,
 // FP64) and Tinv, Cf = [-G2_0 Tinv; ..; -G2_{nl-1} Tinv; Tinv], G2T = G2 in type T, and
 // Hm(lo + b, j) += G2_b; with need[0] == 0 (no second pass) only Cf[nl] = Tinv.

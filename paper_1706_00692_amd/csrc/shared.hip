@@ -174,6 +174,79 @@ __global__ __launch_bounds__(1024) void k_local_loss(int rows, int m0, const dou
   }
 }
 
+// The three device decisions of a shared-basis step in one launch (one workgroup of 1024 threads),
+// all from the step's Grams with gw = W^T W:
+//  * sketch (Gsk = U^T W, nk x m0, may be null): out[0] = max_b ||Gsk[:, b]|| / ||w_b|| (NaN when
+//    some column is not finite), as k_sketch_check_real;
+//  * Gershgorin certificate of gw: single[0] / two[0] / count[0], as k_gersh_flags;
+//  * local loss (G2 = [V_lo..]^T W, rows x m0): act[0] = act[1] = (loss > eta), act[2] = 1, as
+//    k_local_loss.
+__global__ __launch_bounds__(1024) void k_step_checks(int nk, int m0, const double* __restrict__ Gsk,
+                                                      const double* __restrict__ gw, double gersh, double dead_thr,
+                                                      int* __restrict__ single, int* __restrict__ two,
+                                                      int* __restrict__ count, int rows, const double* __restrict__ G2,
+                                                      double eta, int* __restrict__ act, double* __restrict__ out) {
+  __shared__ double dsc[128], colr[128], colk[128];
+  __shared__ double part[1024];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  // column norms of gw; the local loss's and the sketch's column sums of squares beside them
+  const int ns = 1024 / m0;
+  const int b = t % m0, sl = t / m0;
+  double g2 = 0.0;
+  if (sl < ns)
+    for (int a = sl; a < rows; a += ns) g2 += G2[(int64_t)a * m0 + b] * G2[(int64_t)a * m0 + b];
+  part[t] = g2;
+  if (t < m0) {
+    const double d = gw[t * m0 + t];
+    if (!(d > dead_thr)) bad = 1;
+    dsc[t] = sqrt(fmax(d, 1e-300));
+    if (Gsk != nullptr) {
+      double ss = 0.0;
+      for (int a = 0; a < nk; ++a) ss += Gsk[a * m0 + t] * Gsk[a * m0 + t];
+      colk[t] = d > 0.0 ? sqrt(ss / d) : (ss > 0.0 ? INFINITY : 0.0);
+    }
+  }
+  __syncthreads();
+  // Gershgorin: 8 lanes per row of the scaled Gram
+  const int r = t >> 3, pp = t & 7;
+  double off = 0.0;
+  if (r < m0) {
+#pragma unroll 4
+    for (int c = pp; c < m0; c += 8)
+      if (c != r) off += fabs(gw[r * m0 + c]) / (dsc[r] * dsc[c]);
+  }
+  off += __shfl_xor(off, 1);
+  off += __shfl_xor(off, 2);
+  off += __shfl_xor(off, 4);
+  if (r < m0 && pp == 0 && !(off <= gersh)) bad = 1;
+  if (t < m0) {
+    double sum = 0.0;
+    for (int k = 0; k < ns; ++k) sum += part[k * m0 + t];
+    const double w2 = gw[(int64_t)t * m0 + t];
+    colr[t] = w2 > 0.0 ? sum / w2 : (sum > 0.0 ? INFINITY : 0.0);
+  }
+  __syncthreads();
+  if (t == 0) {
+    single[0] = bad ? 0 : 1;
+    two[0] = bad ? 1 : 0;
+    if (count != nullptr) count[0] += bad ? 0 : 1;
+    double mx = 0.0;
+    for (int c = 0; c < m0; ++c) mx = (colr[c] > mx || colr[c] != colr[c]) ? colr[c] : mx;
+    const int need = mx <= eta * eta ? 0 : 1;
+    act[0] = need;
+    act[1] = need;
+    act[2] = 1;
+    if (Gsk != nullptr) {
+      double mk = 0.0;
+      for (int c = 0; c < m0; ++c) mk = (colk[c] > mk || colk[c] != colk[c]) ? colk[c] : mk;
+      out[0] = mk;
+    }
+  }
+}
+
 // The second Gram-Schmidt pass folded into the normalisation.  With G2 = [V_lo..V_{lo+nl-1}]^T W
 // the second pass's coefficients and R^{-1} = Tinv the Cholesky-QR factor of
 // (W - V G2)^T (W - V G2) = W^T W - G2^T G2, the next block is
@@ -247,6 +320,14 @@ void launch_fold_second_pass(hipStream_t st, int m0, int nl, const double* G2, c
                              double* Hm, int ldh, int j, int lo, const int* need) {
   hipLaunchKernelGGL((k_fold_second_pass<T>), dim3(nblk((int64_t)(nl + 1) * m0 * m0)), dim3(256), 0, st, m0, nl, G2,
                      Tinv, Cf, G2T, Hm, ldh, j, lo, need);
+  IF_HIP(hipGetLastError());
+}
+void launch_step_checks(hipStream_t st, int nk, int m0, const double* Gsk, const double* gw, double gersh,
+                        double dead_thr, int* single, int* two, int* count, int rows, const double* G2, double eta,
+                        int* act, double* out) {
+  IF_REQUIRE(m0 <= 128, "step checks: m0 > 128");
+  hipLaunchKernelGGL(k_step_checks, dim3(1), dim3(1024), 0, st, nk, m0, Gsk, gw, gersh, dead_thr, single, two, count,
+                     rows, G2, eta, act, out);
   IF_HIP(hipGetLastError());
 }
 void launch_local_loss(hipStream_t st, int rows, int m0, const double* G2, const double* gw, double eta, int* act) {

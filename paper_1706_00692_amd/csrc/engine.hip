@@ -413,9 +413,15 @@ struct Engine::Impl {
   char* h_stage = nullptr;  // pinned staging of the shared inner solve's small uploads
   size_t stage_off = 0;
   hipEvent_t ev_chk = nullptr;
+  // stream of the sketch updates queued one step ahead, and its two events
+  hipStream_t st_sk = nullptr;
+  hipEvent_t ev_sk_go = nullptr, ev_sk_done = nullptr;
   void side_stream() {
     if (st_lsq) return;
     IF_HIP(hipStreamCreateWithFlags(&st_lsq, hipStreamNonBlocking));
+    IF_HIP(hipStreamCreateWithFlags(&st_sk, hipStreamNonBlocking));
+    IF_HIP(hipEventCreateWithFlags(&ev_sk_go, hipEventDisableTiming));
+    IF_HIP(hipEventCreateWithFlags(&ev_sk_done, hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[0], hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[1], hipEventDisableTiming));
@@ -425,11 +431,13 @@ struct Engine::Impl {
   }
   ~Impl() {
     if (st_lsq) (void)hipStreamSynchronize(st_lsq);
+    if (st_sk) (void)hipStreamSynchronize(st_sk);
     if (h_flags) (void)hipHostFree(h_flags);
     if (h_stage) (void)hipHostFree(h_stage);
-    for (hipEvent_t e : {ev_main, ev_lsq[0], ev_lsq[1], ev_chk})
+    for (hipEvent_t e : {ev_main, ev_lsq[0], ev_lsq[1], ev_chk, ev_sk_go, ev_sk_done})
       if (e) (void)hipEventDestroy(e);
     if (st_lsq) (void)hipStreamDestroy(st_lsq);
+    if (st_sk) (void)hipStreamDestroy(st_sk);
   }
   Impl(const Impl&) = delete;
   Impl& operator=(const Impl&) = delete;
@@ -915,6 +923,7 @@ struct Engine::Impl {
     if (!always || nonsym_sel) launch_fill_zero(st, Us.p, Us.bytes);
     bool force_next = false;  // the step after a triggered third pass takes one too
     int skip_checks = 0;      // steps left before the next orthogonality estimate
+    int sk_queued = -1;       // the step whose sketch update is already queued on st_sk
     const int zero_cnt = 0;
     h2d_staged(d_cnt, &zero_cnt, sizeof(int));
     side_stream();
@@ -976,9 +985,17 @@ struct Engine::Impl {
           double* gwf = gred.as<double>() + nl * mm0;        // W^T W: the combined Gram's last item
           double* gsk = gred.as<double>() + (nl + 1) * mm0;  // the sketch product, beside it
           // V_{j-2} joins the older blocks: U += V_{j-2} Om_{j-2}; then the estimate from U^T W
-          ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(j - 2) * bs, m0, 0, 0, 0,
-                       Om.as<T>() + (int64_t)(j - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
-          launch_apply<T, T>(st, au);
+          auto sketch_update = [&](hipStream_t s, int i) {
+            ApplyArgs au{n, m0, kSketch, 1, 1, 1, Vb + (int64_t)(i - 2) * bs, m0, 0, 0, 0,
+                         Om.as<T>() + (int64_t)(i - 2) * m0 * kSketch, 0, U, kSketch, 0, 1.0, 1.0, nullptr, nullptr};
+            // untimed off the main stream: the event timer synchronises when the stream changes
+            if (s != st) au.kclass = -1;
+            launch_apply<T, T>(s, au);
+          };
+          if (sk_queued == j)
+            IF_HIP(hipStreamWaitEvent(st, ev_sk_done, 0));
+          else
+            sketch_update(st, j);
           // 16 x 16 tiles: the sketch is read once per tile column, the block once.  Far below
           // the threshold the estimate is left out for a few steps: the loss grows by well under
           // a factor 2 per step (measured: at most about 1.5)
@@ -1009,6 +1026,17 @@ struct Engine::Impl {
           double* hchk = reinterpret_cast<double*>(h_flags + 128);
           IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 3 * sizeof(int), hipMemcpyDeviceToHost, st));
           IF_HIP(hipEventRecord(ev_chk, st));
+          // step j + 1's sketch update, U += V_{j-1} Om_{j-1}, on its own stream beside the
+          // single-workgroup Cholesky-QR: V_{j-1} is final and this step's reads of U are queued
+          // before the event; step j + 1 waits for it before its sketch product.  FP32 only
+          // (measured 0.6 % faster per solve; the FP64 basis was 1 % slower)
+          if (sizeof(T) == 4 && j + 1 < K) {
+            IF_HIP(hipEventRecord(ev_sk_go, st));
+            IF_HIP(hipStreamWaitEvent(st_sk, ev_sk_go, 0));
+            sketch_update(st_sk, j + 1);
+            IF_HIP(hipEventRecord(ev_sk_done, st_sk));
+            sk_queued = j + 1;
+          }
           // the common case (no pass against the older blocks) runs while the host waits: the
           // second pass, when needed, folded into the normalisation, V_{j+1} = (W - V G2) R^{-1}
           // from the Gram W^T W - G2^T G2 (the pass removes little, so the downdate loses nothing
@@ -1114,6 +1142,8 @@ struct Engine::Impl {
     }
     IF_HIP(hipEventRecord(ev_lsq[0], st_lsq));
     IF_HIP(hipStreamWaitEvent(st, ev_lsq[0], 0));
+    // a sketch update queued for a step that did not run: U is cleared by the next solve
+    if (sk_queued >= 0) IF_HIP(hipStreamWaitEvent(st, ev_sk_done, 0));
     shared_steps = jdone;
     single_steps += d2h_ints(d_cnt, 1)[0];
     launch_lsq_finish(st, la, jdone);

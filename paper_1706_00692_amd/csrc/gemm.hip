@@ -170,14 +170,20 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g, int nsplit, int64_t ro
     }
 }
 
+// Waves per workgroup of the split-K reduction.  The output is small (a few hundred workgroups of
+// 64 elements), so the loads in flight per CU set its speed: sixteen waves striding the splits
+// keep four times as many in flight as four did.
+constexpr int kRedWaves = 16;
+
 template <class T>
-__global__ __launch_bounds__(256) void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni,
-                                                     const int* __restrict__ active, const T* __restrict__ partial,
-                                                     double* __restrict__ G, GramCombine cmb) {
+__global__ __launch_bounds__(64 * kRedWaves) void k_gram_reduce(int items, int nsplit, int PW, int QW, int ni,
+                                                               const int* __restrict__ active,
+                                                               const T* __restrict__ partial, double* __restrict__ G,
+                                                               GramCombine cmb) {
   // 64 consecutive output elements per workgroup, one per lane, so every load of a wave reads 64
-  // consecutive partial sums; the four waves take every fourth split and their sums are added in
-  // wave order (a fixed order: results are reproducible)
-  __shared__ double red[4][64];
+  // consecutive partial sums; wave w takes every kRedWaves-th split from w, and the waves' sums
+  // are added in wave order (a fixed order: results are reproducible)
+  __shared__ double red[kRedWaves][64];
   const int64_t per_item = (int64_t)PW * QW;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
@@ -189,12 +195,14 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int items, int nsplit, int 
     const T* p = partial + (int64_t)item * nsplit * per_item + idx % per_item;
     // unrolled so that eight loads are in flight before the (in-order) additions
 #pragma unroll 8
-    for (int sp = wave; sp < nsplit; sp += 4) sum += (double)p[(int64_t)sp * per_item];
+    for (int sp = wave; sp < nsplit; sp += kRedWaves) sum += (double)p[(int64_t)sp * per_item];
   }
   red[wave][lane] = sum;
   __syncthreads();
   if (wave != 0 || !on) return;
-  sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  sum = red[0][lane];
+#pragma unroll
+  for (int w = 1; w < kRedWaves; ++w) sum += red[w][lane];
   G[idx] = sum;
   if (cmb.Hm != nullptr) {
     // block column j of Hm (block rows i0 + item) and the update factors, as k_combine_real
@@ -829,8 +837,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
         kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * nact, (double)g.n * g.PW * sizeof(T) * nact + rb);
       }
       const int64_t total = (int64_t)g.ns * g.PW * g.QW;
-      hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, g.ns, nsplit,
-                         g.PW, g.QW, 1, g.active, part, g.G, g.cmb);
+      hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(64 * kRedWaves), 0, st, g.ns,
+                         nsplit, g.PW, g.QW, 1, g.active, part, g.G, g.cmb);
       IF_HIP(hipGetLastError());
       return;
     }
@@ -908,8 +916,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
       kt->end(tok, g.kclass, fl, (double)g.n * g.PW * sizeof(T) * eff + rb);
     }
     const int64_t total = (int64_t)items * g.PW * g.QW;
-    hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, items, nsplit,
-                       g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
+    hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(64 * kRedWaves), 0, st, items,
+                       nsplit, g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
     IF_HIP(hipGetLastError());
     return;
   }
@@ -955,8 +963,8 @@ void launch_gram(hipStream_t st, const GramArgs& g, void* partial, size_t partia
     kt->end(tok, g.kclass, 2.0 * g.n * g.PW * g.QW * eff, ra + rb);
   }
   const int64_t total = (int64_t)items * g.PW * g.QW;
-  hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, items, nsplit,
-                     g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
+  hipLaunchKernelGGL((k_gram_reduce<T>), dim3((unsigned)((total + 63) / 64)), dim3(64 * kRedWaves), 0, st, items,
+                     nsplit, g.PW, g.QW, g.ni, g.active, part, g.G, g.cmb);
   IF_HIP(hipGetLastError());
 }
 

@@ -416,12 +416,17 @@ struct Engine::Impl {
   // stream of the sketch updates queued one step ahead, and its two events
   hipStream_t st_sk = nullptr;
   hipEvent_t ev_sk_go = nullptr, ev_sk_done = nullptr;
-  void side_stream() {
-    if (st_lsq) return;
-    IF_HIP(hipStreamCreateWithFlags(&st_lsq, hipStreamNonBlocking));
+  // the third stream, created on first use (the FP32 shared basis only: engines of the FP64
+  // basis, several of which may serve requests at once, keep to two streams)
+  void third_stream() {
+    if (st_sk) return;
     IF_HIP(hipStreamCreateWithFlags(&st_sk, hipStreamNonBlocking));
     IF_HIP(hipEventCreateWithFlags(&ev_sk_go, hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_sk_done, hipEventDisableTiming));
+  }
+  void side_stream() {
+    if (st_lsq) return;
+    IF_HIP(hipStreamCreateWithFlags(&st_lsq, hipStreamNonBlocking));
     IF_HIP(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[0], hipEventDisableTiming));
     IF_HIP(hipEventCreateWithFlags(&ev_lsq[1], hipEventDisableTiming));
@@ -927,6 +932,7 @@ struct Engine::Impl {
     const int zero_cnt = 0;
     h2d_staged(d_cnt, &zero_cnt, sizeof(int));
     side_stream();
+    if (sizeof(T) == 4) third_stream();
     int jdone = 0;
     // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
     // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike).
@@ -1022,17 +1028,24 @@ struct Engine::Impl {
           // older blocks)
           launch_step_checks(st, kSketch, m0, check ? gsk : nullptr, gwf, single_gersh - 4.0 * thr, dead_thr,
                              d_single_sh, d_two_sh, d_cnt, nl * m0, gred.as<double>(), 0.01 * thr, d_act3, d_loss);
-          // the estimate and the flags in one copy
+          // the estimate and the flags in one copy.  With the FP32 basis it goes to the third
+          // stream, so that the main stream goes on at once (the words are next written by step
+          // j + 1's checks, which the host queues only after reading them), and step j + 1's
+          // sketch update, U += V_{j-1} Om_{j-1}, follows it there, beside the single-workgroup
+          // Cholesky-QR: V_{j-1} is final and this step's reads of U are queued before the event;
+          // step j + 1 waits for it before its sketch product.  Measured per solve: 0.7 % and
+          // 0.4 % faster in FP32, 0.65 % and 1.6 % slower with the FP64 basis, which keeps both on
+          // the main stream.
           double* hchk = reinterpret_cast<double*>(h_flags + 128);
-          IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-          IF_HIP(hipEventRecord(ev_chk, st));
-          // step j + 1's sketch update, U += V_{j-1} Om_{j-1}, on its own stream beside the
-          // single-workgroup Cholesky-QR: V_{j-1} is final and this step's reads of U are queued
-          // before the event; step j + 1 waits for it before its sketch product.  FP32 only
-          // (measured 0.6 % faster per solve; the FP64 basis was 1 % slower)
-          if (sizeof(T) == 4 && j + 1 < K) {
+          const bool third = sizeof(T) == 4;
+          hipStream_t cs = third ? st_sk : st;
+          if (third) {
             IF_HIP(hipEventRecord(ev_sk_go, st));
             IF_HIP(hipStreamWaitEvent(st_sk, ev_sk_go, 0));
+          }
+          IF_HIP(hipMemcpyAsync(hchk, d_loss, sizeof(double) + 3 * sizeof(int), hipMemcpyDeviceToHost, cs));
+          IF_HIP(hipEventRecord(ev_chk, cs));
+          if (third && j + 1 < K) {
             sketch_update(st_sk, j + 1);
             IF_HIP(hipEventRecord(ev_sk_done, st_sk));
             sk_queued = j + 1;

@@ -288,6 +288,27 @@ def test_solve_shared_m0_128_mixed(ctx):
     assert res.resid[: res.m].max() <= prob.tol
 
 
+def test_solve_shared_mixed_repeats_bitwise(ctx):
+    """Three mixed solves on the shared basis in a row agree to the last bit.  The FP32 basis
+    copies each step's decision words to the host, and forms the next step's sketch update, on a
+    third stream ordered by events alone (a missing order would show as a change between runs);
+    the pairs match the dense spectrum of a 14^3 Laplacian + potential."""
+    import paper_1706_00692_amd as pk
+
+    N = 14
+    lam_all = np.linalg.eigvalsh(W.laplacian_3d(N, W.random_potential(N ** 3, 1002)).to_dense())
+    prob = W.config2_small(N=N, m0=48, emin=0.5 * (lam_all[9] + lam_all[10]), emax=0.5 * (lam_all[39] + lam_all[40]))
+    runs = [ctx.solve_problem(prob, precision=pk.PREC_MIXED) for _ in range(3)]
+    r0 = runs[0]
+    assert r0.status == 0 and r0.converged and r0.m == 30
+    assert np.allclose(np.sort(r0.lam_in), lam_all[10:40], rtol=1e-10, atol=0)
+    assert r0.resid[: r0.m].max() <= prob.tol
+    for r in runs[1:]:
+        assert (r.m, r.outer_iters, r.seq_matvec) == (r0.m, r0.outer_iters, r0.seq_matvec)
+        assert np.array_equal(r.lam, r0.lam) and np.array_equal(r.resid, r0.resid)
+        assert np.array_equal(r.X, r0.X)
+
+
 def test_filter_parity_mixed(ctx, torch_cuda):
     import paper_1706_00692_amd as pk
 

@@ -925,6 +925,12 @@ struct Engine::Impl {
     };
     GramArgs gw{n, m0, m0, 1, 1, t1, m0, 0, 0, t1, m0, 0, 0, nullptr, gwb.as<double>()};
     T* U = Us.as<T>();
+    if (sizeof(T) == 4) {
+      // a sketch update still queued on the third stream (a solve that ended early on an error)
+      // finishes before U is cleared
+      third_stream();
+      IF_HIP(hipStreamWaitEvent(st, ev_sk_done, 0));
+    }
     if (!always || nonsym_sel) launch_fill_zero(st, Us.p, Us.bytes);
     bool force_next = false;  // the step after a triggered third pass takes one too
     int skip_checks = 0;      // steps left before the next orthogonality estimate
@@ -932,7 +938,6 @@ struct Engine::Impl {
     const int zero_cnt = 0;
     h2d_staged(d_cnt, &zero_cnt, sizeof(int));
     side_stream();
-    if (sizeof(T) == 4) third_stream();
     int jdone = 0;
     // W = M V_j = -A V_j: the shifted product with one zero shift on the block viewed as
     // n x m0/2 complex numbers (A is real, so it acts on real and imaginary parts alike).

@@ -152,9 +152,13 @@ __global__ __launch_bounds__(1024) void k_local_loss(int rows, int m0, const dou
   __shared__ double colr[128];
   const int t = threadIdx.x, ns = 1024 / m0;
   const int b = t % m0, sl = t / m0;
+  // (the loops are unrolled so that their loads are in flight together; each thread's sum keeps
+  // its order)
   double g2 = 0.0;
-  if (sl < ns)
+  if (sl < ns) {
+#pragma unroll 8
     for (int a = sl; a < rows; a += ns) g2 += G2[(int64_t)a * m0 + b] * G2[(int64_t)a * m0 + b];
+  }
   part[t] = g2;
   __syncthreads();
   if (t < m0) {
@@ -195,9 +199,13 @@ __global__ __launch_bounds__(1024) void k_step_checks(int nk, int m0, const doub
   // column norms of gw; the local loss's and the sketch's column sums of squares beside them
   const int ns = 1024 / m0;
   const int b = t % m0, sl = t / m0;
+  // (the loops are unrolled so that their loads are in flight together; each thread's sum keeps
+  // its order)
   double g2 = 0.0;
-  if (sl < ns)
+  if (sl < ns) {
+#pragma unroll 8
     for (int a = sl; a < rows; a += ns) g2 += G2[(int64_t)a * m0 + b] * G2[(int64_t)a * m0 + b];
+  }
   part[t] = g2;
   if (t < m0) {
     const double d = gw[t * m0 + t];
@@ -205,6 +213,7 @@ __global__ __launch_bounds__(1024) void k_step_checks(int nk, int m0, const doub
     dsc[t] = sqrt(fmax(d, 1e-300));
     if (Gsk != nullptr) {
       double ss = 0.0;
+#pragma unroll 16
       for (int a = 0; a < nk; ++a) ss += Gsk[a * m0 + t] * Gsk[a * m0 + t];
       colk[t] = d > 0.0 ? sqrt(ss / d) : (ss > 0.0 ? INFINITY : 0.0);
     }
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(1024) void k_step_checks(int nk, int m0, const doub
   const int r = t >> 3, pp = t & 7;
   double off = 0.0;
   if (r < m0) {
-#pragma unroll 4
+#pragma unroll 8
     for (int c = pp; c < m0; c += 8)
       if (c != r) off += fabs(gw[r * m0 + c]) / (dsc[r] * dsc[c]);
   }
@@ -229,20 +238,28 @@ __global__ __launch_bounds__(1024) void k_step_checks(int nk, int m0, const doub
     colr[t] = w2 > 0.0 ? sum / w2 : (sum > 0.0 ? INFINITY : 0.0);
   }
   __syncthreads();
-  if (t == 0) {
-    single[0] = bad ? 0 : 1;
-    two[0] = bad ? 1 : 0;
-    if (count != nullptr) count[0] += bad ? 0 : 1;
-    double mx = 0.0;
-    for (int c = 0; c < m0; ++c) mx = (colr[c] > mx || colr[c] != colr[c]) ? colr[c] : mx;
-    const int need = mx <= eta * eta ? 0 : 1;
-    act[0] = need;
-    act[1] = need;
-    act[2] = 1;
-    if (Gsk != nullptr) {
-      double mk = 0.0;
-      for (int c = 0; c < m0; ++c) mk = (colk[c] > mk || colk[c] != colk[c]) ? colk[c] : mk;
-      out[0] = mk;
+  if (t < 64) {
+    // wave 0: the largest column loss and sketched estimate over the lanes, then across them (a
+    // NaN wins, so that a check that went wrong asks for the extra pass)
+    auto nanmax = [](double a, double b) { return (b > a || b != b) ? b : a; };
+    double mx = 0.0, mk = 0.0;
+    for (int c = t; c < m0; c += 64) {
+      mx = nanmax(mx, colr[c]);
+      if (Gsk != nullptr) mk = nanmax(mk, colk[c]);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      mx = nanmax(mx, __shfl_xor(mx, o));
+      mk = nanmax(mk, __shfl_xor(mk, o));
+    }
+    if (t == 0) {
+      single[0] = bad ? 0 : 1;
+      two[0] = bad ? 1 : 0;
+      if (count != nullptr) count[0] += bad ? 0 : 1;
+      const int need = mx <= eta * eta ? 0 : 1;
+      act[0] = need;
+      act[1] = need;
+      act[2] = 1;
+      if (Gsk != nullptr) out[0] = mk;
     }
   }
 }
